@@ -1,0 +1,177 @@
+/*
+ * xlbomd.h - C ABI of the MI355X (gfx950) finite-temperature XL-BOMD library.
+ *
+ * Method: A. M. N. Niklasson, "Next generation extended Lagrangian first
+ * principles molecular dynamics".  One library handle holds one system:
+ * nuclear positions R, velocities, the extended electronic variable n (net
+ * Mulliken charges per atom) with its Verlet history, and a low-rank kernel
+ * K ~ (J - I)^-1.  A step is the integration scheme of Eqs. 22-23:
+ *   - half kick and drift of the nuclei (velocity Verlet);
+ *   - n(t+dt) = 2n(t) - n(t-dt) - kappa K r(t) + alpha sum_k c_k n(t-k dt)
+ *     with the Table I coefficients (K_max = 5, 6 or 7);
+ *   - H[n] = H0(R) + diag(Gamma n) (Section IV.A, SCC tight binding), the
+ *     Fermi-Dirac density matrix D = 2 f(H) at fixed electron number
+ *     (Section IV.B, Eq. 36), net charges q and the residual r = q - n;
+ *   - Hellmann-Feynman forces at fixed n (Eq. 40, first line);
+ *   - the rank-m kernel from Sherman-Morrison updates of K0 = -gamma I
+ *     (Eqs. 48-51) along Krylov directions whose responses dq/dv come from
+ *     density-matrix perturbation theory (Section V.B);
+ *   - the second half kick.
+ *
+ * Conventions:
+ *   - All pointers in this header are HOST pointers.  Arrays passed in are
+ *     caller-owned and copied during the call; device memory is owned by the
+ *     library until xlbomd_destroy.
+ *   - Every call returns an xlbomd_status.  No call aborts, no C++ exception
+ *     crosses the ABI.  On failure xlbomd_last_error() (thread-local) gives a
+ *     message.  A handle is not re-entrant: calls on one handle must not
+ *     overlap.  Different handles may be used from different threads.
+ *   - Layouts: positions/velocities/forces are n_atoms x 3 row-major doubles;
+ *     per-atom vectors have n_atoms doubles; the orbital index of orbital a on
+ *     atom I is I*n_orb + a.
+ *   - Units are model units with k_B = 1 (te is an energy).
+ *   - Everything crossing the ABI is FP64; the working precision of the dense
+ *     matrix algebra is chosen by xlbomd_desc.precision.
+ */
+#ifndef XLBOMD_H
+#define XLBOMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xlbomd_system xlbomd_system;   /* opaque, library-owned */
+
+typedef enum {
+    XLBOMD_OK = 0,
+    XLBOMD_E_INVALID = -1,   /* bad argument or descriptor                */
+    XLBOMD_E_NOMEM = -2,     /* device allocation failed                  */
+    XLBOMD_E_NOCONV = -3,    /* SCF or chemical-potential solve failed    */
+    XLBOMD_E_DIVERGED = -4,  /* NaN/Inf or runaway residual detected      */
+    XLBOMD_E_HIP = -5,       /* HIP runtime error                         */
+    XLBOMD_E_STATE = -6      /* call not valid in the handle's state      */
+} xlbomd_status;
+
+typedef enum {
+    XLBOMD_FP64 = 0,         /* every dense product in FP64 (FP64 MFMA)   */
+    XLBOMD_FP32 = 1          /* dense products in FP32 MFMA; mu, kernel
+                                solve, Verlet and energy sums in FP64     */
+} xlbomd_precision;
+
+/* System descriptor.  Model (orthogonal SCC tight binding):
+ *   H0[Ia,Ia] = onsite[a] + onsite_jitter[Ia]
+ *   H0[Ia,Jb] = hop_block[a*n_orb+b] exp(-r/hop_decay) s(r), I != J, r < hop_cutoff
+ *   s(r): 1 below hop_cutoff - taper_width, quintic C2 ramp to 0 at hop_cutoff
+ *   Gamma[I,I] = hubbard_u[I], Gamma[I,J] = 1/sqrt(r^2 + gamma_soft^2)
+ *   E_rep = sum_{I<J} rep_a exp(-r/rep_decay) s(r)
+ *   q_I = sum_a D[Ia,Ia] - n_electrons/n_atoms */
+typedef struct {
+    int32_t n_atoms, n_orb;
+    const double *pos;            /* n_atoms*3                              */
+    const double *vel;            /* n_atoms*3, NULL = zero                 */
+    const double *mass;           /* n_atoms                                */
+    const double *onsite;         /* n_orb                                  */
+    const double *onsite_jitter;  /* n_atoms*n_orb, NULL = zero             */
+    const double *hop_block;      /* n_orb*n_orb, symmetric                 */
+    double hop_decay, hop_cutoff, taper_width;
+    const double *hubbard_u;      /* n_atoms                                */
+    double gamma_soft, rep_a, rep_decay;
+    double n_electrons;           /* in (0, 2*n_atoms*n_orb)                */
+    double te;                    /* electronic temperature, > 0            */
+    double dt;                    /* time step, > 0                         */
+    int32_t kmax;                 /* 5, 6 or 7: Table I row                 */
+    int32_t kernel_rank;          /* m >= 0 (0 = K0 only), m <= n_atoms     */
+    int32_t kernel_every;         /* rebuild the kernel every k steps (>=1) */
+    int32_t krylov_mode;          /* 0 sequential Krylov, 1 block           */
+    double k0_gamma;              /* K0 = -k0_gamma I, in (0, 1]            */
+    int32_t precision;            /* xlbomd_precision                       */
+    double scf_tol;               /* RMS residual of the initial SCF        */
+    int32_t scf_max_iter;
+    int32_t energy_every;         /* energy evaluation period (0 = never
+                                     inside xlbomd_step)                    */
+    void *stream;                 /* hipStream_t to run on; NULL = library's
+                                     own stream                             */
+} xlbomd_desc;
+
+typedef struct {
+    double omega;      /* shadow free energy Omega[n](R)                    */
+    double e_band, e_coul, e_rep, te_s;  /* its parts: Tr[H0 D], Coulomb,
+                                            repulsion, Te * S               */
+    double e_kin;      /* nuclear kinetic energy                            */
+    double e_total;    /* e_kin + omega: the constant of motion             */
+    double rms_res;    /* RMS of r = q[n] - n                               */
+    double mu;         /* chemical potential                                */
+    double d_nelec;    /* Tr D - n_electrons after the mu correction        */
+    int32_t step;      /* steps taken since init                            */
+    int32_t foe_levels, ns_iters, mu_reruns, scf_iters, kernel_rank;
+    int32_t has_energy;/* 1 if the energy fields are valid                  */
+} xlbomd_report;
+
+/* Create a system: copies the descriptor's arrays to the device, solves the
+ * ground state by the kernel SCF of Eq. 52 from n = 0 to RMS(r) <= scf_tol,
+ * sets the initial conditions of Eq. 20 (history filled with n(t0)),
+ * computes F(t0) and the kernel at t0.  On success *out owns the handle. */
+int xlbomd_init_system(const xlbomd_desc *desc, xlbomd_system **out);
+
+/* Advance n_steps XL-BOMD steps (Eqs. 22-23).  If last != NULL the report
+ * of the final step is written (with energies if that step evaluated
+ * them).  Returns XLBOMD_E_DIVERGED if a non-finite value or a residual
+ * above 1e3 appears; the state is then the last good step. */
+int xlbomd_step(xlbomd_system *h, int32_t n_steps, xlbomd_report *last);
+
+/* Rebuild the low-rank kernel at the current state with rank `rank`
+ * (<= 0 keeps the descriptor's rank) and refresh K r (Eqs. 50-51). */
+int xlbomd_kernel_update(xlbomd_system *h, int32_t rank);
+
+/* Copy the current forces (n_atoms*3) and, if energy != NULL, evaluate and
+ * return the energy terms at the current state. */
+int xlbomd_forces(xlbomd_system *h, double *forces, xlbomd_report *energy);
+
+/* Current n(t) and q[n(t)] (n_atoms each; either may be NULL). */
+int xlbomd_get_charges(xlbomd_system *h, double *n_out, double *q_out);
+
+/* Overwrite the dynamical state: positions and velocities (n_atoms*3), the
+ * n history (kmax+1 rows of n_atoms: n(t), n(t-dt), ...) and the stored
+ * K r(t) used for the next n update (n_atoms).  Any of them may be NULL to
+ * keep the current value.  The electronic solve, forces and kernel are
+ * recomputed at the new state (kr, if given, is kept as passed). */
+int xlbomd_set_state(xlbomd_system *h, const double *pos, const double *vel,
+                     const double *n_hist, const double *kr);
+
+/* Read the dynamical state (same layouts as xlbomd_set_state). */
+int xlbomd_get_state(xlbomd_system *h, double *pos, double *vel,
+                     double *n_hist, double *kr);
+
+/* Electronic solve at the current positions for the charge vector n
+ * (n_atoms): writes q[n] (n_atoms) and, if rep != NULL, mu, RMS(q-n) and
+ * the FOE statistics.  Does not change the dynamical state. */
+int xlbomd_solve(xlbomd_system *h, const double *n, double *q_out,
+                 xlbomd_report *rep);
+
+/* Canonical first-order response dq/dlambda of q[n + lambda v] at the last
+ * xlbomd_solve (Section V.B), for `count` directions v (count rows of
+ * n_atoms), written to dq_out (count rows of n_atoms). */
+int xlbomd_response(xlbomd_system *h, int32_t count, const double *v,
+                    double *dq_out);
+
+/* Apply the rank-m kernel built at the last xlbomd_solve to r (n_atoms):
+ * kr_out = K_m r (Eq. 50 in closed Woodbury form). */
+int xlbomd_kernel_apply(xlbomd_system *h, int32_t rank, const double *r,
+                        double *kr_out);
+
+void xlbomd_destroy(xlbomd_system *h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *xlbomd_last_error(void);
+
+/* Library version string. */
+const char *xlbomd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XLBOMD_H */

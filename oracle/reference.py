@@ -1,0 +1,426 @@
+"""CPU oracle for finite-temperature XL-BOMD, FP64.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the HIP library (which shares no code
+with it).  Heavy loops (model, Jacobi, occupations, response, forces) are in
+xlbomd_oracle.c; this module strings them together in the order the paper
+states the method.
+
+Paper map (A. M. N. Niklasson, "Next generation extended Lagrangian first
+principles molecular dynamics"):
+  electronic solve    Section IV.A-B: H[n] = H0 + diag(Gamma n), Fermi-Dirac
+                      occupations with mu from sum f = N_occ (Eq. 36),
+                      D = 2 f(H), net Mulliken charges q (Section VI).
+  free energy         Eqs. 35, 37, 38 specialised to SCC tight binding:
+                      Omega = Tr[H0 D] + 1/2 (2q - n)^T Gamma n + E_rep - Te S.
+  forces              Eq. 40 first line (partial derivative at fixed n).
+  response            Section V.B: canonical first-order response of q to a
+                      potential perturbation along v (directional derivative
+                      of q[n + lambda v]).
+  kernel              Eqs. 48-51: K0 = (J0 - I)^-1, J0 = c I, followed by the
+                      Sherman-Morrison sequence of rank-1 updates over
+                      orthonormal directions, the first along K0 r.
+  integration         Eq. 22 (velocity Verlet for the nuclei; the second line
+                      is read with the velocity, not the acceleration) and
+                      Eq. 23 with the K_max = 5, 6, 7 rows of Table I.
+  initial state       Eq. 20 with the ground state from the kernel SCF of
+                      Eq. 52.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import build as _build
+
+_c = ctypes
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        L = ctypes.CDLL(path)
+        L.orc_h0.argtypes = [_c.c_int, _c.c_int, _dp, _dp, _dp, _dp,
+                             _c.c_double, _c.c_double, _c.c_double, _dp]
+        L.orc_gamma.argtypes = [_c.c_int, _dp, _dp, _c.c_double, _dp]
+        L.orc_erep.argtypes = [_c.c_int, _dp, _c.c_double, _c.c_double,
+                               _c.c_double, _c.c_double, _dp]
+        L.orc_erep.restype = _c.c_double
+        L.orc_forces.argtypes = [_c.c_int, _c.c_int, _dp, _dp, _c.c_double,
+                                 _c.c_double, _c.c_double, _c.c_double,
+                                 _dp, _dp, _dp, _dp]
+        L.orc_jacobi.argtypes = [_c.c_int, _dp, _dp, _dp, _c.c_double,
+                                 _c.c_int]
+        L.orc_fermi_mu.argtypes = [_c.c_int, _dp, _c.c_double, _c.c_double,
+                                   _dp]
+        L.orc_fermi_mu.restype = _c.c_double
+        L.orc_entropy.argtypes = [_c.c_int, _dp, _c.c_double, _c.c_double]
+        L.orc_entropy.restype = _c.c_double
+        L.orc_entropy_x.argtypes = [_c.c_double]
+        L.orc_entropy_x.restype = _c.c_double
+        L.orc_fermi.argtypes = [_c.c_double]
+        L.orc_fermi.restype = _c.c_double
+        L.orc_fermi_divdiff.argtypes = [_c.c_double, _c.c_double, _c.c_double]
+        L.orc_fermi_divdiff.restype = _c.c_double
+        L.orc_density.argtypes = [_c.c_int, _dp, _dp, _dp]
+        L.orc_response_diag.argtypes = [_c.c_int, _dp, _dp, _c.c_double,
+                                        _c.c_double, _dp, _dp]
+        L.orc_response_diag.restype = _c.c_double
+        L.orc_taper.argtypes = [_c.c_double, _c.c_double, _c.c_double,
+                                _c.POINTER(_c.c_double),
+                                _c.POINTER(_c.c_double)]
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Table I: dissipation coefficients of Eq. 23 (kappa, alpha, c_0..c_K).
+# ---------------------------------------------------------------------------
+TABLE_I = {
+    5: (1.82, 0.018, (-6, 14, -8, -3, 4, -1)),
+    6: (1.84, 0.0055, (-14, 36, -27, -2, 12, -6, 1)),
+    7: (1.86, 0.0016, (-36, 99, -88, 11, 32, -25, 8, -1)),
+}
+
+
+# ---------------------------------------------------------------------------
+# Model
+# ---------------------------------------------------------------------------
+class Model:
+    """SCC tight-binding model built from raw synthetic parameters."""
+
+    def __init__(self, s):
+        self.s = s
+        self.nat = int(s.n_atoms)
+        self.no = int(s.n_orb)
+        self.N = self.nat * self.no
+        self.beta = 1.0 / s.te
+        self.zcore = np.full(self.nat, s.n_electrons / self.nat)
+        self.mass = _f64(s.mass)
+
+    def h0(self, pos):
+        s = self.s
+        H = np.zeros((self.N, self.N))
+        rc = lib().orc_h0(self.nat, self.no, _f64(pos), _f64(s.onsite),
+                          _f64(s.onsite_jitter), _f64(s.hop_block),
+                          s.hop_decay, s.hop_cutoff, s.taper_width, H)
+        assert rc == 0
+        return H
+
+    def gamma(self, pos):
+        G = np.zeros((self.nat, self.nat))
+        assert lib().orc_gamma(self.nat, _f64(pos), _f64(self.s.hubbard_u),
+                               self.s.gamma_soft, G) == 0
+        return G
+
+    def erep(self, pos, want_force=False):
+        F = np.zeros(3 * self.nat)
+        e = lib().orc_erep(self.nat, _f64(pos), self.s.rep_a,
+                           self.s.rep_decay, self.s.hop_cutoff,
+                           self.s.taper_width, F)
+        return (e, F.reshape(self.nat, 3)) if want_force else e
+
+    def orbital_potential(self, G, n):
+        """diag of the charge-dependent Hamiltonian part, per orbital."""
+        return np.repeat(G @ n, self.no)
+
+
+# ---------------------------------------------------------------------------
+# Electronic solve (Section IV.A-B)
+# ---------------------------------------------------------------------------
+@dataclass
+class Electronic:
+    H0: np.ndarray
+    G: np.ndarray
+    H: np.ndarray
+    evals: np.ndarray
+    Vt: np.ndarray          # eigenvectors as rows
+    mu: float
+    f: np.ndarray
+    D: np.ndarray
+    q: np.ndarray
+    n: np.ndarray
+
+    @property
+    def r(self):
+        return self.q - self.n
+
+
+def jacobi(A, tol=1e-14, max_sweeps=60):
+    """Eigen-decomposition of a symmetric matrix by cyclic Jacobi."""
+    N = A.shape[0]
+    W = _f64(A).copy()
+    ev = np.zeros(N)
+    Vt = np.zeros((N, N))
+    sweeps = lib().orc_jacobi(N, W, ev, Vt, tol, max_sweeps)
+    if sweeps < 0:
+        raise RuntimeError("Jacobi did not converge")
+    return ev, Vt
+
+
+def fermi_mu(evals, beta, ne):
+    f = np.zeros(len(evals))
+    mu = lib().orc_fermi_mu(len(evals), _f64(evals), beta, ne, f)
+    return mu, f
+
+
+def density(Vt, f):
+    N = Vt.shape[0]
+    D = np.zeros((N, N))
+    lib().orc_density(N, _f64(Vt), _f64(f), D)
+    return D
+
+
+def charges(model, D):
+    """Net Mulliken charges q_I = sum_a D[Ia,Ia] - Z_I (orthogonal basis)."""
+    return np.diag(D).reshape(model.nat, model.no).sum(axis=1) - model.zcore
+
+
+def electronic(model, pos, n, H0=None, G=None):
+    """One-shot solve of the linearised functional at fixed n."""
+    if H0 is None:
+        H0 = model.h0(pos)
+    if G is None:
+        G = model.gamma(pos)
+    H = H0 + np.diag(model.orbital_potential(G, n))
+    ev, Vt = jacobi(H)
+    mu, f = fermi_mu(ev, model.beta, model.s.n_electrons)
+    D = density(Vt, f)
+    q = charges(model, D)
+    return Electronic(H0=H0, G=G, H=H, evals=ev, Vt=Vt, mu=mu, f=f, D=D, q=q,
+                      n=np.array(n, dtype=np.float64))
+
+
+# ---------------------------------------------------------------------------
+# Free energy and forces (Eqs. 35, 37, 38, 40)
+# ---------------------------------------------------------------------------
+def entropy(model, el):
+    return lib().orc_entropy(model.N, _f64(el.evals), model.beta, el.mu)
+
+
+def free_energy(model, pos, el) -> Dict[str, float]:
+    """Shadow free energy Omega[n](R) and its parts."""
+    e_band = float(np.sum(el.H0 * el.D))
+    e_coul = 0.5 * float((2.0 * el.q - el.n) @ (el.G @ el.n))
+    e_rep = model.erep(pos)
+    ts = model.s.te * entropy(model, el)
+    return dict(omega=e_band + e_coul + e_rep - ts, e_band=e_band,
+                e_coul=e_coul, e_rep=e_rep, te_s=ts)
+
+
+def forces(model, pos, el):
+    """-dOmega/dR at fixed n (Hellmann-Feynman; D is variational)."""
+    s = model.s
+    F = np.zeros(3 * model.nat)
+    assert lib().orc_forces(model.nat, model.no, _f64(pos),
+                            _f64(s.hop_block), s.hop_decay, s.hop_cutoff,
+                            s.taper_width, s.gamma_soft, _f64(el.D),
+                            _f64(el.q), _f64(el.n), F) == 0
+    _, Fr = model.erep(pos, want_force=True)
+    return F.reshape(model.nat, 3) + Fr
+
+
+# ---------------------------------------------------------------------------
+# Response and kernel (Section V)
+# ---------------------------------------------------------------------------
+def response(model, el, v):
+    """Directional derivative of q[n + lambda v] at lambda = 0 (canonical).
+
+    The perturbation of n by v shifts the orbital potentials by Gamma v; the
+    density-matrix response follows in closed form from the eigenpairs.
+    """
+    h = model.orbital_potential(el.G, v)
+    dd = np.zeros(model.N)
+    lib().orc_response_diag(model.N, _f64(el.Vt), _f64(el.evals), model.beta,
+                            el.mu, _f64(h), dd)
+    return dd.reshape(model.nat, model.no).sum(axis=1)
+
+
+def response_fd(model, pos, el, v, h=1e-4):
+    """Central finite difference of q along v (independent check)."""
+    qp = electronic(model, pos, el.n + h * v, el.H0, el.G).q
+    qm = electronic(model, pos, el.n - h * v, el.H0, el.G).q
+    return (qp - qm) / (2.0 * h)
+
+
+def jacobian(model, el):
+    """Full charge Jacobian J = dq/dn, one response per atom."""
+    J = np.zeros((model.nat, model.nat))
+    for j in range(model.nat):
+        e = np.zeros(model.nat)
+        e[j] = 1.0
+        J[:, j] = response(model, el, e)
+    return J
+
+
+@dataclass
+class KernelResult:
+    K: np.ndarray          # explicit N_at x N_at kernel K_m
+    V: np.ndarray          # directions actually used (N_at x m')
+    rank: int
+
+
+def _orth(x, V):
+    """Gram-Schmidt of x against the columns of V (twice), normalised."""
+    y = x.copy()
+    for _ in range(2):
+        for j in range(V.shape[1]):
+            y -= (V[:, j] @ y) * V[:, j]
+    nrm = np.linalg.norm(y)
+    return y, nrm
+
+
+def kernel_sm(model, el, gamma, m, mode=0, v_prev=None, resp=None):
+    """Rank-m kernel by the Sherman-Morrison sequence (Eq. 50).
+
+    K0 = -gamma I, i.e. J0 = (1 - 1/gamma) I (Eqs. 48-49).  Directions:
+      mode 0: v_1 = K0 r / |K0 r| (Eq. 51), then each v_j is K_{j-1} r
+              orthogonalised against v_1..v_{j-1} (Section V.F);
+      mode 1: v_1 as above, then the previous build's directions
+              v_prev[:, 0..m-2], orthogonalised in that order.
+    A direction whose orthogonalised norm falls below 1e-10 of its raw norm
+    ends the sequence (the space is exhausted).  `resp` overrides the
+    response function (defaults to the closed-form canonical response).
+    """
+    nat = model.nat
+    resp = resp or (lambda v: response(model, el, v))
+    c = 1.0 - 1.0 / gamma
+    J = c * np.eye(nat)
+    K = -gamma * np.eye(nat)
+    r = el.r
+    Vs = np.zeros((nat, 0))
+    for i in range(m):
+        if mode == 1 and i > 0:
+            if v_prev is None or i - 1 >= v_prev.shape[1]:
+                break
+            cand = v_prev[:, i - 1]
+        else:
+            cand = K @ r
+        raw = np.linalg.norm(cand)
+        if raw == 0.0:
+            break
+        v, nrm = _orth(cand, Vs)
+        if nrm <= 1e-10 * raw:
+            break
+        v = v / nrm
+        u = resp(v) - J @ v
+        J = J + np.outer(u, v)
+        Ku = K @ u
+        vK = v @ K
+        K = K - np.outer(Ku, vK) / (1.0 + v @ Ku)
+        Vs = np.column_stack([Vs, v])
+    return KernelResult(K=K, V=Vs, rank=Vs.shape[1])
+
+
+# ---------------------------------------------------------------------------
+# Integration (Eqs. 20, 22, 23, 52)
+# ---------------------------------------------------------------------------
+@dataclass
+class State:
+    pos: np.ndarray
+    vel: np.ndarray
+    force: np.ndarray
+    n_hist: np.ndarray            # (kmax+1, nat): n(t), n(t-dt), ...
+    kr: np.ndarray                # K_m r(t), used for n(t+dt)
+    K: Optional[np.ndarray]       # explicit kernel of the last build
+    V: Optional[np.ndarray]       # its directions
+    el: Electronic
+    step: int = 0
+    energy: Dict[str, float] = field(default_factory=dict)
+
+
+def scf(model, pos, gamma, m, tol=1e-10, max_iter=200, n0=None,
+        mode=0):
+    """Ground state by the kernel SCF of Eq. 52, from n = 0."""
+    H0 = model.h0(pos)
+    G = model.gamma(pos)
+    n = np.zeros(model.nat) if n0 is None else np.array(n0, dtype=float)
+    hist = []
+    for it in range(max_iter):
+        el = electronic(model, pos, n, H0, G)
+        rms = float(np.sqrt(np.mean(el.r ** 2)))
+        hist.append(rms)
+        if rms <= tol:
+            return el, hist
+        kr = kernel_sm(model, el, gamma, m, mode=0)
+        n = n - kr.K @ el.r
+    raise RuntimeError(f"SCF did not converge: {hist[-5:]}")
+
+
+def init_state(model, pos=None, vel=None, scf_tol=1e-10, gamma=None,
+               rank=None):
+    s = model.s
+    pos = _f64(s.pos if pos is None else pos).copy()
+    vel = _f64(s.vel if vel is None else vel).copy()
+    gamma = s.k0_gamma if gamma is None else gamma
+    rank = s.rank if rank is None else rank
+    el, _ = scf(model, pos, gamma, rank, tol=scf_tol)
+    hist = np.tile(el.n, (s.kmax + 1, 1))            # Eq. 20: ndot(t0) = 0
+    kres = kernel_sm(model, el, gamma, rank, mode=s.krylov_mode)
+    st = State(pos=pos, vel=vel, force=forces(model, pos, el), n_hist=hist,
+               kr=kres.K @ el.r, K=kres.K, V=kres.V, el=el)
+    st.energy = energy_report(model, st)
+    return st
+
+
+def energy_report(model, st):
+    fe = free_energy(model, st.pos, st.el)
+    ke = 0.5 * float(np.sum(model.mass[:, None] * st.vel ** 2))
+    fe.update(e_kin=ke, e_total=fe["omega"] + ke,
+              rms_res=float(np.sqrt(np.mean(st.el.r ** 2))), mu=st.el.mu)
+    return fe
+
+
+def md_step(model, st, gamma=None, rank=None, want_energy=True):
+    """One XL-BOMD step, t -> t + dt (Eqs. 22, 23)."""
+    s = model.s
+    gamma = s.k0_gamma if gamma is None else gamma
+    rank = s.rank if rank is None else rank
+    kappa, alpha, ck = TABLE_I[s.kmax]
+    dt = s.dt
+    m = model.mass[:, None]
+    vel = st.vel + 0.5 * dt * st.force / m
+    pos = st.pos + dt * vel
+    h = st.n_hist
+    n_new = 2.0 * h[0] - h[1] - kappa * st.kr
+    for k, c in enumerate(ck):
+        n_new = n_new + alpha * c * h[k]
+    hist = np.vstack([n_new[None, :], h[:-1]])
+    el = electronic(model, pos, n_new)
+    F = forces(model, pos, el)
+    step = st.step + 1
+    if step % s.kernel_every == 0 or st.K is None:
+        kres = kernel_sm(model, el, gamma, rank, mode=s.krylov_mode,
+                         v_prev=st.V)
+        K, V = kres.K, kres.V
+    else:
+        K, V = st.K, st.V
+    kr = K @ el.r
+    vel = vel + 0.5 * dt * F / m
+    nst = State(pos=pos, vel=vel, force=F, n_hist=hist, kr=kr, K=K, V=V,
+                el=el, step=step)
+    if want_energy:
+        nst.energy = energy_report(model, nst)
+    return nst
+
+
+def run(model, steps, st=None, callback=None, **kw):
+    st = st if st is not None else init_state(model)
+    out = [st.energy]
+    for _ in range(steps):
+        st = md_step(model, st, **kw)
+        out.append(st.energy)
+        if callback:
+            callback(st)
+    return st, out
