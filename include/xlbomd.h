@@ -162,6 +162,15 @@ int xlbomd_response(xlbomd_system *h, int32_t count, const double *v,
 int xlbomd_kernel_apply(xlbomd_system *h, int32_t rank, const double *r,
                         double *kr_out);
 
+/* Live timing of the dense MFMA products.  enable != 0 starts recording a
+ * HIP event pair on the handle's stream around every product launched by
+ * later calls; enable == 0 stops and, if out != NULL, writes
+ *   out[0] total kernel milliseconds, out[1] total algorithmic flops (each
+ *   output entry 2 n_k flops on the real n x n block; symmetric outputs count
+ *   n(n+1)/2 entries), out[2] number of launches, out[3] shortest and
+ *   out[4] longest launch in ms. */
+int xlbomd_profile(xlbomd_system *h, int32_t enable, double *out);
+
 void xlbomd_destroy(xlbomd_system *h);
 
 /* Message of the last failed call on this thread ("" if none). */

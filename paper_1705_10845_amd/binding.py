@@ -1,0 +1,215 @@
+"""ctypes binding of libxlbomd.so: argument marshalling only.
+
+Every step of the method runs in the HIP library; this module converts
+numpy arrays to host pointers and maps status codes to exceptions.  It
+raises if the library is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libxlbomd.so")
+
+FP64, FP32 = 0, 1
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("n_atoms", ctypes.c_int32), ("n_orb", ctypes.c_int32),
+        ("pos", _dp), ("vel", _dp), ("mass", _dp), ("onsite", _dp),
+        ("onsite_jitter", _dp), ("hop_block", _dp),
+        ("hop_decay", ctypes.c_double), ("hop_cutoff", ctypes.c_double),
+        ("taper_width", ctypes.c_double), ("hubbard_u", _dp),
+        ("gamma_soft", ctypes.c_double), ("rep_a", ctypes.c_double),
+        ("rep_decay", ctypes.c_double), ("n_electrons", ctypes.c_double),
+        ("te", ctypes.c_double), ("dt", ctypes.c_double),
+        ("kmax", ctypes.c_int32), ("kernel_rank", ctypes.c_int32),
+        ("kernel_every", ctypes.c_int32), ("krylov_mode", ctypes.c_int32),
+        ("k0_gamma", ctypes.c_double), ("precision", ctypes.c_int32),
+        ("scf_tol", ctypes.c_double), ("scf_max_iter", ctypes.c_int32),
+        ("energy_every", ctypes.c_int32), ("stream", ctypes.c_void_p),
+    ]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in (
+        "omega", "e_band", "e_coul", "e_rep", "te_s", "e_kin", "e_total",
+        "rms_res", "mu", "d_nelec")] + [(k, ctypes.c_int32) for k in (
+            "step", "foe_levels", "ns_iters", "mu_reruns", "scf_iters",
+            "kernel_rank", "has_energy")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class XlbomdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"xlbomd error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} missing: run "
+                              "python -m paper_1705_10845_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.xlbomd_init_system.argtypes = [ctypes.POINTER(Desc),
+                                         ctypes.POINTER(vp)]
+        L.xlbomd_step.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Report)]
+        L.xlbomd_kernel_update.argtypes = [vp, ctypes.c_int32]
+        L.xlbomd_forces.argtypes = [vp, _dp, ctypes.POINTER(Report)]
+        L.xlbomd_get_charges.argtypes = [vp, _dp, _dp]
+        L.xlbomd_set_state.argtypes = [vp, _dp, _dp, _dp, _dp]
+        L.xlbomd_get_state.argtypes = [vp, _dp, _dp, _dp, _dp]
+        L.xlbomd_solve.argtypes = [vp, _dp, _dp, ctypes.POINTER(Report)]
+        L.xlbomd_response.argtypes = [vp, ctypes.c_int32, _dp, _dp]
+        L.xlbomd_kernel_apply.argtypes = [vp, ctypes.c_int32, _dp, _dp]
+        L.xlbomd_profile.argtypes = [vp, ctypes.c_int32, _dp]
+        L.xlbomd_destroy.argtypes = [vp]
+        L.xlbomd_destroy.restype = None
+        L.xlbomd_last_error.restype = ctypes.c_char_p
+        L.xlbomd_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("xlbomd_init_system", "xlbomd_step", "xlbomd_kernel_update",
+            "xlbomd_forces", "xlbomd_get_charges", "xlbomd_set_state",
+            "xlbomd_get_state", "xlbomd_solve", "xlbomd_response",
+            "xlbomd_kernel_apply", "xlbomd_profile", "xlbomd_destroy", "xlbomd_last_error",
+            "xlbomd_version")
+
+
+def _check(rc):
+    if rc != 0:
+        raise XlbomdError(rc, lib().xlbomd_last_error().decode())
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_dp)
+
+
+def _c(a, shape=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+class XLBOMD:
+    """One system living on the GPU (a library handle)."""
+
+    def __init__(self, system, precision=FP64, scf_tol=None, scf_max_iter=300,
+                 energy_every=0, stream=None, **override):
+        s = system.replace(**override) if override else system
+        self.nat, self.no = int(s.n_atoms), int(s.n_orb)
+        self.kmax = int(s.kmax)
+        keep = dict(pos=_c(s.pos), vel=_c(s.vel), mass=_c(s.mass),
+                    onsite=_c(s.onsite), jit=_c(s.onsite_jitter),
+                    hop=_c(s.hop_block), u=_c(s.hubbard_u))
+        d = Desc()
+        d.n_atoms, d.n_orb = self.nat, self.no
+        d.pos, d.vel, d.mass = _ptr(keep["pos"]), _ptr(keep["vel"]), _ptr(keep["mass"])
+        d.onsite, d.onsite_jitter = _ptr(keep["onsite"]), _ptr(keep["jit"])
+        d.hop_block, d.hubbard_u = _ptr(keep["hop"]), _ptr(keep["u"])
+        d.hop_decay, d.hop_cutoff = s.hop_decay, s.hop_cutoff
+        d.taper_width, d.gamma_soft = s.taper_width, s.gamma_soft
+        d.rep_a, d.rep_decay = s.rep_a, s.rep_decay
+        d.n_electrons, d.te, d.dt = s.n_electrons, s.te, s.dt
+        d.kmax, d.kernel_rank = s.kmax, s.rank
+        d.kernel_every, d.krylov_mode = s.kernel_every, s.krylov_mode
+        d.k0_gamma, d.precision = s.k0_gamma, precision
+        d.scf_tol = scf_tol if scf_tol is not None else (
+            1e-10 if precision == FP64 else 1e-6)
+        d.scf_max_iter, d.energy_every = scf_max_iter, energy_every
+        d.stream = stream
+        self._h = ctypes.c_void_p()
+        _check(lib().xlbomd_init_system(ctypes.byref(d), ctypes.byref(self._h)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().xlbomd_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1, report=True):
+        rep = Report()
+        _check(lib().xlbomd_step(self._h, n, ctypes.byref(rep) if report else None))
+        return rep.as_dict() if report else None
+
+    def kernel_update(self, rank=0):
+        _check(lib().xlbomd_kernel_update(self._h, rank))
+
+    def forces(self, energy=True):
+        F = np.zeros((self.nat, 3))
+        rep = Report()
+        _check(lib().xlbomd_forces(self._h, _ptr(F),
+                                   ctypes.byref(rep) if energy else None))
+        return F, (rep.as_dict() if energy else None)
+
+    def charges(self):
+        n, q = np.zeros(self.nat), np.zeros(self.nat)
+        _check(lib().xlbomd_get_charges(self._h, _ptr(n), _ptr(q)))
+        return n, q
+
+    def set_state(self, pos=None, vel=None, n_hist=None, kr=None):
+        a = [_c(pos, (self.nat, 3)), _c(vel, (self.nat, 3)),
+             _c(n_hist, (self.kmax + 1, self.nat)), _c(kr, (self.nat,))]
+        _check(lib().xlbomd_set_state(self._h, *[_ptr(x) for x in a]))
+
+    def get_state(self):
+        pos, vel = np.zeros((self.nat, 3)), np.zeros((self.nat, 3))
+        hist, kr = np.zeros((self.kmax + 1, self.nat)), np.zeros(self.nat)
+        _check(lib().xlbomd_get_state(self._h, _ptr(pos), _ptr(vel),
+                                      _ptr(hist), _ptr(kr)))
+        return dict(pos=pos, vel=vel, n_hist=hist, kr=kr)
+
+    def solve(self, n):
+        n = _c(n, (self.nat,))
+        q = np.zeros(self.nat)
+        rep = Report()
+        _check(lib().xlbomd_solve(self._h, _ptr(n), _ptr(q), ctypes.byref(rep)))
+        return q, rep.as_dict()
+
+    def response(self, V):
+        V = _c(np.atleast_2d(V))
+        out = np.zeros_like(V)
+        _check(lib().xlbomd_response(self._h, V.shape[0], _ptr(V), _ptr(out)))
+        return out
+
+    def profile_start(self):
+        _check(lib().xlbomd_profile(self._h, 1, None))
+
+    def profile_stop(self):
+        out = np.zeros(5)
+        _check(lib().xlbomd_profile(self._h, 0, _ptr(out)))
+        return dict(ms=out[0], flops=out[1], launches=int(out[2]),
+                    min_ms=out[3], max_ms=out[4])
+
+    def kernel_apply(self, rank, r):
+        r = _c(r, (self.nat,))
+        out = np.zeros(self.nat)
+        _check(lib().xlbomd_kernel_apply(self._h, rank, _ptr(r), _ptr(out)))
+        return out

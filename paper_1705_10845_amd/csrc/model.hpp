@@ -1,0 +1,579 @@
+// Model and bookkeeping kernels: Coulomb products, the scaled Hamiltonian
+// seed of the expansion, Gershgorin bounds, charges, forces and energy
+// parts, reductions over the density matrix, the Krylov/kernel algebra and
+// the Verlet updates.  Everything that leaves the dense algebra is FP64.
+#pragma once
+#include "common.hpp"
+
+namespace xl {
+
+struct ModelDev {
+    int nat, no, n, ld;           // atoms, orbitals/atom, n = nat*no, ld
+    const double *pos;            // nat*3
+    const double *onsite;         // no
+    const double *jit;            // n (may be null)
+    const double *hop;            // no*no
+    const double *U;              // nat
+    double decay, rc, width, soft, rep_a, rep_decay;
+};
+
+// smooth cutoff s(r) and ds/dr: 1 below rc - w, quintic C2 ramp, 0 at rc
+__device__ __forceinline__ void taper(double r, double rc, double w, double &s,
+                                      double &ds) {
+    if (r >= rc) { s = 0.0; ds = 0.0; return; }
+    if (w <= 0.0 || r <= rc - w) { s = 1.0; ds = 0.0; return; }
+    const double t = (r - (rc - w)) / w, t2 = t * t, t3 = t2 * t;
+    s = 1.0 - 10.0 * t3 + 15.0 * t3 * t - 6.0 * t3 * t2;
+    ds = (-30.0 * t2 + 60.0 * t3 - 30.0 * t3 * t) / w;
+}
+
+__device__ __forceinline__ double pair_dist(const double *pos, int I, int J,
+                                            double &dx, double &dy, double &dz) {
+    dx = pos[3 * I] - pos[3 * J];
+    dy = pos[3 * I + 1] - pos[3 * J + 1];
+    dz = pos[3 * I + 2] - pos[3 * J + 2];
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+// y[b][I] = U_I x[b][I] + sum_{J != I} x[b][J] / sqrt(r_IJ^2 + a^2).
+// One wave per (atom, batch); Gamma is never stored.
+__global__ __launch_bounds__(256) void gamma_matvec_kernel(ModelDev m, int nb,
+                                                           const double *x,
+                                                           double *y) {
+    const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (w >= m.nat * nb) return;
+    const int b = w / m.nat, I = w % m.nat;
+    const double *xb = x + (long)b * m.nat;
+    const double a2 = m.soft * m.soft;
+    double s = 0.0;
+    for (int J = lane; J < m.nat; J += 64) {
+        if (J == I) continue;
+        double dx, dy, dz;
+        const double r = pair_dist(m.pos, I, J, dx, dy, dz);
+        s += xb[J] / sqrt(r * r + a2);
+    }
+    s = wave_sum(s);
+    if (lane == 0) y[(long)b * m.nat + I] = s + m.U[I] * xb[I];
+}
+
+// Gershgorin interval of row Ia of H = H0 + diag(v): [d - R, d + R].
+// One wave per atom.  lo/hi get one entry per orbital row.
+__global__ __launch_bounds__(256) void gershgorin_kernel(ModelDev m,
+                                                         const double *v,
+                                                         double *lo, double *hi) {
+    const int I = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (I >= m.nat) return;
+    double rad[8];
+    for (int a = 0; a < m.no; ++a) rad[a] = 0.0;
+    for (int J = lane; J < m.nat; J += 64) {
+        if (J == I) continue;
+        double dx, dy, dz;
+        const double r = pair_dist(m.pos, I, J, dx, dy, dz);
+        if (r >= m.rc) continue;
+        double s, ds;
+        taper(r, m.rc, m.width, s, ds);
+        const double h = exp(-r / m.decay) * s;
+        for (int a = 0; a < m.no; ++a)
+            for (int b = 0; b < m.no; ++b) rad[a] += fabs(m.hop[a * m.no + b] * h);
+    }
+    for (int a = 0; a < m.no; ++a) {
+        const double R = wave_sum(rad[a]);
+        if (lane == 0) {
+            const int i = I * m.no + a;
+            const double d = m.onsite[a] + (m.jit ? m.jit[i] : 0.0) + v[I];
+            lo[i] = d - R;
+            hi[i] = d + R;
+        }
+    }
+}
+
+// out[0] = min(lo), out[1] = max(hi); one block.
+__global__ __launch_bounds__(1024) void minmax_kernel(int n, const double *lo,
+                                                      const double *hi,
+                                                      double *out) {
+    __shared__ double smin[1024], smax[1024];
+    double a = 1e300, b = -1e300;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        a = fmin(a, lo[i]);
+        b = fmax(b, hi[i]);
+    }
+    smin[threadIdx.x] = a;
+    smax[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = smin[0];
+        out[1] = smax[0];
+    }
+}
+
+// Y = sc * (H - mu I) over the real n x n block, zero in the padding.
+// H[Ia,Ia] = onsite[a] + jit[Ia] + v[I];  H[Ia,Jb] = B_ab exp(-r/decay) s(r).
+template <typename T>
+__global__ __launch_bounds__(256) void build_seed_kernel(ModelDev m,
+                                                         const double *v,
+                                                         double mu, double sc,
+                                                         T *Y) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= m.ld) return;
+    double val = 0.0;
+    if (i < m.n && j < m.n) {
+        const int I = i / m.no, a = i % m.no, J = j / m.no, b = j % m.no;
+        if (I == J) {
+            if (a == b)
+                val = sc * (m.onsite[a] + (m.jit ? m.jit[i] : 0.0) + v[I] - mu);
+        } else {
+            double dx, dy, dz;
+            const double r = pair_dist(m.pos, I, J, dx, dy, dz);
+            if (r < m.rc) {
+                double s, ds;
+                taper(r, m.rc, m.width, s, ds);
+                val = sc * m.hop[a * m.no + b] * exp(-r / m.decay) * s;
+            }
+        }
+    }
+    Y[(long)i * m.ld + j] = (T)val;
+}
+
+// Sum of squares of each row of Z over the real block; one wave per row.
+template <typename T>
+__global__ __launch_bounds__(256) void row_sqnorm_kernel(int n, int ld,
+                                                         const T *Z, double *out) {
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;
+    const T *row = Z + (long)i * ld;
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) {
+        const double z = (double)row[j];
+        s += z * z;
+    }
+    s = wave_sum(s);
+    if (lane == 0) out[i] = s;
+}
+
+// Newton step of the electron count (one block):
+//   Tr D = n - 2 Tr Z_L,  dN/dmu = (beta/2) sum_i (1 - 4 |row_i Z_L|^2),
+//   dmu = (n_e - Tr D) / (dN/dmu).   out = {Tr D, dN/dmu, dmu}.
+// Also g[i] = (beta/2)(1 - 4 |row_i|^2) = diag of dD/dmu.
+template <typename T>
+__global__ __launch_bounds__(1024) void mu_newton_kernel(int n, int ld, const T *Z,
+                                                         const double *rsq,
+                                                         double beta, double ne,
+                                                         double *g, double *out) {
+    __shared__ double sh[16];
+    double tr = 0.0, dn = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        tr += 1.0 - 2.0 * (double)Z[(long)i * ld + i];
+        const double gi = 0.5 * beta * (1.0 - 4.0 * rsq[i]);
+        g[i] = gi;
+        dn += gi;
+    }
+    tr = block_sum(tr, sh);
+    dn = block_sum(dn, sh);
+    if (threadIdx.x == 0) {
+        out[0] = tr;
+        out[1] = dn;
+        out[2] = (ne - tr) / dn;
+    }
+}
+
+// q_I = sum_a D[Ia,Ia] - zc;  r = q - n;  out[0] = sum r^2, out[1] = sum q.
+template <typename T>
+__global__ __launch_bounds__(1024) void charges_kernel(int nat, int no, int ld,
+                                                       const T *D, double zc,
+                                                       const double *nvec,
+                                                       double *q, double *r,
+                                                       double *out) {
+    __shared__ double sh[16];
+    double s2 = 0.0, sq = 0.0;
+    for (int I = threadIdx.x; I < nat; I += blockDim.x) {
+        double p = 0.0;
+        for (int a = 0; a < no; ++a) {
+            const long i = (long)I * no + a;
+            p += (double)D[i * ld + i];
+        }
+        const double qi = p - zc;
+        q[I] = qi;
+        const double ri = qi - nvec[I];
+        r[I] = ri;
+        s2 += ri * ri;
+        sq += qi;
+    }
+    s2 = block_sum(s2, sh);
+    sq = block_sum(sq, sh);
+    if (threadIdx.x == 0) {
+        out[0] = s2;
+        out[1] = sq;
+    }
+}
+
+// Hellmann-Feynman forces at fixed n and per-atom energy parts.
+//   F_I = -sum_J g_IJ (R_I - R_J)/r,  g = dE/dr of the pair
+//   band: 2 (h s)'(r) sum_ab B_ab D[Ia,Jb]; Coulomb:
+//   1/2 [(2q_I - n_I) n_J + (2q_J - n_J) n_I] dgamma/dr; repulsion.
+// e[0..3][I]: band (onsite + half of each bond counted twice = full bond),
+// Coulomb 1/2 (2q_I - n_I) v_I, repulsion (half per pair), unused.
+template <typename T>
+__global__ __launch_bounds__(256) void forces_kernel(ModelDev m, const T *D,
+                                                     const double *q,
+                                                     const double *nv,
+                                                     const double *v, double *F,
+                                                     double *e) {
+    const int I = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (I >= m.nat) return;
+    const int no = m.no;
+    const double a2 = m.soft * m.soft;
+    double fx = 0, fy = 0, fz = 0, eb = 0, er = 0;
+    const double cI = 2.0 * q[I] - nv[I];
+    for (int J = lane; J < m.nat; J += 64) {
+        if (J == I) continue;
+        double dx, dy, dz;
+        const double r = pair_dist(m.pos, I, J, dx, dy, dz);
+        double g = 0.0;
+        if (r < m.rc) {
+            double s, ds;
+            taper(r, m.rc, m.width, s, ds);
+            const double ex = exp(-r / m.decay);
+            const double dh = ex * (ds - s / m.decay);
+            double bd = 0.0;
+            for (int a = 0; a < no; ++a) {
+                const T *Drow = D + (long)(I * no + a) * m.ld + J * no;
+                for (int b = 0; b < no; ++b) bd += m.hop[a * no + b] * (double)Drow[b];
+            }
+            g += 2.0 * dh * bd;
+            eb += 2.0 * ex * s * bd;   // both (Ia,Jb) and (Jb,Ia) blocks
+            if (m.rep_a != 0.0) {
+                const double ea = m.rep_a * exp(-r / m.rep_decay);
+                er += 0.5 * ea * s;
+                g += ea * (ds - s / m.rep_decay);
+            }
+        }
+        const double inv = 1.0 / sqrt(r * r + a2);
+        const double dg = -r * inv * inv * inv;
+        g += 0.5 * (cI * nv[J] + (2.0 * q[J] - nv[J]) * nv[I]) * dg;
+        fx -= g * dx / r;
+        fy -= g * dy / r;
+        fz -= g * dz / r;
+    }
+    fx = wave_sum(fx);
+    fy = wave_sum(fy);
+    fz = wave_sum(fz);
+    eb = wave_sum(eb);
+    er = wave_sum(er);
+    if (lane == 0) {
+        F[3 * I] = fx;
+        F[3 * I + 1] = fy;
+        F[3 * I + 2] = fz;
+        double on = 0.0;
+        for (int a = 0; a < no; ++a) {
+            const long i = (long)I * no + a;
+            on += (m.onsite[a] + (m.jit ? m.jit[i] : 0.0)) * (double)D[i * m.ld + i];
+        }
+        // band energy per atom: onsite part plus half of each bond pair
+        // (eb above counts both off-diagonal blocks of the pair; the pair is
+        // visited from I and from J, so halve it)
+        e[I] = on + 0.5 * eb;
+        e[m.nat + I] = 0.5 * cI * v[I];
+        e[2 * m.nat + I] = er;
+    }
+}
+
+// Deterministic single-block sum of k contiguous arrays of length n.
+__global__ __launch_bounds__(1024) void sum_rows_kernel(int n, int k,
+                                                        const double *x,
+                                                        double *out) {
+    __shared__ double sh[16];
+    for (int c = 0; c < k; ++c) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) s += x[(long)c * n + i];
+        s = block_sum(s, sh);
+        if (threadIdx.x == 0) out[c] = s;
+    }
+}
+
+// Seed derivative of the response: with G = Y diag(u) Y and Y2 = Y^2,
+//   Z'_0 = 1/2 diag(u) - 1/6 [G + diag(u) Y2 + Y2 diag(u)].
+template <typename T>
+__global__ __launch_bounds__(256) void seed_resp_kernel(int n, int ld,
+                                                        const T *G, const T *Y2,
+                                                        const double *u,
+                                                        long su, long sG, T *Zp) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    const long b = blockIdx.z;
+    if (j >= ld) return;
+    const long o = (long)i * ld + j;
+    double val = 0.0;
+    if (i < n && j < n) {
+        const double ui = u[b * su + i], uj = u[b * su + j];
+        val = -(1.0 / 6.0) * ((double)G[b * sG + o] + (ui + uj) * (double)Y2[o]);
+        if (i == j) val += 0.5 * ui;
+    }
+    Zp[b * sG + o] = (T)val;
+}
+
+// Partial column sums of Y[l][i] * T[l][i] over row chunks of 64 rows:
+// part[b][chunk][i].  diag(Y T)_i = sum_l Y[i][l] T[l][i] with Y symmetric.
+template <typename T>
+__global__ __launch_bounds__(256) void coldot_kernel(int n, int ld, const T *Y,
+                                                     const T *Tm, long sT,
+                                                     double *part, long sP) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int chunk = blockIdx.y;
+    const long b = blockIdx.z;
+    if (i >= n) return;
+    const T *Tb = Tm + b * sT;
+    double s = 0.0;
+    const int l0 = chunk * 64, l1 = min(n, l0 + 64);
+    for (int l = l0; l < l1; ++l) s += (double)Y[(long)l * ld + i] * (double)Tb[(long)l * ld + i];
+    part[b * sP + (long)chunk * n + i] = s;
+}
+
+// Canonical charge response from diag(Z'_L) partials (one block per batch):
+//   d_i = sum_chunks part; q'fix_I = -2 sum_a d_Ia;
+//   mu' = -sum q'fix / sum g;  q'_I = q'fix_I + mu' sum_a g_Ia;  w = q' - v.
+__global__ __launch_bounds__(1024) void resp_charges_kernel(
+    int nat, int no, int nchunk, const double *part, long sP, const double *g,
+    const double *v, double *qp, double *w) {
+    __shared__ double sh[16];
+    const long b = blockIdx.x;
+    const int n = nat * no;
+    const double *pb = part + b * sP;
+    double sq = 0.0, sg = 0.0;
+    for (int I = threadIdx.x; I < nat; I += blockDim.x) {
+        double qf = 0.0, gs = 0.0;
+        for (int a = 0; a < no; ++a) {
+            const int i = I * no + a;
+            double d = 0.0;
+            for (int c = 0; c < nchunk; ++c) d += pb[(long)c * n + i];
+            qf += -2.0 * d;
+            gs += g[i];
+        }
+        qp[b * nat + I] = qf;
+        sq += qf;
+        sg += gs;
+    }
+    sq = block_sum(sq, sh);
+    sg = block_sum(sg, sh);
+    const double mup = -sq / sg;
+    for (int I = threadIdx.x; I < nat; I += blockDim.x) {
+        double gs = 0.0;
+        for (int a = 0; a < no; ++a) gs += g[I * no + a];
+        const double val = qp[b * nat + I] + mup * gs;
+        qp[b * nat + I] = val;
+        if (w) w[b * nat + I] = val - v[b * nat + I];
+    }
+}
+
+// v_out = orth(x) against the first j columns (rows of V, nat each),
+// Gram-Schmidt applied twice; nrm = {|x|, |orth(x)|}.  If |orth(x)| > 0 the
+// output is normalised.  One block.
+__global__ __launch_bounds__(1024) void orth_kernel(int nat, int j,
+                                                    const double *V,
+                                                    const double *x, double scale,
+                                                    double *vout, double *nrm) {
+    __shared__ double sh[16];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nat; i += blockDim.x) {
+        const double t = scale * x[i];
+        vout[i] = t;
+        s += t * t;
+    }
+    s = block_sum(s, sh);
+    const double raw = sqrt(s);
+    for (int pass = 0; pass < 2; ++pass)
+        for (int c = 0; c < j; ++c) {
+            const double *vc = V + (long)c * nat;
+            double d = 0.0;
+            for (int i = threadIdx.x; i < nat; i += blockDim.x) d += vc[i] * vout[i];
+            d = block_sum(d, sh);
+            for (int i = threadIdx.x; i < nat; i += blockDim.x) vout[i] -= d * vc[i];
+            __syncthreads();
+        }
+    s = 0.0;
+    for (int i = threadIdx.x; i < nat; i += blockDim.x) s += vout[i] * vout[i];
+    s = block_sum(s, sh);
+    const double on = sqrt(s);
+    if (on > 0.0)
+        for (int i = threadIdx.x; i < nat; i += blockDim.x) vout[i] /= on;
+    if (threadIdx.x == 0) {
+        nrm[0] = raw;
+        nrm[1] = on;
+    }
+}
+
+// kr = K_m r with K_m = -gamma (I - W M V^T) + V M V^T, M = (V^T W)^-1
+// (Sherman-Morrison sequence in closed form), m <= 16.  One block.
+__global__ __launch_bounds__(1024) void kernel_apply_kernel(int nat, int m,
+                                                            const double *V,
+                                                            const double *W,
+                                                            const double *r,
+                                                            double gamma,
+                                                            double *kr,
+                                                            double *info) {
+    __shared__ double sh[16];
+    __shared__ double G[16][17];
+    __shared__ double c[16];
+    __shared__ int ok;
+    for (int a = 0; a < m; ++a) {
+        for (int b = 0; b < m; ++b) {
+            double d = 0.0;
+            for (int i = threadIdx.x; i < nat; i += blockDim.x)
+                d += V[(long)a * nat + i] * W[(long)b * nat + i];
+            d = block_sum(d, sh);
+            if (threadIdx.x == 0) G[a][b] = d;
+        }
+        double d = 0.0;
+        for (int i = threadIdx.x; i < nat; i += blockDim.x) d += V[(long)a * nat + i] * r[i];
+        d = block_sum(d, sh);
+        if (threadIdx.x == 0) G[a][m] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // Gaussian elimination with partial pivoting on [G | V^T r]
+        ok = 1;
+        for (int k = 0; k < m; ++k) {
+            int p = k;
+            for (int i = k + 1; i < m; ++i)
+                if (fabs(G[i][k]) > fabs(G[p][k])) p = i;
+            if (G[p][k] == 0.0) { ok = 0; break; }
+            if (p != k)
+                for (int t = 0; t <= m; ++t) { double z = G[k][t]; G[k][t] = G[p][t]; G[p][t] = z; }
+            for (int i = k + 1; i < m; ++i) {
+                const double f = G[i][k] / G[k][k];
+                for (int t = k; t <= m; ++t) G[i][t] -= f * G[k][t];
+            }
+        }
+        for (int k = m - 1; k >= 0 && ok; --k) {
+            double s = G[k][m];
+            for (int t = k + 1; t < m; ++t) s -= G[k][t] * c[t];
+            c[k] = s / G[k][k];
+        }
+        if (!ok) for (int k = 0; k < m; ++k) c[k] = 0.0;
+        if (info) info[0] = ok;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nat; i += blockDim.x) {
+        double wc = 0.0, vc = 0.0;
+        for (int a = 0; a < m; ++a) {
+            wc += W[(long)a * nat + i] * c[a];
+            vc += V[(long)a * nat + i] * c[a];
+        }
+        kr[i] = -gamma * (r[i] - wc) + vc;
+    }
+}
+
+// n(t+dt) = 2 n(t) - n(t-dt) - kappa kr + alpha sum_k c_k n(t - k dt) (Eq. 23)
+// hist rows are addressed through the ring: row k of the history is
+// hist[((head + k) % (kmax+1)) * nat].  Writes the new row at slot `dst`.
+__global__ __launch_bounds__(256) void verlet_n_kernel(int nat, int kmax, int head,
+                                                       int dst, double kappa,
+                                                       double alpha,
+                                                       const double *cvec,
+                                                       const double *kr,
+                                                       double *hist) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nat) return;
+    const int K = kmax + 1;
+    auto row = [&](int k) { return hist[(long)((head + k) % K) * nat + i]; };
+    double val = 2.0 * row(0) - row(1) - kappa * kr[i];
+    double d = 0.0;
+    for (int k = 0; k <= kmax; ++k) d += cvec[k] * row(k);
+    val += alpha * d;
+    hist[(long)dst * nat + i] = val;
+}
+
+// velocity half kick and optional drift (Eq. 22)
+__global__ __launch_bounds__(256) void kick_drift_kernel(int nat, double hdt,
+                                                         double dt, const double *F,
+                                                         const double *mass,
+                                                         double *vel, double *pos) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * nat) return;
+    const int I = i / 3;
+    double v = vel[i] + hdt * F[i] / mass[I];
+    vel[i] = v;
+    if (pos) pos[i] += dt * v;
+}
+
+// out = 1/2 sum M v^2 (one block)
+__global__ __launch_bounds__(1024) void kinetic_kernel(int nat, const double *vel,
+                                                       const double *mass,
+                                                       double *out) {
+    __shared__ double sh[16];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < 3 * nat; i += blockDim.x) s += mass[i / 3] * vel[i] * vel[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[0] = 0.5 * s;
+}
+
+// out[b] = u[b] scaled per orbital: u[b][Ia] = sc * h[b][I]
+__global__ __launch_bounds__(256) void expand_orbital_kernel(int nat, int no,
+                                                             int nb, double sc,
+                                                             const double *h,
+                                                             long su, double *u) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long n = (long)nat * no;
+    if (t >= n * nb) return;
+    const long b = t / n, i = t % n;
+    u[b * su + i] = sc * h[b * nat + i / no];
+}
+
+// dst = scale * src (whole padded matrix), converted to FP64
+template <typename T>
+__global__ __launch_bounds__(256) void convert_kernel(long n, const T *src,
+                                                      double scale, double *dst) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = scale * (double)src[i];
+}
+
+// C = A + val * I on the first n diagonal entries (whole padded copy)
+__global__ __launch_bounds__(256) void add_diag_copy_kernel(int ld, int n,
+                                                            const double *A,
+                                                            double val, double *C) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)ld * ld) return;
+    const long i = t / ld, j = t % ld;
+    C[t] = A[t] + ((i == j && i < n) ? val : 0.0);
+}
+
+// Per row i < n: part[0][i] = P_ii, part[1][i] = sum_j P_ij Z_ij,
+// part[2][i] = sum_j P_ij Z2_ij (real block only).  One block per row.
+__global__ __launch_bounds__(256) void frob3_kernel(int n, int ld, const double *P,
+                                                    const double *Z,
+                                                    const double *Z2, double *part) {
+    __shared__ double sh[16];
+    const int i = blockIdx.x;
+    const double *p = P + (long)i * ld, *z = Z + (long)i * ld, *z2 = Z2 + (long)i * ld;
+    double a = 0.0, b = 0.0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        a += p[j] * z[j];
+        b += p[j] * z2[j];
+    }
+    a = block_sum(a, sh);
+    b = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        part[i] = p[i];
+        part[n + i] = a;
+        part[2 * n + i] = b;
+    }
+}
+
+__global__ __launch_bounds__(256) void axpy_kernel(int n, double a, const double *x,
+                                                   double *y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += a * x[i];
+}
+
+}  // namespace xl

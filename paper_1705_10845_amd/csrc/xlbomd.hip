@@ -1,0 +1,1039 @@
+// Host orchestration and C ABI of the XL-BOMD library (gfx950).
+//
+// Per step (Eqs. 22-23): half kick + drift of the nuclei, the dissipative
+// Verlet update of n, the one-shot electronic solve of the linearised
+// functional at the new (R, n), Hellmann-Feynman forces at fixed n, the
+// low-rank kernel K_m and K_m r for the next n update, the second half kick.
+//
+// Electronic solve without diagonalisation.  With X = beta (H - mu I), the
+// occupation f(x) = 1/(1+e^x) = (1 - tanh(x/2))/2.  tanh doubles its
+// argument under t -> 2t / (1 + t^2), so starting from t0 ~ tanh(x/2^(L+1))
+// and applying the map L times gives tanh(x/2); D = 2f(H) = I - t_L.  In
+// matrix form with Z = t/2 every level is
+//     A_k = I + 4 Z_k^2,   Y_k = A_k^-1,   Z_{k+1} = 2 Y_k Z_k,
+// D = I - 2 Z_L.  A_k has its spectrum in [1, 1 + t_k,max^2] within [1, 2],
+// so Y_k follows from a fixed Chebyshev-optimal linear guess plus a few
+// Newton-Schulz steps Y <- Y (2I - A Y), the number of steps chosen per level
+// from the known spectral bound.  The seed t0 = y - y^3/3, y = X/2^(L+1),
+// is tanh(y) to O(y^5), which lets L be about half of what t0 = y needs for
+// the same truncation error.  All products are dense symmetric GEMMs on
+// MFMA (FP64 or FP32).  The chemical potential follows from a Newton step
+// on Tr D in FP64 (rerun of the expansion if beta |dmu| is above a
+// threshold) and a first-order correction dD/dmu = (beta/2)(I - 4 Z_L^2).
+//
+// Response (Section V.B).  Differentiating the same recursion along a
+// perturbation H1 = diag(Gamma v) gives, with Z'_0 from the seed,
+//     A'_k = 4 (Z_k Z'_k + Z'_k Z_k),
+//     Z'_{k+1} = Y_k (2 Z'_k - A'_k Z_{k+1}),
+// and D' = -2 Z'_L, made canonical (fixed electron number) by mu'.
+#include "../../include/xlbomd.h"
+#include "common.hpp"
+#include "gemm.hpp"
+#include "model.hpp"
+#include "chol.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+using namespace xl;
+
+namespace {
+
+thread_local std::string g_err;
+
+// Table I: kappa, alpha and c_0..c_K of the dissipative term of Eq. 23.
+struct DampRow {
+    double kappa, alpha;
+    int nc;
+    double c[8];
+};
+const DampRow kDamp[3] = {
+    {1.82, 0.018, 6, {-6, 14, -8, -3, 4, -1}},
+    {1.84, 0.0055, 7, {-14, 36, -27, -2, 12, -6, 1}},
+    {1.86, 0.0016, 8, {-36, 99, -88, 11, 32, -25, 8, -1}},
+};
+
+template <typename T> T *dalloc(size_t n) {
+    void *p = nullptr;
+    if (n == 0) n = 1;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        throw NoMem("device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    }
+    return (T *)p;
+}
+
+struct DevFree {
+    std::vector<void *> ptrs;
+    ~DevFree() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+};
+
+// Fermi function written without overflow
+double fermi(double x) {
+    if (x > 0) {
+        const double e = std::exp(-x);
+        return e / (1.0 + e);
+    }
+    return 1.0 / (1.0 + std::exp(x));
+}
+
+// The scalar map the matrix expansion applies to each eigenvalue.
+double foe_scalar(double x, int L) {
+    const double y = std::ldexp(x, -(L + 1));
+    double t = y - y * y * y / 3.0;
+    for (int k = 0; k < L; ++k) t = 2.0 * t / (1.0 + t * t);
+    return 0.5 * (1.0 - t);
+}
+
+// Smallest L whose expansion keeps |y| <= 1/2 and stays within `tol` of the
+// Fermi function on [-xmax, xmax].
+int choose_levels(double xmax, double tol) {
+    for (int L = 1; L <= 40; ++L) {
+        if (std::ldexp(xmax, -(L + 1)) > 0.5) continue;
+        double err = 0.0;
+        const int G = 2000;
+        for (int g = 0; g <= G; ++g) {
+            const double x = -xmax + 2.0 * xmax * g / G;
+            err = std::max(err, std::fabs(foe_scalar(x, L) - fermi(x)));
+        }
+        for (int g = 0; g <= 400; ++g) {   // dense near the Fermi level
+            const double x = -12.0 + 24.0 * g / 400.0;
+            if (std::fabs(x) <= xmax)
+                err = std::max(err, std::fabs(foe_scalar(x, L) - fermi(x)));
+        }
+        if (err <= tol) return L;
+    }
+    return 40;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Precision-independent state of one system
+// ---------------------------------------------------------------------------
+struct SysBase {
+    virtual ~SysBase() = default;
+    xlbomd_desc d{};
+    int nat = 0, no = 0, N = 0, Np = 0;
+    double beta = 0.0, zc = 0.0;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    DevFree mem;
+    ModelDev md{};
+
+    // device arrays (FP64)
+    double *pos = nullptr, *vel = nullptr, *mass = nullptr, *force = nullptr;
+    double *onsite = nullptr, *jit = nullptr, *hop = nullptr, *U = nullptr;
+    double *hist = nullptr, *kr = nullptr, *q = nullptr, *r = nullptr;
+    double *ncur = nullptr, *vpot = nullptr, *glo = nullptr, *ghi = nullptr;
+    double *g = nullptr, *epart = nullptr, *scal = nullptr, *cvec = nullptr;
+    double *V = nullptr, *W = nullptr, *Vprev = nullptr, *vtmp = nullptr;
+    double *qp = nullptr, *hb = nullptr, *ub = nullptr, *part = nullptr, *vin = nullptr;
+    double *hscal = nullptr;   // pinned host scalars
+    int head = 0;              // ring index of n(t) in hist
+    int mcap = 0, rank_built = 0, rank_prev = 0, step_no = 0;
+    int bcap = 0;              // response batch capacity
+
+    // electronic state of the last solve
+    double mu = 0.0, mu_prev = 0.0, mu_prev2 = 0.0;
+    int mu_known = 0;          // number of valid entries in mu history
+    int L = 0, ns_total = 0, reruns = 0, scf_iters = 0;
+    double dmu = 0.0, trd = 0.0, rms = 0.0, sumq = 0.0, sc = 0.0;
+    double elo = 0.0, ehi = 0.0, t0max = 0.0;
+    bool have_energy = false;
+    xlbomd_report last{};
+
+    // Optional live timing of the dense products with HIP events recorded on
+    // the library stream around each launch.
+    struct Prof {
+        bool on = false;
+        std::vector<hipEvent_t> ev;
+        std::vector<double> flops;
+        size_t used = 0;
+    } prof;
+
+    void prof_begin() {
+        if (!prof.on) return;
+        if (prof.used + 2 > prof.ev.size()) {
+            for (int i = 0; i < 256; ++i) {
+                hipEvent_t e;
+                XL_HIP(hipEventCreate(&e));
+                prof.ev.push_back(e);
+            }
+        }
+        XL_HIP(hipEventRecord(prof.ev[prof.used], st));
+    }
+    void prof_end(double flops) {
+        if (!prof.on) return;
+        XL_HIP(hipEventRecord(prof.ev[prof.used + 1], st));
+        prof.flops.push_back(flops);
+        prof.used += 2;
+    }
+    // algorithmic flops of one product on the real n x n block: each output
+    // entry needs 2 n_k flops; a symmetric output has n (n+1)/2 entries
+    double gemm_flops(bool sym, int npairs) const {
+        const double n = N, ent = sym ? 0.5 * n * (n + 1.0) : n * n;
+        return ent * 2.0 * n * npairs;
+    }
+
+    void sync() { XL_HIP(hipStreamSynchronize(st)); }
+
+    void upload_model(const xlbomd_desc *ds) {
+        d = *ds;
+        nat = d.n_atoms;
+        no = d.n_orb;
+        N = nat * no;
+        Np = ((N + GT - 1) / GT) * GT;
+        beta = 1.0 / d.te;
+        zc = d.n_electrons / nat;
+        if (d.stream) {
+            st = (hipStream_t)d.stream;
+        } else {
+            XL_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            own_stream = true;
+        }
+        auto A = [&](auto *&p, size_t n) {
+            using E = std::remove_pointer_t<std::remove_reference_t<decltype(p)>>;
+            p = dalloc<E>(n);
+            mem.ptrs.push_back(p);
+        };
+        A(pos, 3 * nat); A(vel, 3 * nat); A(mass, nat); A(force, 3 * nat);
+        A(onsite, no); A(jit, N); A(hop, no * no); A(U, nat);
+        const int K = d.kmax + 1;
+        A(hist, (size_t)K * nat); A(kr, nat); A(q, nat); A(r, nat); A(ncur, nat);
+        A(vpot, nat); A(glo, N); A(ghi, N); A(g, N); A(epart, 4 * nat);
+        A(scal, 64); A(cvec, 8);
+        mcap = std::max(1, std::min(d.kernel_rank, 16));
+        A(V, (size_t)mcap * nat); A(W, (size_t)mcap * nat); A(Vprev, (size_t)mcap * nat);
+        A(vtmp, nat); A(vin, (size_t)mcap * nat); A(qp, (size_t)mcap * nat); A(hb, (size_t)mcap * nat);
+        A(ub, (size_t)mcap * Np);
+        A(part, (size_t)mcap * ((Np + 63) / 64) * N + 3 * (size_t)N);
+        void *hp = nullptr;
+        XL_HIP(hipHostMalloc(&hp, 64 * sizeof(double), hipHostMallocDefault));
+        hscal = (double *)hp;
+
+        auto up = [&](double *dst, const double *src, size_t n) {
+            XL_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, st));
+        };
+        up(pos, d.pos, 3 * nat);
+        if (d.vel) up(vel, d.vel, 3 * nat);
+        else XL_HIP(hipMemsetAsync(vel, 0, 3 * nat * sizeof(double), st));
+        up(mass, d.mass, nat);
+        up(onsite, d.onsite, no);
+        if (d.onsite_jitter) up(jit, d.onsite_jitter, N);
+        else XL_HIP(hipMemsetAsync(jit, 0, N * sizeof(double), st));
+        up(hop, d.hop_block, no * no);
+        up(U, d.hubbard_u, nat);
+        XL_HIP(hipMemsetAsync(ub, 0, (size_t)mcap * Np * sizeof(double), st));
+        const DampRow &row = kDamp[d.kmax - 5];
+        up(cvec, row.c, row.nc);
+        sync();   // host arrays may be released after the call
+
+        md.nat = nat; md.no = no; md.n = N; md.ld = Np;
+        md.pos = pos; md.onsite = onsite; md.jit = jit; md.hop = hop; md.U = U;
+        md.decay = d.hop_decay; md.rc = d.hop_cutoff; md.width = d.taper_width;
+        md.soft = d.gamma_soft; md.rep_a = d.rep_a; md.rep_decay = d.rep_decay;
+    }
+
+    double *hist_row(int k) {
+        const int K = d.kmax + 1;
+        return hist + (size_t)(((head + k) % K + K) % K) * nat;
+    }
+
+    // ---- precision-dependent parts ----
+    virtual void alloc_matrices(int Lcap) = 0;
+    virtual void foe(double mu0) = 0;       // expansion at mu0 -> Z, Y, g, dmu
+    virtual void finish_density() = 0;      // D_c and charges
+    virtual void responses(int nb, const double *v, double *qout, double *wout) = 0;
+    virtual void forces_parts() = 0;
+    virtual double entropy_ts() = 0;        // Te * S at the corrected state
+    virtual int levels_cap() const = 0;
+
+    // ---- electronic solve at charges n (device, nat) ----
+    void gershgorin() {
+        hipLaunchKernelGGL(gershgorin_kernel, dim3(ceil_div(nat, 4)), dim3(256), 0, st, md,
+                           vpot, glo, ghi);
+        XL_LAUNCH_CHECK();
+        hipLaunchKernelGGL(minmax_kernel, dim3(1), dim3(1024), 0, st, N, glo, ghi, scal + 8);
+        XL_LAUNCH_CHECK();
+    }
+
+    double initial_mu() {
+        // Fermi level of the diagonal of H alone (host bisection on N values)
+        std::vector<double> v(nat), jh(N), on(no);
+        XL_HIP(hipMemcpyAsync(v.data(), vpot, nat * sizeof(double), hipMemcpyDeviceToHost, st));
+        XL_HIP(hipMemcpyAsync(jh.data(), jit, N * sizeof(double), hipMemcpyDeviceToHost, st));
+        XL_HIP(hipMemcpyAsync(on.data(), onsite, no * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        std::vector<double> e(N);
+        for (int i = 0; i < N; ++i) e[i] = on[i % no] + jh[i] + v[i / no];
+        double lo = elo - 1.0, hi = ehi + 1.0;
+        for (int it = 0; it < 200; ++it) {
+            const double m = 0.5 * (lo + hi);
+            double s = 0.0;
+            for (double x : e) s += 2.0 * fermi(beta * (x - m));
+            if (s < d.n_electrons) lo = m; else hi = m;
+        }
+        return 0.5 * (lo + hi);
+    }
+
+    // One-shot electronic solve at n (device pointer, nat).  mu0 < -1e300
+    // requests a fresh guess.
+    void solve(const double *n_dev, double mu_guess, bool have_guess) {
+        if (n_dev != ncur)
+            XL_HIP(hipMemcpyAsync(ncur, n_dev, nat * sizeof(double), hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(gamma_matvec_kernel, dim3(ceil_div((long)nat * 64, 256)), dim3(256),
+                           0, st, md, 1, ncur, vpot);
+        XL_LAUNCH_CHECK();
+        gershgorin();
+        XL_HIP(hipMemcpyAsync(hscal, scal + 8, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        elo = hscal[0];
+        ehi = hscal[1];
+        double mu0 = have_guess ? mu_guess : initial_mu();
+        const double tau = (d.precision == XLBOMD_FP64) ? 1e-5 : 1e-3;
+        reruns = 0;
+        ns_total = 0;
+        for (int it = 0;; ++it) {
+            mu0 = std::min(std::max(mu0, elo), ehi);
+            foe(mu0);
+            XL_HIP(hipMemcpyAsync(hscal, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+            sync();
+            trd = hscal[0];
+            dmu = hscal[2];
+            if (!std::isfinite(dmu)) throw Diverged("non-finite chemical potential step");
+            if (beta * std::fabs(dmu) <= tau) break;
+            if (it >= 60) throw NoConv("chemical potential did not converge");
+            // damped Newton far from the root
+            const double cap = 0.25 * (ehi - elo);
+            mu0 += std::max(-cap, std::min(cap, dmu));
+            ++reruns;
+        }
+        mu = mu0 + dmu;
+        finish_density();
+        XL_HIP(hipMemcpyAsync(hscal, scal + 16, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        rms = std::sqrt(hscal[0] / nat);
+        sumq = hscal[1];
+        if (!std::isfinite(rms)) throw Diverged("non-finite residual");
+    }
+
+    double predict_mu() const {
+        if (mu_known >= 2) return 2.0 * mu_prev - mu_prev2;
+        return mu_prev;
+    }
+    void push_mu() {
+        mu_prev2 = mu_prev;
+        mu_prev = mu;
+        mu_known = std::min(mu_known + 1, 2);
+    }
+
+    // ---- low-rank kernel (Eqs. 48-51) at the last solve, applied to r ----
+    int build_kernel(int m, int mode, bool use_prev) {
+        m = std::min(m, mcap);
+        if (d.kernel_rank <= 0) m = 0;
+        const double gam = d.k0_gamma;
+        int rank = 0;
+        if (m > 0) {
+            // v_1 = K0 r / |K0 r|, K0 = -gamma I
+            hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(1024), 0, st, nat, 0, V, r, -gam, V,
+                               scal + 24);
+            XL_LAUNCH_CHECK();
+            XL_HIP(hipMemcpyAsync(hscal + 24, scal + 24, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+            sync();
+            if (hscal[24 + 1] > 0.0) rank = 1;
+        }
+        if (rank > 0 && mode == 1) {
+            // block mode: v_1 plus the previous build's directions,
+            // orthogonalised in order, all responses in one batch
+            if (use_prev)
+                for (int j = 1; j < m && j - 1 < rank_prev; ++j) {
+                    hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(1024), 0, st, nat, j, V,
+                                       Vprev + (size_t)(j - 1) * nat, 1.0, V + (size_t)j * nat,
+                                       scal + 24);
+                    XL_LAUNCH_CHECK();
+                    XL_HIP(hipMemcpyAsync(hscal + 24, scal + 24, 2 * sizeof(double),
+                                          hipMemcpyDeviceToHost, st));
+                    sync();
+                    if (!(hscal[25] > 1e-10 * hscal[24])) break;
+                    rank = j + 1;
+                }
+            responses(rank, V, qp, W);
+        } else if (rank > 0) {
+            // sequential Krylov: v_{j+1} = orth(w_j)
+            for (int j = 0; j < m; ++j) {
+                responses(1, V + (size_t)j * nat, qp, W + (size_t)j * nat);
+                rank = j + 1;
+                if (j + 1 == m) break;
+                hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(1024), 0, st, nat, j + 1, V,
+                                   W + (size_t)j * nat, 1.0, V + (size_t)(j + 1) * nat,
+                                   scal + 24);
+                XL_LAUNCH_CHECK();
+                XL_HIP(hipMemcpyAsync(hscal + 24, scal + 24, 2 * sizeof(double),
+                                      hipMemcpyDeviceToHost, st));
+                sync();
+                if (!(hscal[25] > 1e-10 * hscal[24])) break;
+            }
+        }
+        rank_built = rank;
+        if (rank > 0) {
+            XL_HIP(hipMemcpyAsync(Vprev, V, (size_t)rank * nat * sizeof(double),
+                                  hipMemcpyDeviceToDevice, st));
+            rank_prev = rank;
+        }
+        return rank;
+    }
+
+    void apply_kernel(const double *rin, double *out) {
+        hipLaunchKernelGGL(kernel_apply_kernel, dim3(1), dim3(1024), 0, st, nat, rank_built, V, W,
+                           rin, d.k0_gamma, out, scal + 32);
+        XL_LAUNCH_CHECK();
+    }
+
+    // ---- energy report at the current state ----
+    void energy(xlbomd_report *rep) {
+        forces_parts();
+        hipLaunchKernelGGL(sum_rows_kernel, dim3(1), dim3(1024), 0, st, nat, 3, epart, scal + 40);
+        XL_LAUNCH_CHECK();
+        hipLaunchKernelGGL(kinetic_kernel, dim3(1), dim3(1024), 0, st, nat, vel, mass, scal + 44);
+        XL_LAUNCH_CHECK();
+        const double ts = entropy_ts();
+        XL_HIP(hipMemcpyAsync(hscal + 40, scal + 40, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        rep->e_band = hscal[40];
+        rep->e_coul = hscal[41];
+        rep->e_rep = hscal[42];
+        rep->te_s = ts;
+        rep->omega = rep->e_band + rep->e_coul + rep->e_rep - ts;
+        rep->e_kin = hscal[44];
+        rep->e_total = rep->omega + rep->e_kin;
+        rep->has_energy = 1;
+    }
+
+    void fill_report(xlbomd_report *rep) {
+        rep->rms_res = rms;
+        rep->mu = mu;
+        rep->d_nelec = sumq;   // sum of net charges = Tr D - N_e
+        rep->step = step_no;
+        rep->foe_levels = L;
+        rep->ns_iters = ns_total;
+        rep->mu_reruns = reruns;
+        rep->scf_iters = scf_iters;
+        rep->kernel_rank = rank_built;
+    }
+
+    // ---- one XL-BOMD step (Eqs. 22-23) ----
+    void md_step(bool want_energy, xlbomd_report *rep) {
+        const double dt = d.dt;
+        const int nthr3 = ceil_div(3 * nat, 256);
+        hipLaunchKernelGGL(kick_drift_kernel, dim3(nthr3), dim3(256), 0, st, nat, 0.5 * dt, dt,
+                           force, mass, vel, pos);
+        XL_LAUNCH_CHECK();
+        const DampRow &row = kDamp[d.kmax - 5];
+        const int K = d.kmax + 1;
+        const int dst = ((head - 1) % K + K) % K;   // oldest slot becomes n(t+dt)
+        hipLaunchKernelGGL(verlet_n_kernel, dim3(ceil_div(nat, 256)), dim3(256), 0, st, nat,
+                           d.kmax, head, dst, row.kappa, row.alpha, cvec, kr, hist);
+        XL_LAUNCH_CHECK();
+        head = dst;
+        solve(hist_row(0), predict_mu(), mu_known > 0);
+        push_mu();
+        forces_parts();
+        ++step_no;
+        if (step_no % std::max(1, d.kernel_every) == 0)
+            build_kernel(d.kernel_rank, d.krylov_mode, true);
+        apply_kernel(r, kr);
+        hipLaunchKernelGGL(kick_drift_kernel, dim3(nthr3), dim3(256), 0, st, nat, 0.5 * dt, 0.0,
+                           force, mass, vel, (double *)nullptr);
+        XL_LAUNCH_CHECK();
+        if (rms > 1e3) throw Diverged("residual above 1e3");
+        have_energy = want_energy;
+        if (want_energy) energy(&last);
+        if (rep) {
+            if (want_energy) *rep = last;
+            else std::memset(rep, 0, sizeof(*rep));
+            fill_report(rep);
+            rep->has_energy = want_energy ? 1 : 0;
+        }
+    }
+
+    // ---- initial state (Eqs. 20, 52) ----
+    void init() {
+        XL_HIP(hipMemsetAsync(ncur, 0, nat * sizeof(double), st));
+        const double tol = d.scf_tol > 0 ? d.scf_tol : 1e-10;
+        const int maxit = d.scf_max_iter > 0 ? d.scf_max_iter : 200;
+        bool have = false;
+        for (scf_iters = 0;; ++scf_iters) {
+            solve(ncur, mu, have);
+            have = true;
+            if (rms <= tol) break;
+            if (scf_iters >= maxit) throw NoConv("initial SCF did not reach the tolerance");
+            // n <- n - K_j (q[n] - n), fresh rank-m kernel each iteration
+            rank_prev = 0;
+            build_kernel(d.kernel_rank, 0, false);
+            apply_kernel(r, vtmp);
+            hipLaunchKernelGGL(axpy_kernel, dim3(ceil_div(nat, 256)), dim3(256), 0, st, nat, -1.0,
+                               vtmp, ncur);
+            XL_LAUNCH_CHECK();
+        }
+        const int K = d.kmax + 1;
+        for (int k = 0; k < K; ++k)
+            XL_HIP(hipMemcpyAsync(hist + (size_t)k * nat, ncur, nat * sizeof(double),
+                                  hipMemcpyDeviceToDevice, st));
+        head = 0;
+        mu_known = 0;
+        push_mu();
+        forces_parts();
+        rank_prev = 0;
+        build_kernel(d.kernel_rank, d.krylov_mode, false);
+        apply_kernel(r, kr);
+        step_no = 0;
+        sync();
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Precision-dependent dense algebra
+// ---------------------------------------------------------------------------
+template <typename T> struct Sys : SysBase {
+    std::vector<T *> Z, Yk;       // Z_0..Z_L, Y_0..Y_{L-1}
+    T *Ys = nullptr, *Y2 = nullptr, *Am = nullptr, *E = nullptr, *Wk = nullptr;
+    T *Dc = nullptr;
+    T *Zp = nullptr, *Ap = nullptr, *Tb = nullptr;   // response batch buffers
+    double *e64[8] = {};                             // FP64 energy workspace
+    int Lcap = 0;
+
+    size_t mat() const { return (size_t)Np * Np; }
+    T *amat() {
+        T *p = dalloc<T>(mat());
+        mem.ptrs.push_back(p);
+        return p;
+    }
+    int levels_cap() const override { return Lcap; }
+
+    void alloc_matrices(int cap) override {
+        if (cap <= Lcap) return;
+        while ((int)Z.size() < cap + 1) Z.push_back(amat());
+        while ((int)Yk.size() < cap) Yk.push_back(amat());
+        if (!Ys) {
+            Ys = amat(); Y2 = amat(); Am = amat(); E = amat(); Wk = amat(); Dc = amat();
+        }
+        Lcap = cap;
+    }
+    void alloc_resp(int nb) {
+        if (nb <= bcap) return;
+        // one allocation each for the whole batch
+        T *zp = dalloc<T>(mat() * nb), *ap = dalloc<T>(mat() * nb), *tb = dalloc<T>(mat() * nb);
+        mem.ptrs.push_back(zp); mem.ptrs.push_back(ap); mem.ptrs.push_back(tb);
+        Zp = zp; Ap = ap; Tb = tb;
+        bcap = nb;
+    }
+
+    template <typename U> void run_gemm(const GemmArgs<U> &a, bool sym) {
+        prof_begin();
+        gemm(a, sym, st);
+        prof_end(gemm_flops(sym, a.A1 ? 2 : 1) * a.batch);
+    }
+
+    GemmArgs<T> base() const {
+        GemmArgs<T> a;
+        a.n = Np;
+        a.ld = Np;
+        return a;
+    }
+
+    void foe(double mu0) override {
+        const double xmax = beta * std::max(std::fabs(elo - mu0), std::fabs(ehi - mu0)) * 1.02 + 1e-12;
+        const double tol = 2e-10;
+        L = choose_levels(xmax, tol);
+        alloc_matrices(L);
+        sc = std::ldexp(beta, -(L + 1));
+        // Y = sc (H - mu0 I)
+        hipLaunchKernelGGL((build_seed_kernel<T>), dim3(ceil_div(Np, 256), Np), dim3(256), 0, st,
+                           md, vpot, mu0, sc, Ys);
+        XL_LAUNCH_CHECK();
+        const double ymax = std::ldexp(xmax, -(L + 1));
+        t0max = ymax - ymax * ymax * ymax / 3.0;
+        {   // Y2 = Y Y ; Z0 = Y/2 - Y Y2 / 6
+            GemmArgs<T> a = base();
+            a.A0 = Ys; a.B0 = Ys; a.C = Y2;
+            run_gemm(a, true);
+            a = base();
+            a.A0 = Ys; a.B0 = Y2; a.X = Ys; a.alpha = (T)(-1.0 / 6.0); a.beta = (T)0.5;
+            a.C = Z[0];
+            run_gemm(a, true);
+        }
+        const double nstol = (sizeof(T) == 8) ? 2e-16 : 1e-8;
+        double t = t0max;
+        for (int k = 0; k < L; ++k) {
+            const double b = t * t;            // spectrum of A_k within [1, 1 + b]
+            const double c = 2.0 + b, den = 2.0 * c * c - b * b;
+            const double al = 8.0 * c / den, ga = -8.0 / den;
+            double e = b * b / den;
+            int ns = 0;
+            while (e > nstol && ns < 8) { e = e * e; ++ns; }
+            ns_total += ns;
+            GemmArgs<T> a = base();
+            a.A0 = Z[k]; a.B0 = Z[k]; a.alpha = (T)4.0; a.gamma = (T)1.0; a.C = Am;
+            a.C2 = Yk[k]; a.p0 = (T)al; a.p1 = (T)ga;
+            run_gemm(a, true);
+            for (int j = 0; j < ns; ++j) {
+                GemmArgs<T> e1 = base();   // E = 2I - A Y
+                e1.A0 = Am; e1.B0 = Yk[k]; e1.alpha = (T)-1.0; e1.gamma = (T)2.0; e1.C = E;
+                run_gemm(e1, true);
+                GemmArgs<T> e2 = base();   // Y <- Y E
+                e2.A0 = Yk[k]; e2.B0 = E; e2.C = Wk;
+                run_gemm(e2, true);
+                std::swap(Yk[k], Wk);
+            }
+            GemmArgs<T> z = base();        // Z_{k+1} = 2 Y_k Z_k
+            z.A0 = Yk[k]; z.B0 = Z[k]; z.alpha = (T)2.0; z.C = Z[k + 1];
+            run_gemm(z, true);
+            t = 2.0 * t / (1.0 + t * t);
+        }
+        hipLaunchKernelGGL((row_sqnorm_kernel<T>), dim3(ceil_div((long)N * 64, 256)), dim3(256), 0,
+                           st, N, Np, Z[L], g);
+        XL_LAUNCH_CHECK();
+        hipLaunchKernelGGL((mu_newton_kernel<T>), dim3(1), dim3(1024), 0, st, N, Np, Z[L], g, beta,
+                           d.n_electrons, g, scal);
+        XL_LAUNCH_CHECK();
+    }
+
+    void finish_density() override {
+        // D_c = I - 2 Z + dmu (beta/2)(I - 4 Z^2)
+        GemmArgs<T> a = base();
+        a.A0 = Z[L]; a.B0 = Z[L]; a.alpha = (T)(-2.0 * dmu * beta);
+        a.X = Z[L]; a.beta = (T)-2.0; a.gamma = (T)(1.0 + 0.5 * dmu * beta); a.C = Dc;
+        run_gemm(a, true);
+        hipLaunchKernelGGL((charges_kernel<T>), dim3(1), dim3(1024), 0, st, nat, no, Np, Dc, zc,
+                           ncur, q, r, scal + 16);
+        XL_LAUNCH_CHECK();
+    }
+
+    void forces_parts() override {
+        hipLaunchKernelGGL((forces_kernel<T>), dim3(ceil_div((long)nat * 64, 256)), dim3(256), 0,
+                           st, md, Dc, q, ncur, vpot, force, epart);
+        XL_LAUNCH_CHECK();
+    }
+
+    void responses(int nb, const double *v, double *qout, double *wout) override {
+        if (nb <= 0) return;
+        alloc_resp(nb);
+        const long sm = (long)mat();
+        // h = Gamma v, u = sc * h per orbital
+        hipLaunchKernelGGL(gamma_matvec_kernel, dim3(ceil_div((long)nat * nb * 64, 256)),
+                           dim3(256), 0, st, md, nb, v, hb);
+        XL_LAUNCH_CHECK();
+        hipLaunchKernelGGL(expand_orbital_kernel, dim3(ceil_div((long)N * nb, 256)), dim3(256), 0,
+                           st, nat, no, nb, sc, hb, (long)Np, ub);
+        XL_LAUNCH_CHECK();
+        {   // G = Y diag(u) Y, then Z'_0
+            GemmArgs<T> a = base();
+            a.batch = nb; a.A0 = Ys; a.B0 = Ys; a.kscale = ub; a.sK = Np;
+            a.C = Tb; a.sC = sm;
+            run_gemm(a, true);
+            hipLaunchKernelGGL((seed_resp_kernel<T>), dim3(ceil_div(Np, 256), Np, nb), dim3(256),
+                               0, st, N, Np, Tb, Y2, ub, (long)Np, sm, Zp);
+            XL_LAUNCH_CHECK();
+        }
+        for (int k = 0; k < L; ++k) {
+            GemmArgs<T> a = base();        // A' = 4 (Z Z' + Z' Z)
+            a.batch = nb;
+            a.A0 = Z[k]; a.B0 = Zp; a.sB0 = sm; a.A1 = Zp; a.sA1 = sm; a.B1 = Z[k];
+            a.alpha = (T)4.0; a.C = Ap; a.sC = sm;
+            run_gemm(a, true);
+            GemmArgs<T> b = base();        // T = 2 Z' - A' Z_{k+1}
+            b.batch = nb;
+            b.A0 = Ap; b.sA0 = sm; b.B0 = Z[k + 1]; b.alpha = (T)-1.0;
+            b.X = Zp; b.sX = sm; b.beta = (T)2.0; b.C = Tb; b.sC = sm;
+            run_gemm(b, false);
+            if (k + 1 < L) {
+                GemmArgs<T> c = base();    // Z'_{k+1} = Y_k T
+                c.batch = nb;
+                c.A0 = Yk[k]; c.B0 = Tb; c.sB0 = sm; c.C = Zp; c.sC = sm;
+                run_gemm(c, true);
+            }
+        }
+        const int nchunk = (N + 63) / 64;
+        const long sP = (long)nchunk * N;
+        hipLaunchKernelGGL((coldot_kernel<T>), dim3(ceil_div(N, 256), nchunk, nb), dim3(256), 0, st,
+                           N, Np, Yk[L - 1], Tb, sm, part, sP);
+        XL_LAUNCH_CHECK();
+        hipLaunchKernelGGL(resp_charges_kernel, dim3(nb), dim3(1024), 0, st, nat, no, nchunk, part,
+                           sP, g, v, qout, wout);
+        XL_LAUNCH_CHECK();
+    }
+
+    // ---- entropy without eigenvalues ----
+    // With F = 1/2 I - Z_L the occupations and X_eff = 2^(L+1) atanh(2 Z_0)
+    // the argument the expansion actually applies:
+    //   S/2 = -ln det(1/2 I + Z_L) + <F, X_eff>
+    //   ln det(1/2 I + Z_L) = 2^L ln det(1/2 I + Z_0)
+    //                       + sum_k 2^(L-1-k) (N ln 2 - ln det A_k)
+    // (from 1/2 + z_{k+1} = 2 (1/2 + z_k)^2 / (1 + 4 z_k^2)), and the mu
+    // correction adds dmu <X_eff, (1/2)(I - 4 Z_L^2)>.
+    double *w64(int i) {
+        if (!e64[i]) {
+            e64[i] = dalloc<double>(mat());
+            mem.ptrs.push_back(e64[i]);
+        }
+        return e64[i];
+    }
+    const double *as64(const T *src, int slot, double scale) {
+        double *dst = w64(slot);
+        hipLaunchKernelGGL((convert_kernel<T>), dim3(ceil_div((long)mat(), 256)), dim3(256), 0, st,
+                           (long)mat(), src, scale, dst);
+        XL_LAUNCH_CHECK();
+        return dst;
+    }
+
+    double logdet_shift(double *A) {   // ln det of the leading block, A destroyed
+        const int n32 = ((N + CB - 1) / CB) * CB;
+        chol_logdet(n32, Np, A, scal + 48, st);
+        XL_HIP(hipMemcpyAsync(hscal + 48, scal + 48, sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        return hscal[48];
+    }
+
+    double entropy_ts() override {
+        GemmArgs<double> a;
+        a.n = Np; a.ld = Np;
+        // T0 = 2 Z_0
+        const double *T0 = as64(Z[0], 0, 2.0);
+        // l0 = ln det(I + T0)
+        double *C = w64(1);
+        hipLaunchKernelGGL(add_diag_copy_kernel, dim3(ceil_div((long)mat(), 256)), dim3(256), 0, st,
+                           Np, N, T0, 1.0, C);
+        XL_LAUNCH_CHECK();
+        const double l0 = logdet_shift(C);
+        const double ln2 = std::log(2.0);
+        double lnF = std::ldexp(-N * ln2 + l0, L);
+        for (int k = 0; k < L; ++k) {
+            const double *Zk = as64(Z[k], 2, 1.0);
+            GemmArgs<double> b = a;
+            b.A0 = Zk; b.B0 = Zk; b.alpha = 4.0; b.gamma = 1.0; b.C = C;
+            gemm(b, true, st);
+            const double lk = logdet_shift(C);
+            lnF += std::ldexp(N * ln2 - lk, L - 1 - k);
+        }
+        // series of atanh(T0): P_j = T0^(2j+1)
+        const double *ZL = as64(Z[L], 2, 1.0);
+        double *ZL2 = w64(3), *T0sq = w64(4), *P = w64(5), *Pn = w64(6);
+        {
+            GemmArgs<double> b = a;
+            b.A0 = ZL; b.B0 = ZL; b.C = ZL2;
+            gemm(b, true, st);
+            b = a;
+            b.A0 = T0; b.B0 = T0; b.C = T0sq;
+            gemm(b, true, st);
+        }
+        XL_HIP(hipMemcpyAsync(P, T0, mat() * sizeof(double), hipMemcpyDeviceToDevice, st));
+        const double tmax = 2.0 * 0.5 * t0max;   // |2 z_0| <= t0max
+        double s1 = 0.0, s2 = 0.0;
+        const double scale = std::ldexp(1.0, L + 1);
+        for (int j = 0; j < 64; ++j) {
+            const double cj = scale / (2 * j + 1);
+            hipLaunchKernelGGL(frob3_kernel, dim3(N), dim3(256), 0, st, N, Np, P, ZL, ZL2, part);
+            XL_LAUNCH_CHECK();
+            hipLaunchKernelGGL(sum_rows_kernel, dim3(1), dim3(1024), 0, st, N, 3, part, scal + 52);
+            XL_LAUNCH_CHECK();
+            XL_HIP(hipMemcpyAsync(hscal + 52, scal + 52, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+            sync();
+            const double trP = hscal[52], zp = hscal[53], z2p = hscal[54];
+            s1 += cj * (0.5 * trP - zp);          // <1/2 I - Z_L, P>
+            s2 += cj * (trP - 4.0 * z2p);         // <P, I - 4 Z_L^2>
+            if (std::pow(tmax, 2 * j + 3) * scale / (2 * j + 3) * N < 1e-14) break;
+            GemmArgs<double> b = a;
+            b.A0 = T0sq; b.B0 = P; b.C = Pn;
+            gemm(b, true, st);
+            std::swap(P, Pn);
+            e64[5] = P; e64[6] = Pn;
+        }
+        const double S0 = 2.0 * (-lnF + s1);
+        return S0 / beta + dmu * 0.5 * s2;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+struct xlbomd_system {
+    std::unique_ptr<SysBase> s;
+};
+
+namespace {
+
+int fail(int code, const std::string &m) {
+    g_err = m;
+    return code;
+}
+
+template <typename F> int guarded(F &&f) {
+    try {
+        g_err.clear();
+        f();
+        return XLBOMD_OK;
+    } catch (const InvalidArg &e) {
+        return fail(XLBOMD_E_INVALID, e.what());
+    } catch (const NoMem &e) {
+        return fail(XLBOMD_E_NOMEM, e.what());
+    } catch (const NoConv &e) {
+        return fail(XLBOMD_E_NOCONV, e.what());
+    } catch (const Diverged &e) {
+        return fail(XLBOMD_E_DIVERGED, e.what());
+    } catch (const HipError &e) {
+        return fail(XLBOMD_E_HIP, e.what());
+    } catch (const std::exception &e) {
+        return fail(XLBOMD_E_STATE, e.what());
+    } catch (...) {
+        return fail(XLBOMD_E_STATE, "unknown error");
+    }
+}
+
+void validate(const xlbomd_desc *d) {
+    if (!d) throw InvalidArg("null descriptor");
+    if (d->n_atoms <= 0 || d->n_orb <= 0 || d->n_orb > 8)
+        throw InvalidArg("n_atoms must be > 0 and n_orb in 1..8");
+    if (!d->pos || !d->mass || !d->onsite || !d->hop_block || !d->hubbard_u)
+        throw InvalidArg("pos, mass, onsite, hop_block and hubbard_u are required");
+    const double n2 = 2.0 * d->n_atoms * d->n_orb;
+    if (!(d->n_electrons > 0.0 && d->n_electrons < n2))
+        throw InvalidArg("n_electrons must lie in (0, 2 n_atoms n_orb)");
+    if (!(d->te > 0.0) || !(d->dt > 0.0)) throw InvalidArg("te and dt must be > 0");
+    if (d->kmax < 5 || d->kmax > 7) throw InvalidArg("kmax must be 5, 6 or 7");
+    if (d->kernel_rank < 0 || d->kernel_rank > d->n_atoms || d->kernel_rank > 16)
+        throw InvalidArg("kernel_rank must be in 0..min(n_atoms, 16)");
+    if (d->kernel_every < 1) throw InvalidArg("kernel_every must be >= 1");
+    if (d->krylov_mode != 0 && d->krylov_mode != 1) throw InvalidArg("krylov_mode is 0 or 1");
+    if (!(d->k0_gamma > 0.0 && d->k0_gamma <= 1.0)) throw InvalidArg("k0_gamma must be in (0, 1]");
+    if (d->precision != XLBOMD_FP64 && d->precision != XLBOMD_FP32)
+        throw InvalidArg("precision must be XLBOMD_FP64 or XLBOMD_FP32");
+    if (!(d->hop_decay > 0.0) || !(d->hop_cutoff > 0.0) || d->taper_width < 0.0 ||
+        !(d->gamma_soft > 0.0) || (d->rep_a != 0.0 && !(d->rep_decay > 0.0)))
+        throw InvalidArg("model lengths must be positive");
+    for (int i = 0; i < d->n_atoms; ++i)
+        if (!(d->mass[i] > 0.0)) throw InvalidArg("masses must be positive");
+}
+
+}  // namespace
+
+extern "C" {
+
+int xlbomd_init_system(const xlbomd_desc *desc, xlbomd_system **out) {
+    if (!out) return fail(XLBOMD_E_INVALID, "null output handle");
+    *out = nullptr;
+    std::unique_ptr<xlbomd_system> h(new xlbomd_system);
+    const int rc = guarded([&] {
+        validate(desc);
+        if (desc->precision == XLBOMD_FP64) h->s.reset(new Sys<double>());
+        else h->s.reset(new Sys<float>());
+        h->s->upload_model(desc);
+        h->s->init();
+    });
+    if (rc == XLBOMD_OK) *out = h.release();
+    return rc;
+}
+
+int xlbomd_step(xlbomd_system *h, int32_t n_steps, xlbomd_report *last) {
+    if (!h || !h->s) return fail(XLBOMD_E_INVALID, "null handle");
+    if (n_steps < 0) return fail(XLBOMD_E_INVALID, "n_steps < 0");
+    return guarded([&] {
+        SysBase &s = *h->s;
+        for (int i = 0; i < n_steps; ++i) {
+            const int ev = s.d.energy_every;
+            const bool is_last = (i + 1 == n_steps);
+            const bool want = (ev > 0 && ((s.step_no + 1) % ev == 0)) || (is_last && last);
+            s.md_step(want, is_last ? last : nullptr);
+        }
+        s.sync();
+    });
+}
+
+int xlbomd_kernel_update(xlbomd_system *h, int32_t rank) {
+    if (!h || !h->s) return fail(XLBOMD_E_INVALID, "null handle");
+    return guarded([&] {
+        SysBase &s = *h->s;
+        const int m = rank > 0 ? rank : s.d.kernel_rank;
+        if (m > s.mcap) throw InvalidArg("rank above the descriptor's kernel_rank");
+        s.build_kernel(m, s.d.krylov_mode, true);
+        s.apply_kernel(s.r, s.kr);
+        s.sync();
+    });
+}
+
+int xlbomd_forces(xlbomd_system *h, double *forces, xlbomd_report *energy) {
+    if (!h || !h->s) return fail(XLBOMD_E_INVALID, "null handle");
+    return guarded([&] {
+        SysBase &s = *h->s;
+        if (energy) {
+            s.energy(energy);
+            s.fill_report(energy);
+        }
+        if (forces)
+            XL_HIP(hipMemcpyAsync(forces, s.force, 3 * s.nat * sizeof(double),
+                                  hipMemcpyDeviceToHost, s.st));
+        s.sync();
+    });
+}
+
+int xlbomd_get_charges(xlbomd_system *h, double *n_out, double *q_out) {
+    if (!h || !h->s) return fail(XLBOMD_E_INVALID, "null handle");
+    return guarded([&] {
+        SysBase &s = *h->s;
+        if (n_out)
+            XL_HIP(hipMemcpyAsync(n_out, s.hist_row(0), s.nat * sizeof(double),
+                                  hipMemcpyDeviceToHost, s.st));
+        if (q_out)
+            XL_HIP(hipMemcpyAsync(q_out, s.q, s.nat * sizeof(double), hipMemcpyDeviceToHost, s.st));
+        s.sync();
+    });
+}
+
+int xlbomd_set_state(xlbomd_system *h, const double *pos, const double *vel,
+                     const double *n_hist, const double *kr) {
+    if (!h || !h->s) return fail(XLBOMD_E_INVALID, "null handle");
+    return guarded([&] {
+        SysBase &s = *h->s;
+        const size_t b3 = 3 * s.nat * sizeof(double), b1 = s.nat * sizeof(double);
+        if (pos) XL_HIP(hipMemcpyAsync(s.pos, pos, b3, hipMemcpyHostToDevice, s.st));
+        if (vel) XL_HIP(hipMemcpyAsync(s.vel, vel, b3, hipMemcpyHostToDevice, s.st));
+        if (n_hist) {
+            const int K = s.d.kmax + 1;
+            for (int k = 0; k < K; ++k)
+                XL_HIP(hipMemcpyAsync(s.hist + (size_t)k * s.nat, n_hist + (size_t)k * s.nat, b1,
+                                      hipMemcpyHostToDevice, s.st));
+            s.head = 0;
+        }
+        s.sync();
+        s.mu_known = 0;
+        s.solve(s.hist_row(0), 0.0, false);
+        s.push_mu();
+        s.forces_parts();
+        s.rank_prev = 0;
+        if (kr) {
+            XL_HIP(hipMemcpyAsync(s.kr, kr, b1, hipMemcpyHostToDevice, s.st));
+        } else {
+            s.build_kernel(s.d.kernel_rank, s.d.krylov_mode, false);
+            s.apply_kernel(s.r, s.kr);
+        }
+        s.sync();
+    });
+}
+
+int xlbomd_get_state(xlbomd_system *h, double *pos, double *vel, double *n_hist,
+                     double *kr) {
+    if (!h || !h->s) return fail(XLBOMD_E_INVALID, "null handle");
+    return guarded([&] {
+        SysBase &s = *h->s;
+        const size_t b3 = 3 * s.nat * sizeof(double), b1 = s.nat * sizeof(double);
+        if (pos) XL_HIP(hipMemcpyAsync(pos, s.pos, b3, hipMemcpyDeviceToHost, s.st));
+        if (vel) XL_HIP(hipMemcpyAsync(vel, s.vel, b3, hipMemcpyDeviceToHost, s.st));
+        if (n_hist)
+            for (int k = 0; k <= s.d.kmax; ++k)
+                XL_HIP(hipMemcpyAsync(n_hist + (size_t)k * s.nat, s.hist_row(k), b1,
+                                      hipMemcpyDeviceToHost, s.st));
+        if (kr) XL_HIP(hipMemcpyAsync(kr, s.kr, b1, hipMemcpyDeviceToHost, s.st));
+        s.sync();
+    });
+}
+
+int xlbomd_solve(xlbomd_system *h, const double *n, double *q_out, xlbomd_report *rep) {
+    if (!h || !h->s || !n) return fail(XLBOMD_E_INVALID, "null argument");
+    return guarded([&] {
+        SysBase &s = *h->s;
+        XL_HIP(hipMemcpyAsync(s.vtmp, n, s.nat * sizeof(double), hipMemcpyHostToDevice, s.st));
+        s.solve(s.vtmp, s.mu, s.mu_known > 0);
+        if (q_out)
+            XL_HIP(hipMemcpyAsync(q_out, s.q, s.nat * sizeof(double), hipMemcpyDeviceToHost, s.st));
+        if (rep) {
+            std::memset(rep, 0, sizeof(*rep));
+            s.fill_report(rep);
+        }
+        s.sync();
+    });
+}
+
+int xlbomd_response(xlbomd_system *h, int32_t count, const double *v, double *dq_out) {
+    if (!h || !h->s || !v || !dq_out) return fail(XLBOMD_E_INVALID, "null argument");
+    return guarded([&] {
+        SysBase &s = *h->s;
+        if (count < 1 || count > s.mcap) throw InvalidArg("count must be in 1..kernel capacity");
+        XL_HIP(hipMemcpyAsync(s.vin, v, (size_t)count * s.nat * sizeof(double),
+                              hipMemcpyHostToDevice, s.st));
+        s.responses(count, s.vin, s.qp, nullptr);
+        XL_HIP(hipMemcpyAsync(dq_out, s.qp, (size_t)count * s.nat * sizeof(double),
+                              hipMemcpyDeviceToHost, s.st));
+        s.sync();
+    });
+}
+
+int xlbomd_kernel_apply(xlbomd_system *h, int32_t rank, const double *rr, double *kr_out) {
+    if (!h || !h->s || !rr || !kr_out) return fail(XLBOMD_E_INVALID, "null argument");
+    return guarded([&] {
+        SysBase &s = *h->s;
+        if (rank < 0 || rank > s.mcap) throw InvalidArg("rank above capacity");
+        XL_HIP(hipMemcpyAsync(s.r, rr, s.nat * sizeof(double), hipMemcpyHostToDevice, s.st));
+        s.rank_prev = 0;
+        s.build_kernel(rank, 0, false);
+        s.apply_kernel(s.r, s.vtmp);
+        XL_HIP(hipMemcpyAsync(kr_out, s.vtmp, s.nat * sizeof(double), hipMemcpyDeviceToHost, s.st));
+        s.sync();
+    });
+}
+
+int xlbomd_profile(xlbomd_system *h, int32_t enable, double *out) {
+    if (!h || !h->s) return fail(XLBOMD_E_INVALID, "null handle");
+    return guarded([&] {
+        SysBase &s = *h->s;
+        if (enable) {
+            s.sync();
+            s.prof.on = true;
+            s.prof.used = 0;
+            s.prof.flops.clear();
+            return;
+        }
+        s.sync();
+        double ms = 0.0, fl = 0.0, mx = 0.0, mn = 1e300;
+        const size_t n = s.prof.used / 2;
+        for (size_t i = 0; i < n; ++i) {
+            float e = 0.0f;
+            XL_HIP(hipEventElapsedTime(&e, s.prof.ev[2 * i], s.prof.ev[2 * i + 1]));
+            ms += e;
+            fl += s.prof.flops[i];
+            mx = std::max(mx, (double)e);
+            mn = std::min(mn, (double)e);
+        }
+        s.prof.on = false;
+        if (out) {
+            out[0] = ms;
+            out[1] = fl;
+            out[2] = (double)n;
+            out[3] = n ? mn : 0.0;
+            out[4] = mx;
+        }
+    });
+}
+
+void xlbomd_destroy(xlbomd_system *h) {
+    if (!h) return;
+    if (h->s) {
+        (void)hipStreamSynchronize(h->s->st);
+        if (h->s->hscal) (void)hipHostFree(h->s->hscal);
+        for (hipEvent_t e : h->s->prof.ev) (void)hipEventDestroy(e);
+        if (h->s->own_stream) (void)hipStreamDestroy(h->s->st);
+    }
+    delete h;
+}
+
+const char *xlbomd_last_error(void) { return g_err.c_str(); }
+
+const char *xlbomd_version(void) { return "xlbomd-gfx950 0.1"; }
+
+}  // extern "C"
