@@ -2,9 +2,11 @@
 
 Workload: 1024 atoms x 4 orbitals (s + 3p) on a jittered 8x8x16 cubic
 lattice, Te = 0.05, rank-4 sequential-Krylov kernel rebuilt every step,
-Table I K_max = 5 integrator.  `value` is the mixed path (dense products in
-FP32 MFMA; chemical potential, Krylov solve, Verlet and energy sums in FP64);
-the FP64-plain path is timed the same way and reported beside it.
+Table I K_max = 5 integrator.  `value` is the mixed path: the density-matrix
+expansion in FP64 MFMA (it fixes charges, forces and energy, which then meet
+the FP64 tolerances) and the kernel's response products in FP32 MFMA; the
+chemical potential, Krylov solve, Verlet and energy sums are FP64.  The
+FP64-plain path and the all-FP32 path are timed the same way beside it.
 
 Prints one JSON line.  The oracle (test infrastructure) is used only for the
 CPU baseline leg.
@@ -44,7 +46,7 @@ def time_path(system, precision, steps, warmup, label):
     from paper_1705_10845_amd import XLBOMD
     t0 = time.perf_counter()
     g = XLBOMD(system, precision=precision, stream=_stream(),
-               scf_tol=1e-7 if precision == 1 else 1e-9)
+               scf_tol=1e-6 if precision == 1 else 1e-9)
     t_init = time.perf_counter() - t0
     print(f"[bench] {label}: init (SCF) {t_init:.1f}s", file=sys.stderr, flush=True)
     if warmup:
@@ -99,6 +101,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -108,16 +111,35 @@ def main():
         sys.exit(2)
 
     from synth import make_system
-    from paper_1705_10845_amd import FP32, FP64
+    from paper_1705_10845_amd import FP32, FP64, MIXED
     s = make_system("c2")
 
-    mixed = time_path(s, FP32, args.steps, args.warmup, "fp32")
-    fp64 = None
-    if not args.no_fp64:
-        fp64 = time_path(s, FP64, args.fp64_steps, 1, "fp64")
+    mixed = time_path(s, MIXED, args.steps, args.warmup, "mixed")
+    fp64 = None if args.no_fp64 else time_path(s, FP64, args.fp64_steps, 1, "fp64")
+    fp32 = None if args.no_fp32 else time_path(s, FP32, args.steps, 1, "fp32")
 
-    p = mixed["prof"]
-    achieved = p["flops"] / (p["ms"] * 1e-3) / 1e12 if p["ms"] > 0 else 0.0
+    def roof(prof, steps):
+        # the dominant product class of the step (the most kernel time)
+        key = max(("f64", "f32"), key=lambda k: prof[k]["ms"])
+        p = prof[key]
+        ach = p["flops"] / (p["ms"] * 1e-3) / 1e12 if p["ms"] > 0 else 0.0
+        return {"bound": "mfma", "achieved": ach, "peak": PEAK[key], "unit": "TFLOP/s",
+                "frac": ach / PEAK[key], "traffic": None,
+                "kernel": f"gemm_tn_kernel<{'double' if key == 'f64' else 'float'}>",
+                "launches": p["launches"], "avg_launch_ms": p["ms"] / max(1, p["launches"]),
+                "gemm_ms_per_step": p["ms"] / steps,
+                "other_class_ms_per_step": prof["f32" if key == "f64" else "f64"]["ms"] / steps}
+
+    def summary(r, steps):
+        out = {"value": r["steps_per_s"], "ms_per_step": r["ms_per_step"], "steps": steps,
+               "foe_levels": r["report"]["foe_levels"], "mu_reruns_last": r["report"]["mu_reruns"]}
+        for k in ("f64", "f32"):
+            p = r["prof"][k]
+            if p["ms"] > 0:
+                out[f"mfma_{k}_tflops"] = p["flops"] / (p["ms"] * 1e-3) / 1e12
+                out[f"gemm_{k}_ms_per_step"] = p["ms"] / steps
+        return out
+
     out = {
         "metric": "MD steps/s at N=4096 (mixed vs FP64 plain), % MFMA peak, p99 step latency",
         "value": mixed["steps_per_s"],
@@ -129,26 +151,23 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64+f32",
         "data": "synthetic",
         "config": {"workload": "c2: 1024 atoms x 4 orbitals (N=4096) jittered cubic "
                                "lattice, Te=0.05, rank-4 sequential Krylov kernel every "
-                               "step, K_max=5; dense products FP32 MFMA, mu/Krylov/"
-                               "Verlet/energy sums FP64",
-                   "n_orbitals": 4096, "kernel_rank": 4, "foe_levels":
-                       mixed["report"]["foe_levels"]},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["f32"],
-                     "unit": "TFLOP/s", "frac": achieved / PEAK["f32"], "traffic": None,
-                     "kernel": "gemm_tn_kernel<float> (all dense products of a step)",
-                     "launches": p["launches"], "gemm_ms_per_step": p["ms"] / args.steps},
+                               "step, K_max=5; mixed path: FP64 MFMA density-matrix "
+                               "expansion, FP32 MFMA kernel responses, FP64 mu/Krylov/"
+                               "Verlet/energy sums",
+                   "n_orbitals": 4096, "kernel_rank": 4,
+                   "foe_levels": mixed["report"]["foe_levels"]},
+        "roofline": roof(mixed["prof"], args.steps),
+        "mixed": summary(mixed, args.steps),
     }
     if fp64 is not None:
-        q = fp64["prof"]
-        a64 = q["flops"] / (q["ms"] * 1e-3) / 1e12 if q["ms"] > 0 else 0.0
-        out["fp64_plain"] = {"value": fp64["steps_per_s"], "ms_per_step": fp64["ms_per_step"],
-                             "steps": args.fp64_steps, "mfma_tflops": a64,
-                             "mfma_frac": a64 / PEAK["f64"]}
+        out["fp64_plain"] = summary(fp64, args.fp64_steps)
         out["mixed_over_fp64"] = mixed["steps_per_s"] / fp64["steps_per_s"]
+    if fp32 is not None:
+        out["fp32"] = summary(fp32, args.steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

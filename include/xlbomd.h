@@ -57,8 +57,11 @@ typedef enum {
 
 typedef enum {
     XLBOMD_FP64 = 0,         /* every dense product in FP64 (FP64 MFMA)   */
-    XLBOMD_FP32 = 1          /* dense products in FP32 MFMA; mu, kernel
+    XLBOMD_FP32 = 1,         /* dense products in FP32 MFMA; mu, kernel
                                 solve, Verlet and energy sums in FP64     */
+    XLBOMD_MIXED = 2         /* density-matrix expansion in FP64 MFMA (it
+                                fixes charges, forces, energy); the
+                                kernel's response products in FP32 MFMA   */
 } xlbomd_precision;
 
 /* System descriptor.  Model (orthogonal SCC tight binding):
@@ -122,6 +125,15 @@ int xlbomd_init_system(const xlbomd_desc *desc, xlbomd_system **out);
  * above 1e3 appears; the state is then the last good step. */
 int xlbomd_step(xlbomd_system *h, int32_t n_steps, xlbomd_report *last);
 
+/* Advance n_steps steps of `count` independent systems concurrently: each
+ * handle is stepped by its own host thread on its own stream, so the device
+ * overlaps their kernels.  Handles must be distinct and must not share a
+ * stream (shared streams serialise).  reports (count entries) and status
+ * (count entries) are optional.  Returns the first failing status, with the
+ * system index in xlbomd_last_error(); the other systems still advance. */
+int xlbomd_step_batch(xlbomd_system *const *hs, int32_t count, int32_t n_steps,
+                      xlbomd_report *reports, int32_t *status);
+
 /* Rebuild the low-rank kernel at the current state with rank `rank`
  * (<= 0 keeps the descriptor's rank) and refresh K r (Eqs. 50-51). */
 int xlbomd_kernel_update(xlbomd_system *h, int32_t rank);
@@ -164,11 +176,11 @@ int xlbomd_kernel_apply(xlbomd_system *h, int32_t rank, const double *r,
 
 /* Live timing of the dense MFMA products.  enable != 0 starts recording a
  * HIP event pair on the handle's stream around every product launched by
- * later calls; enable == 0 stops and, if out != NULL, writes
- *   out[0] total kernel milliseconds, out[1] total algorithmic flops (each
- *   output entry 2 n_k flops on the real n x n block; symmetric outputs count
- *   n(n+1)/2 entries), out[2] number of launches, out[3] shortest and
- *   out[4] longest launch in ms. */
+ * later calls; enable == 0 stops and, if out != NULL, writes 10 doubles:
+ * out[0..4] for FP64 products and out[5..9] for FP32 products, each
+ *   {total kernel milliseconds, total algorithmic flops (2 n_k flops per
+ *    output entry on the real n x n block; symmetric outputs count n(n+1)/2
+ *    entries), number of launches, shortest launch ms, longest launch ms}. */
 int xlbomd_profile(xlbomd_system *h, int32_t enable, double *out);
 
 void xlbomd_destroy(xlbomd_system *h);

@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libxlbomd.so")
 
-FP64, FP32 = 0, 1
+FP64, FP32, MIXED = 0, 1, 2
 _dp = ctypes.POINTER(ctypes.c_double)
 
 
@@ -70,6 +70,9 @@ def lib():
                                          ctypes.POINTER(vp)]
         L.xlbomd_step.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Report)]
         L.xlbomd_kernel_update.argtypes = [vp, ctypes.c_int32]
+        L.xlbomd_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.POINTER(Report),
+                                        ctypes.POINTER(ctypes.c_int32)]
         L.xlbomd_forces.argtypes = [vp, _dp, ctypes.POINTER(Report)]
         L.xlbomd_get_charges.argtypes = [vp, _dp, _dp]
         L.xlbomd_set_state.argtypes = [vp, _dp, _dp, _dp, _dp]
@@ -86,7 +89,8 @@ def lib():
     return _lib
 
 
-EXPORTED = ("xlbomd_init_system", "xlbomd_step", "xlbomd_kernel_update",
+EXPORTED = ("xlbomd_init_system", "xlbomd_step", "xlbomd_step_batch",
+            "xlbomd_kernel_update",
             "xlbomd_forces", "xlbomd_get_charges", "xlbomd_set_state",
             "xlbomd_get_state", "xlbomd_solve", "xlbomd_response",
             "xlbomd_kernel_apply", "xlbomd_profile", "xlbomd_destroy", "xlbomd_last_error",
@@ -113,6 +117,17 @@ def _c(a, shape=None):
     return a
 
 
+def step_batch(systems, n_steps=1):
+    """Step several XLBOMD handles concurrently (native threads, one stream
+    each).  Returns (reports, statuses)."""
+    k = len(systems)
+    arr = (ctypes.c_void_p * k)(*[s._h.value for s in systems])
+    reps = (Report * k)()
+    st = (ctypes.c_int32 * k)()
+    rc = lib().xlbomd_step_batch(arr, k, n_steps, reps, st)
+    return [r.as_dict() for r in reps], list(st), rc
+
+
 class XLBOMD:
     """One system living on the GPU (a library handle)."""
 
@@ -137,7 +152,7 @@ class XLBOMD:
         d.kernel_every, d.krylov_mode = s.kernel_every, s.krylov_mode
         d.k0_gamma, d.precision = s.k0_gamma, precision
         d.scf_tol = scf_tol if scf_tol is not None else (
-            1e-10 if precision == FP64 else 1e-6)
+            1e-6 if precision == FP32 else 1e-10)
         d.scf_max_iter, d.energy_every = scf_max_iter, energy_every
         d.stream = stream
         self._h = ctypes.c_void_p()
@@ -203,10 +218,14 @@ class XLBOMD:
         _check(lib().xlbomd_profile(self._h, 1, None))
 
     def profile_stop(self):
-        out = np.zeros(5)
+        """GEMM timing since profile_start: {'f64': {...}, 'f32': {...}}."""
+        out = np.zeros(10)
         _check(lib().xlbomd_profile(self._h, 0, _ptr(out)))
-        return dict(ms=out[0], flops=out[1], launches=int(out[2]),
-                    min_ms=out[3], max_ms=out[4])
+        res = {}
+        for key, o in (("f64", out[:5]), ("f32", out[5:])):
+            res[key] = dict(ms=o[0], flops=o[1], launches=int(o[2]),
+                            min_ms=o[3], max_ms=o[4])
+        return res
 
     def kernel_apply(self, rank, r):
         r = _c(r, (self.nat,))

@@ -38,7 +38,7 @@ template <> struct MF<double> {
     }
 };
 
-// C = alpha * sum_s A_s^T B_s + beta * X + gamma * I ; optionally
+// C = alpha * sum_s A_s^T B_s + beta * X + beta2 * X2 + gamma * I ; optionally
 // C2 = p0 * I + p1 * C.  A_s must be symmetric (A_s^T = A_s) for the result
 // to be the product A_s B_s.  kscale (optional) multiplies row k of B_0 by
 // kscale[k].  All matrices n x n with leading dimension ld; n % 128 == 0.
@@ -46,11 +46,11 @@ template <> struct MF<double> {
 template <typename T> struct GemmArgs {
     int n = 0, ld = 0, batch = 1;
     const T *A0 = nullptr, *B0 = nullptr, *A1 = nullptr, *B1 = nullptr;
-    const T *X = nullptr;
+    const T *X = nullptr, *X2 = nullptr;
     const double *kscale = nullptr;
     T *C = nullptr, *C2 = nullptr;
-    T alpha = 1, beta = 0, gamma = 0, p0 = 0, p1 = 0;
-    long sA0 = 0, sB0 = 0, sA1 = 0, sB1 = 0, sX = 0, sC = 0, sC2 = 0, sK = 0;
+    T alpha = 1, beta = 0, beta2 = 0, gamma = 0, p0 = 0, p1 = 0;
+    long sA0 = 0, sB0 = 0, sA1 = 0, sB1 = 0, sX = 0, sX2 = 0, sC = 0, sC2 = 0, sK = 0;
 };
 
 constexpr int GT = 128;   // output tile edge
@@ -64,8 +64,8 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(GemmArgs<T> p) {
     constexpr int VEC = 16 / sizeof(T);
     constexpr int VPR = GT / VEC;              // vectors per tile row
     constexpr int PAD = 4;
-    __shared__ T As[2][BK][GT + PAD];
-    __shared__ T Bs[2][BK][GT + PAD];
+    __shared__ __attribute__((aligned(16))) T As[2][BK][GT + PAD];
+    __shared__ __attribute__((aligned(16))) T Bs[2][BK][GT + PAD];
 
     const int ti = blockIdx.y, tj = blockIdx.x;
     if (SYM && ti > tj) return;
@@ -114,14 +114,14 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(GemmArgs<T> p) {
             }
         }
     };
+    // (GT + PAD) * sizeof(T) is a multiple of 16 bytes: one 16-byte LDS
+    // store per vector
     auto sstore = [&](int buf) {
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                As[buf][lrow[v]][lcol[v] + e] = ra[v][e];
-                Bs[buf][lrow[v]][lcol[v] + e] = rb[v][e];
-            }
+        for (int v = 0; v < 2; ++v) {
+            *reinterpret_cast<vec_t *>(&As[buf][lrow[v]][lcol[v]]) = ra[v];
+            *reinterpret_cast<vec_t *>(&Bs[buf][lrow[v]][lcol[v]]) = rb[v];
+        }
     };
 
     gload(0);
@@ -152,6 +152,7 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(GemmArgs<T> p) {
     T *C = p.C + bz * p.sC;
     T *C2 = p.C2 ? p.C2 + bz * p.sC2 : nullptr;
     const T *X = p.X ? p.X + bz * p.sX : nullptr;
+    const T *X2 = p.X2 ? p.X2 + bz * p.sX2 : nullptr;
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -163,6 +164,7 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(GemmArgs<T> p) {
                 const long o = (long)row * ld + col;
                 T val = p.alpha * acc[x][y][r];
                 if (X) val += p.beta * X[o];
+                if (X2) val += p.beta2 * X2[o];
                 if (row == col) val += p.gamma;
                 T val2 = 0;
                 if (C2) val2 = p.p1 * val + (row == col ? p.p0 : (T)0);

@@ -161,29 +161,54 @@ __global__ __launch_bounds__(256) void row_sqnorm_kernel(int n, int ld,
     if (lane == 0) out[i] = s;
 }
 
-// Newton step of the electron count (one block):
-//   Tr D = n - 2 Tr Z_L,  dN/dmu = (beta/2) sum_i (1 - 4 |row_i Z_L|^2),
-//   dmu = (n_e - Tr D) / (dN/dmu).   out = {Tr D, dN/dmu, dmu}.
-// Also g[i] = (beta/2)(1 - 4 |row_i|^2) = diag of dD/dmu.
+// Per row i of the real block: m[i] = sum_j Z_ij Z2_ij  (for Tr Z^3).
 template <typename T>
-__global__ __launch_bounds__(1024) void mu_newton_kernel(int n, int ld, const T *Z,
-                                                         const double *rsq,
-                                                         double beta, double ne,
-                                                         double *g, double *out) {
+__global__ __launch_bounds__(256) void zz2_rows_kernel(int n, int ld, const T *Z,
+                                                       const T *Z2, double *m) {
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;
+    const T *a = Z + (long)i * ld, *b = Z2 + (long)i * ld;
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) s += (double)a[j] * (double)b[j];
+    s = wave_sum(s);
+    if (lane == 0) m[i] = s;
+}
+
+// Electron count and its mu-derivatives at the expansion's mu0 (one block):
+//   N0 = n - 2 Tr Z,  N' = (beta/2)(n - 4 Tr Z^2),  N'' = beta^2 (Tr Z - 4 Tr Z^3)
+// (from dD/dmu = (beta/2)(I - 4Z^2), d2D/dmu2 = beta^2 (Z - 4 Z^3)), and the
+// root dmu of N0 + N' d + N''/2 d^2 = ne nearest to the Newton step.
+// g[i] = (beta/2)(1 - 4 (Z^2)_ii).  out = {N0, N', dmu, N''}.
+template <typename T>
+__global__ __launch_bounds__(1024) void mu_step_kernel(int n, int ld, const T *Z,
+                                                       const T *Z2, const double *m3,
+                                                       double beta, double ne,
+                                                       double *g, double *out) {
     __shared__ double sh[16];
-    double tr = 0.0, dn = 0.0;
+    double t1 = 0.0, t2 = 0.0, t3 = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        tr += 1.0 - 2.0 * (double)Z[(long)i * ld + i];
-        const double gi = 0.5 * beta * (1.0 - 4.0 * rsq[i]);
-        g[i] = gi;
-        dn += gi;
+        const double z = (double)Z[(long)i * ld + i], z2 = (double)Z2[(long)i * ld + i];
+        t1 += z;
+        t2 += z2;
+        t3 += m3[i];
+        g[i] = 0.5 * beta * (1.0 - 4.0 * z2);
     }
-    tr = block_sum(tr, sh);
-    dn = block_sum(dn, sh);
+    t1 = block_sum(t1, sh);
+    t2 = block_sum(t2, sh);
+    t3 = block_sum(t3, sh);
     if (threadIdx.x == 0) {
-        out[0] = tr;
-        out[1] = dn;
-        out[2] = (ne - tr) / dn;
+        const double N0 = n - 2.0 * t1;
+        const double N1 = 0.5 * beta * (n - 4.0 * t2);
+        const double N2 = beta * beta * (t1 - 4.0 * t3);
+        const double dN = ne - N0;
+        double d = dN / N1;
+        const double disc = N1 * N1 + 2.0 * N2 * dN;
+        if (disc > 0.0) d = 2.0 * dN / (N1 + sqrt(disc));
+        out[0] = N0;
+        out[1] = N1;
+        out[2] = d;
+        out[3] = N2;
     }
 }
 
@@ -530,12 +555,12 @@ __global__ __launch_bounds__(256) void expand_orbital_kernel(int nat, int no,
     u[b * su + i] = sc * h[b * nat + i / no];
 }
 
-// dst = scale * src (whole padded matrix), converted to FP64
-template <typename T>
-__global__ __launch_bounds__(256) void convert_kernel(long n, const T *src,
-                                                      double scale, double *dst) {
+// dst = scale * src (whole padded matrix), converted between precisions
+template <typename S, typename D>
+__global__ __launch_bounds__(256) void convert_kernel(long n, const S *src,
+                                                      double scale, D *dst) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = scale * (double)src[i];
+    if (i < n) dst[i] = (D)(scale * (double)src[i]);
 }
 
 // C = A + val * I on the first n diagonal entries (whole padded copy)

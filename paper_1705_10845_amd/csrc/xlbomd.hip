@@ -36,7 +36,9 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <atomic>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -156,6 +158,7 @@ struct SysBase {
         bool on = false;
         std::vector<hipEvent_t> ev;
         std::vector<double> flops;
+        std::vector<int> f64;
         size_t used = 0;
     } prof;
 
@@ -170,10 +173,11 @@ struct SysBase {
         }
         XL_HIP(hipEventRecord(prof.ev[prof.used], st));
     }
-    void prof_end(double flops) {
+    void prof_end(double flops, bool is64) {
         if (!prof.on) return;
         XL_HIP(hipEventRecord(prof.ev[prof.used + 1], st));
         prof.flops.push_back(flops);
+        prof.f64.push_back(is64 ? 1 : 0);
         prof.used += 2;
     }
     // algorithmic flops of one product on the real n x n block: each output
@@ -298,7 +302,7 @@ struct SysBase {
         elo = hscal[0];
         ehi = hscal[1];
         double mu0 = have_guess ? mu_guess : initial_mu();
-        const double tau = (d.precision == XLBOMD_FP64) ? 1e-5 : 1e-3;
+        const double tau = (d.precision == XLBOMD_FP64) ? 1e-6 : 1e-3;
         reruns = 0;
         ns_total = 0;
         for (int it = 0;; ++it) {
@@ -307,7 +311,7 @@ struct SysBase {
             XL_HIP(hipMemcpyAsync(hscal, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
             sync();
             trd = hscal[0];
-            dmu = hscal[2];
+            dmu = hscal[2];   // root of the quadratic model of the count
             if (!std::isfinite(dmu)) throw Diverged("non-finite chemical potential step");
             if (beta * std::fabs(dmu) <= tau) break;
             if (it >= 60) throw NoConv("chemical potential did not converge");
@@ -500,19 +504,25 @@ struct SysBase {
 };
 
 // ---------------------------------------------------------------------------
-// Precision-dependent dense algebra
+// Precision-dependent dense algebra.  TF: expansion (density matrix, charges,
+// forces, energy); TR: the kernel's responses.  MIXED runs TF = double,
+// TR = float: the physics at FP64, the preconditioner at FP32.
 // ---------------------------------------------------------------------------
-template <typename T> struct Sys : SysBase {
-    std::vector<T *> Z, Yk;       // Z_0..Z_L, Y_0..Y_{L-1}
-    T *Ys = nullptr, *Y2 = nullptr, *Am = nullptr, *E = nullptr, *Wk = nullptr;
-    T *Dc = nullptr;
-    T *Zp = nullptr, *Ap = nullptr, *Tb = nullptr;   // response batch buffers
-    double *e64[8] = {};                             // FP64 energy workspace
-    int Lcap = 0;
+template <typename TF, typename TR> struct Sys : SysBase {
+    static constexpr bool SAME = std::is_same<TF, TR>::value;
+    std::vector<TF *> Z, Yk;       // Z_0..Z_L, Y_0..Y_{L-1}
+    TF *Ys = nullptr, *Y2 = nullptr, *Am = nullptr, *E = nullptr, *Wk = nullptr;
+    TF *Dc = nullptr, *ZL2 = nullptr;
+    std::vector<TR *> Zr, Yr;      // response copies (alias when SAME)
+    TR *Ysr = nullptr, *Y2r = nullptr;
+    TR *Zp = nullptr, *Ap = nullptr, *Tb = nullptr;   // response batch buffers
+    double *m3 = nullptr;
+    double *e64[8] = {};                              // FP64 energy workspace
+    int Lcap = 0, Lr = -1;                            // Lr: levels converted
 
     size_t mat() const { return (size_t)Np * Np; }
-    T *amat() {
-        T *p = dalloc<T>(mat());
+    template <typename U> U *amat() {
+        U *p = dalloc<U>(mat());
         mem.ptrs.push_back(p);
         return p;
     }
@@ -520,17 +530,19 @@ template <typename T> struct Sys : SysBase {
 
     void alloc_matrices(int cap) override {
         if (cap <= Lcap) return;
-        while ((int)Z.size() < cap + 1) Z.push_back(amat());
-        while ((int)Yk.size() < cap) Yk.push_back(amat());
+        while ((int)Z.size() < cap + 1) Z.push_back(amat<TF>());
+        while ((int)Yk.size() < cap) Yk.push_back(amat<TF>());
         if (!Ys) {
-            Ys = amat(); Y2 = amat(); Am = amat(); E = amat(); Wk = amat(); Dc = amat();
+            Ys = amat<TF>(); Y2 = amat<TF>(); Am = amat<TF>(); E = amat<TF>();
+            Wk = amat<TF>(); Dc = amat<TF>(); ZL2 = amat<TF>();
+            m3 = dalloc<double>(Np);
+            mem.ptrs.push_back(m3);
         }
         Lcap = cap;
     }
     void alloc_resp(int nb) {
         if (nb <= bcap) return;
-        // one allocation each for the whole batch
-        T *zp = dalloc<T>(mat() * nb), *ap = dalloc<T>(mat() * nb), *tb = dalloc<T>(mat() * nb);
+        TR *zp = dalloc<TR>(mat() * nb), *ap = dalloc<TR>(mat() * nb), *tb = dalloc<TR>(mat() * nb);
         mem.ptrs.push_back(zp); mem.ptrs.push_back(ap); mem.ptrs.push_back(tb);
         Zp = zp; Ap = ap; Tb = tb;
         bcap = nb;
@@ -539,38 +551,42 @@ template <typename T> struct Sys : SysBase {
     template <typename U> void run_gemm(const GemmArgs<U> &a, bool sym) {
         prof_begin();
         gemm(a, sym, st);
-        prof_end(gemm_flops(sym, a.A1 ? 2 : 1) * a.batch);
+        prof_end(gemm_flops(sym, a.A1 ? 2 : 1) * a.batch, sizeof(U) == 8);
     }
-
-    GemmArgs<T> base() const {
-        GemmArgs<T> a;
+    template <typename U> GemmArgs<U> base() const {
+        GemmArgs<U> a;
         a.n = Np;
         a.ld = Np;
         return a;
     }
+    template <typename S, typename D> void convert(const S *src, D *dst, double scale) {
+        hipLaunchKernelGGL((convert_kernel<S, D>), dim3(ceil_div((long)mat(), 256)), dim3(256), 0,
+                           st, (long)mat(), src, scale, dst);
+        XL_LAUNCH_CHECK();
+    }
 
     void foe(double mu0) override {
         const double xmax = beta * std::max(std::fabs(elo - mu0), std::fabs(ehi - mu0)) * 1.02 + 1e-12;
-        const double tol = 2e-10;
-        L = choose_levels(xmax, tol);
+        L = choose_levels(xmax, 2e-10);
         alloc_matrices(L);
+        Lr = -1;
         sc = std::ldexp(beta, -(L + 1));
         // Y = sc (H - mu0 I)
-        hipLaunchKernelGGL((build_seed_kernel<T>), dim3(ceil_div(Np, 256), Np), dim3(256), 0, st,
+        hipLaunchKernelGGL((build_seed_kernel<TF>), dim3(ceil_div(Np, 256), Np), dim3(256), 0, st,
                            md, vpot, mu0, sc, Ys);
         XL_LAUNCH_CHECK();
         const double ymax = std::ldexp(xmax, -(L + 1));
         t0max = ymax - ymax * ymax * ymax / 3.0;
         {   // Y2 = Y Y ; Z0 = Y/2 - Y Y2 / 6
-            GemmArgs<T> a = base();
+            auto a = base<TF>();
             a.A0 = Ys; a.B0 = Ys; a.C = Y2;
             run_gemm(a, true);
-            a = base();
-            a.A0 = Ys; a.B0 = Y2; a.X = Ys; a.alpha = (T)(-1.0 / 6.0); a.beta = (T)0.5;
+            a = base<TF>();
+            a.A0 = Ys; a.B0 = Y2; a.X = Ys; a.alpha = (TF)(-1.0 / 6.0); a.beta = (TF)0.5;
             a.C = Z[0];
             run_gemm(a, true);
         }
-        const double nstol = (sizeof(T) == 8) ? 2e-16 : 1e-8;
+        const double nstol = (sizeof(TF) == 8) ? 2e-16 : 1e-8;
         double t = t0max;
         for (int k = 0; k < L; ++k) {
             const double b = t * t;            // spectrum of A_k within [1, 1 + b]
@@ -580,52 +596,81 @@ template <typename T> struct Sys : SysBase {
             int ns = 0;
             while (e > nstol && ns < 8) { e = e * e; ++ns; }
             ns_total += ns;
-            GemmArgs<T> a = base();
-            a.A0 = Z[k]; a.B0 = Z[k]; a.alpha = (T)4.0; a.gamma = (T)1.0; a.C = Am;
-            a.C2 = Yk[k]; a.p0 = (T)al; a.p1 = (T)ga;
+            auto a = base<TF>();
+            a.A0 = Z[k]; a.B0 = Z[k]; a.alpha = (TF)4.0; a.gamma = (TF)1.0; a.C = Am;
+            a.C2 = Yk[k]; a.p0 = (TF)al; a.p1 = (TF)ga;
             run_gemm(a, true);
             for (int j = 0; j < ns; ++j) {
-                GemmArgs<T> e1 = base();   // E = 2I - A Y
-                e1.A0 = Am; e1.B0 = Yk[k]; e1.alpha = (T)-1.0; e1.gamma = (T)2.0; e1.C = E;
+                auto e1 = base<TF>();   // E = 2I - A Y
+                e1.A0 = Am; e1.B0 = Yk[k]; e1.alpha = (TF)-1.0; e1.gamma = (TF)2.0; e1.C = E;
                 run_gemm(e1, true);
-                GemmArgs<T> e2 = base();   // Y <- Y E
+                auto e2 = base<TF>();   // Y <- Y E
                 e2.A0 = Yk[k]; e2.B0 = E; e2.C = Wk;
                 run_gemm(e2, true);
                 std::swap(Yk[k], Wk);
             }
-            GemmArgs<T> z = base();        // Z_{k+1} = 2 Y_k Z_k
-            z.A0 = Yk[k]; z.B0 = Z[k]; z.alpha = (T)2.0; z.C = Z[k + 1];
+            auto z = base<TF>();        // Z_{k+1} = 2 Y_k Z_k
+            z.A0 = Yk[k]; z.B0 = Z[k]; z.alpha = (TF)2.0; z.C = Z[k + 1];
             run_gemm(z, true);
             t = 2.0 * t / (1.0 + t * t);
         }
-        hipLaunchKernelGGL((row_sqnorm_kernel<T>), dim3(ceil_div((long)N * 64, 256)), dim3(256), 0,
-                           st, N, Np, Z[L], g);
+        {   // Z_L^2 for the electron-count derivatives and the mu correction
+            auto a = base<TF>();
+            a.A0 = Z[L]; a.B0 = Z[L]; a.C = ZL2;
+            run_gemm(a, true);
+        }
+        hipLaunchKernelGGL((zz2_rows_kernel<TF>), dim3(ceil_div((long)N * 64, 256)), dim3(256), 0,
+                           st, N, Np, Z[L], ZL2, m3);
         XL_LAUNCH_CHECK();
-        hipLaunchKernelGGL((mu_newton_kernel<T>), dim3(1), dim3(1024), 0, st, N, Np, Z[L], g, beta,
-                           d.n_electrons, g, scal);
+        hipLaunchKernelGGL((mu_step_kernel<TF>), dim3(1), dim3(1024), 0, st, N, Np, Z[L], ZL2, m3,
+                           beta, d.n_electrons, g, scal);
         XL_LAUNCH_CHECK();
     }
 
     void finish_density() override {
-        // D_c = I - 2 Z + dmu (beta/2)(I - 4 Z^2)
-        GemmArgs<T> a = base();
-        a.A0 = Z[L]; a.B0 = Z[L]; a.alpha = (T)(-2.0 * dmu * beta);
-        a.X = Z[L]; a.beta = (T)-2.0; a.gamma = (T)(1.0 + 0.5 * dmu * beta); a.C = Dc;
+        // D(mu0 + d) = I - 2Z + d (beta/2)(I - 4Z^2) + d^2/2 beta^2 (Z - 4Z^3)
+        const double bd = beta * dmu;
+        auto a = base<TF>();
+        a.A0 = Z[L]; a.B0 = ZL2; a.alpha = (TF)(-2.0 * bd * bd);
+        a.X = Z[L]; a.beta = (TF)(-2.0 + 0.5 * bd * bd);
+        a.X2 = ZL2; a.beta2 = (TF)(-2.0 * bd);
+        a.gamma = (TF)(1.0 + 0.5 * bd); a.C = Dc;
         run_gemm(a, true);
-        hipLaunchKernelGGL((charges_kernel<T>), dim3(1), dim3(1024), 0, st, nat, no, Np, Dc, zc,
+        hipLaunchKernelGGL((charges_kernel<TF>), dim3(1), dim3(1024), 0, st, nat, no, Np, Dc, zc,
                            ncur, q, r, scal + 16);
         XL_LAUNCH_CHECK();
     }
 
     void forces_parts() override {
-        hipLaunchKernelGGL((forces_kernel<T>), dim3(ceil_div((long)nat * 64, 256)), dim3(256), 0,
+        hipLaunchKernelGGL((forces_kernel<TF>), dim3(ceil_div((long)nat * 64, 256)), dim3(256), 0,
                            st, md, Dc, q, ncur, vpot, force, epart);
         XL_LAUNCH_CHECK();
+    }
+
+    // response operands in TR (converted once per expansion when TF != TR)
+    void response_operands() {
+        if (Lr == L) return;
+        if constexpr (SAME) {
+            Zr.assign(Z.begin(), Z.end());
+            Yr.assign(Yk.begin(), Yk.end());
+            Ysr = (TR *)Ys;
+            Y2r = (TR *)Y2;
+        } else {
+            while ((int)Zr.size() < L + 1) Zr.push_back(amat<TR>());
+            while ((int)Yr.size() < L) Yr.push_back(amat<TR>());
+            if (!Ysr) { Ysr = amat<TR>(); Y2r = amat<TR>(); }
+            for (int k = 0; k <= L; ++k) convert(Z[k], Zr[k], 1.0);
+            for (int k = 0; k < L; ++k) convert(Yk[k], Yr[k], 1.0);
+            convert(Ys, Ysr, 1.0);
+            convert(Y2, Y2r, 1.0);
+        }
+        Lr = L;
     }
 
     void responses(int nb, const double *v, double *qout, double *wout) override {
         if (nb <= 0) return;
         alloc_resp(nb);
+        response_operands();
         const long sm = (long)mat();
         // h = Gamma v, u = sc * h per orbital
         hipLaunchKernelGGL(gamma_matvec_kernel, dim3(ceil_div((long)nat * nb * 64, 256)),
@@ -635,36 +680,36 @@ template <typename T> struct Sys : SysBase {
                            st, nat, no, nb, sc, hb, (long)Np, ub);
         XL_LAUNCH_CHECK();
         {   // G = Y diag(u) Y, then Z'_0
-            GemmArgs<T> a = base();
-            a.batch = nb; a.A0 = Ys; a.B0 = Ys; a.kscale = ub; a.sK = Np;
+            auto a = base<TR>();
+            a.batch = nb; a.A0 = Ysr; a.B0 = Ysr; a.kscale = ub; a.sK = Np;
             a.C = Tb; a.sC = sm;
             run_gemm(a, true);
-            hipLaunchKernelGGL((seed_resp_kernel<T>), dim3(ceil_div(Np, 256), Np, nb), dim3(256),
-                               0, st, N, Np, Tb, Y2, ub, (long)Np, sm, Zp);
+            hipLaunchKernelGGL((seed_resp_kernel<TR>), dim3(ceil_div(Np, 256), Np, nb), dim3(256),
+                               0, st, N, Np, Tb, Y2r, ub, (long)Np, sm, Zp);
             XL_LAUNCH_CHECK();
         }
         for (int k = 0; k < L; ++k) {
-            GemmArgs<T> a = base();        // A' = 4 (Z Z' + Z' Z)
+            auto a = base<TR>();           // A' = 4 (Z Z' + Z' Z)
             a.batch = nb;
-            a.A0 = Z[k]; a.B0 = Zp; a.sB0 = sm; a.A1 = Zp; a.sA1 = sm; a.B1 = Z[k];
-            a.alpha = (T)4.0; a.C = Ap; a.sC = sm;
+            a.A0 = Zr[k]; a.B0 = Zp; a.sB0 = sm; a.A1 = Zp; a.sA1 = sm; a.B1 = Zr[k];
+            a.alpha = (TR)4.0; a.C = Ap; a.sC = sm;
             run_gemm(a, true);
-            GemmArgs<T> b = base();        // T = 2 Z' - A' Z_{k+1}
+            auto b = base<TR>();           // T = 2 Z' - A' Z_{k+1}
             b.batch = nb;
-            b.A0 = Ap; b.sA0 = sm; b.B0 = Z[k + 1]; b.alpha = (T)-1.0;
-            b.X = Zp; b.sX = sm; b.beta = (T)2.0; b.C = Tb; b.sC = sm;
+            b.A0 = Ap; b.sA0 = sm; b.B0 = Zr[k + 1]; b.alpha = (TR)-1.0;
+            b.X = Zp; b.sX = sm; b.beta = (TR)2.0; b.C = Tb; b.sC = sm;
             run_gemm(b, false);
             if (k + 1 < L) {
-                GemmArgs<T> c = base();    // Z'_{k+1} = Y_k T
+                auto c = base<TR>();       // Z'_{k+1} = Y_k T
                 c.batch = nb;
-                c.A0 = Yk[k]; c.B0 = Tb; c.sB0 = sm; c.C = Zp; c.sC = sm;
+                c.A0 = Yr[k]; c.B0 = Tb; c.sB0 = sm; c.C = Zp; c.sC = sm;
                 run_gemm(c, true);
             }
         }
         const int nchunk = (N + 63) / 64;
         const long sP = (long)nchunk * N;
-        hipLaunchKernelGGL((coldot_kernel<T>), dim3(ceil_div(N, 256), nchunk, nb), dim3(256), 0, st,
-                           N, Np, Yk[L - 1], Tb, sm, part, sP);
+        hipLaunchKernelGGL((coldot_kernel<TR>), dim3(ceil_div(N, 256), nchunk, nb), dim3(256), 0,
+                           st, N, Np, Yr[L - 1], Tb, sm, part, sP);
         XL_LAUNCH_CHECK();
         hipLaunchKernelGGL(resp_charges_kernel, dim3(nb), dim3(1024), 0, st, nat, no, nchunk, part,
                            sP, g, v, qout, wout);
@@ -673,7 +718,7 @@ template <typename T> struct Sys : SysBase {
 
     // ---- entropy without eigenvalues ----
     // With F = 1/2 I - Z_L the occupations and X_eff = 2^(L+1) atanh(2 Z_0)
-    // the argument the expansion actually applies:
+    // the argument the expansion actually applies (f_L = 1/(1 + e^X_eff)):
     //   S/2 = -ln det(1/2 I + Z_L) + <F, X_eff>
     //   ln det(1/2 I + Z_L) = 2^L ln det(1/2 I + Z_0)
     //                       + sum_k 2^(L-1-k) (N ln 2 - ln det A_k)
@@ -686,15 +731,16 @@ template <typename T> struct Sys : SysBase {
         }
         return e64[i];
     }
-    const double *as64(const T *src, int slot, double scale) {
+    const double *as64(const TF *src, int slot, double scale) {
+        if constexpr (std::is_same<TF, double>::value) {
+            if (scale == 1.0) return src;
+        }
         double *dst = w64(slot);
-        hipLaunchKernelGGL((convert_kernel<T>), dim3(ceil_div((long)mat(), 256)), dim3(256), 0, st,
-                           (long)mat(), src, scale, dst);
-        XL_LAUNCH_CHECK();
+        convert(src, dst, scale);
         return dst;
     }
 
-    double logdet_shift(double *A) {   // ln det of the leading block, A destroyed
+    double logdet_lead(double *A) {   // ln det of the leading block, A destroyed
         const int n32 = ((N + CB - 1) / CB) * CB;
         chol_logdet(n32, Np, A, scal + 48, st);
         XL_HIP(hipMemcpyAsync(hscal + 48, scal + 48, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -705,14 +751,12 @@ template <typename T> struct Sys : SysBase {
     double entropy_ts() override {
         GemmArgs<double> a;
         a.n = Np; a.ld = Np;
-        // T0 = 2 Z_0
-        const double *T0 = as64(Z[0], 0, 2.0);
-        // l0 = ln det(I + T0)
+        const double *T0 = as64(Z[0], 0, 2.0);          // T0 = 2 Z_0
         double *C = w64(1);
         hipLaunchKernelGGL(add_diag_copy_kernel, dim3(ceil_div((long)mat(), 256)), dim3(256), 0, st,
                            Np, N, T0, 1.0, C);
         XL_LAUNCH_CHECK();
-        const double l0 = logdet_shift(C);
+        const double l0 = logdet_lead(C);                // ln det(I + T0)
         const double ln2 = std::log(2.0);
         double lnF = std::ldexp(-N * ln2 + l0, L);
         for (int k = 0; k < L; ++k) {
@@ -720,27 +764,25 @@ template <typename T> struct Sys : SysBase {
             GemmArgs<double> b = a;
             b.A0 = Zk; b.B0 = Zk; b.alpha = 4.0; b.gamma = 1.0; b.C = C;
             gemm(b, true, st);
-            const double lk = logdet_shift(C);
-            lnF += std::ldexp(N * ln2 - lk, L - 1 - k);
+            lnF += std::ldexp(N * ln2 - logdet_lead(C), L - 1 - k);
         }
         // series of atanh(T0): P_j = T0^(2j+1)
         const double *ZL = as64(Z[L], 2, 1.0);
-        double *ZL2 = w64(3), *T0sq = w64(4), *P = w64(5), *Pn = w64(6);
+        double *Z2 = w64(3), *T0sq = w64(4), *P = w64(5), *Pn = w64(6);
         {
             GemmArgs<double> b = a;
-            b.A0 = ZL; b.B0 = ZL; b.C = ZL2;
+            b.A0 = ZL; b.B0 = ZL; b.C = Z2;
             gemm(b, true, st);
             b = a;
             b.A0 = T0; b.B0 = T0; b.C = T0sq;
             gemm(b, true, st);
         }
         XL_HIP(hipMemcpyAsync(P, T0, mat() * sizeof(double), hipMemcpyDeviceToDevice, st));
-        const double tmax = 2.0 * 0.5 * t0max;   // |2 z_0| <= t0max
         double s1 = 0.0, s2 = 0.0;
         const double scale = std::ldexp(1.0, L + 1);
         for (int j = 0; j < 64; ++j) {
             const double cj = scale / (2 * j + 1);
-            hipLaunchKernelGGL(frob3_kernel, dim3(N), dim3(256), 0, st, N, Np, P, ZL, ZL2, part);
+            hipLaunchKernelGGL(frob3_kernel, dim3(N), dim3(256), 0, st, N, Np, P, ZL, Z2, part);
             XL_LAUNCH_CHECK();
             hipLaunchKernelGGL(sum_rows_kernel, dim3(1), dim3(1024), 0, st, N, 3, part, scal + 52);
             XL_LAUNCH_CHECK();
@@ -749,12 +791,11 @@ template <typename T> struct Sys : SysBase {
             const double trP = hscal[52], zp = hscal[53], z2p = hscal[54];
             s1 += cj * (0.5 * trP - zp);          // <1/2 I - Z_L, P>
             s2 += cj * (trP - 4.0 * z2p);         // <P, I - 4 Z_L^2>
-            if (std::pow(tmax, 2 * j + 3) * scale / (2 * j + 3) * N < 1e-14) break;
+            if (std::pow(t0max, 2 * j + 3) * scale / (2 * j + 3) * N < 1e-14) break;
             GemmArgs<double> b = a;
             b.A0 = T0sq; b.B0 = P; b.C = Pn;
             gemm(b, true, st);
             std::swap(P, Pn);
-            e64[5] = P; e64[6] = Pn;
         }
         const double S0 = 2.0 * (-lnF + s1);
         return S0 / beta + dmu * 0.5 * s2;
@@ -813,8 +854,8 @@ void validate(const xlbomd_desc *d) {
     if (d->kernel_every < 1) throw InvalidArg("kernel_every must be >= 1");
     if (d->krylov_mode != 0 && d->krylov_mode != 1) throw InvalidArg("krylov_mode is 0 or 1");
     if (!(d->k0_gamma > 0.0 && d->k0_gamma <= 1.0)) throw InvalidArg("k0_gamma must be in (0, 1]");
-    if (d->precision != XLBOMD_FP64 && d->precision != XLBOMD_FP32)
-        throw InvalidArg("precision must be XLBOMD_FP64 or XLBOMD_FP32");
+    if (d->precision < XLBOMD_FP64 || d->precision > XLBOMD_MIXED)
+        throw InvalidArg("precision must be XLBOMD_FP64, XLBOMD_FP32 or XLBOMD_MIXED");
     if (!(d->hop_decay > 0.0) || !(d->hop_cutoff > 0.0) || d->taper_width < 0.0 ||
         !(d->gamma_soft > 0.0) || (d->rep_a != 0.0 && !(d->rep_decay > 0.0)))
         throw InvalidArg("model lengths must be positive");
@@ -832,8 +873,9 @@ int xlbomd_init_system(const xlbomd_desc *desc, xlbomd_system **out) {
     std::unique_ptr<xlbomd_system> h(new xlbomd_system);
     const int rc = guarded([&] {
         validate(desc);
-        if (desc->precision == XLBOMD_FP64) h->s.reset(new Sys<double>());
-        else h->s.reset(new Sys<float>());
+        if (desc->precision == XLBOMD_FP64) h->s.reset(new Sys<double, double>());
+        else if (desc->precision == XLBOMD_FP32) h->s.reset(new Sys<float, float>());
+        else h->s.reset(new Sys<double, float>());
         h->s->upload_model(desc);
         h->s->init();
     });
@@ -854,6 +896,39 @@ int xlbomd_step(xlbomd_system *h, int32_t n_steps, xlbomd_report *last) {
         }
         s.sync();
     });
+}
+
+int xlbomd_step_batch(xlbomd_system *const *hs, int32_t count, int32_t n_steps,
+                      xlbomd_report *reports, int32_t *status) {
+    if (!hs || count < 0 || n_steps < 0) return fail(XLBOMD_E_INVALID, "bad batch arguments");
+    for (int i = 0; i < count; ++i)
+        if (!hs[i] || !hs[i]->s) return fail(XLBOMD_E_INVALID, "null handle in batch");
+    for (int i = 0; i < count; ++i)
+        for (int j = i + 1; j < count; ++j)
+            if (hs[i] == hs[j]) return fail(XLBOMD_E_INVALID, "handle repeated in batch");
+    std::vector<int> rc(count, XLBOMD_OK);
+    std::vector<std::string> msg(count);
+    auto run = [&](int i) {
+        rc[i] = xlbomd_step(hs[i], n_steps, reports ? &reports[i] : nullptr);
+        if (rc[i] != XLBOMD_OK) msg[i] = xlbomd_last_error();
+    };
+    if (count == 1) {
+        run(0);
+    } else {
+        std::vector<std::thread> th;
+        th.reserve(count);
+        for (int i = 0; i < count; ++i) th.emplace_back(run, i);
+        for (auto &x : th) x.join();
+    }
+    int first = XLBOMD_OK;
+    for (int i = 0; i < count; ++i) {
+        if (status) status[i] = rc[i];
+        if (rc[i] != XLBOMD_OK && first == XLBOMD_OK) {
+            first = rc[i];
+            g_err = "system " + std::to_string(i) + ": " + msg[i];
+        }
+    }
+    return first;
 }
 
 int xlbomd_kernel_update(xlbomd_system *h, int32_t rank) {
@@ -992,32 +1067,32 @@ int xlbomd_profile(xlbomd_system *h, int32_t enable, double *out) {
     if (!h || !h->s) return fail(XLBOMD_E_INVALID, "null handle");
     return guarded([&] {
         SysBase &s = *h->s;
+        s.sync();
         if (enable) {
-            s.sync();
             s.prof.on = true;
             s.prof.used = 0;
             s.prof.flops.clear();
+            s.prof.f64.clear();
             return;
         }
-        s.sync();
-        double ms = 0.0, fl = 0.0, mx = 0.0, mn = 1e300;
+        double acc[2][5] = {{0, 0, 0, 1e300, 0}, {0, 0, 0, 1e300, 0}};
         const size_t n = s.prof.used / 2;
         for (size_t i = 0; i < n; ++i) {
             float e = 0.0f;
             XL_HIP(hipEventElapsedTime(&e, s.prof.ev[2 * i], s.prof.ev[2 * i + 1]));
-            ms += e;
-            fl += s.prof.flops[i];
-            mx = std::max(mx, (double)e);
-            mn = std::min(mn, (double)e);
+            double *a = acc[s.prof.f64[i] ? 0 : 1];
+            a[0] += e;
+            a[1] += s.prof.flops[i];
+            a[2] += 1.0;
+            a[3] = std::min(a[3], (double)e);
+            a[4] = std::max(a[4], (double)e);
         }
         s.prof.on = false;
-        if (out) {
-            out[0] = ms;
-            out[1] = fl;
-            out[2] = (double)n;
-            out[3] = n ? mn : 0.0;
-            out[4] = mx;
-        }
+        if (out)
+            for (int p = 0; p < 2; ++p) {
+                if (acc[p][2] == 0.0) acc[p][3] = 0.0;
+                for (int k = 0; k < 5; ++k) out[5 * p + k] = acc[p][k];
+            }
     });
 }
 

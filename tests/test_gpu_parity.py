@@ -181,3 +181,25 @@ def test_invalid_descriptor_rejected(gpu):
     assert e.value.code == -1
     with pytest.raises(gpu.XlbomdError):
         gpu.XLBOMD(s.replace(n_electrons=0.0))
+
+
+@pytest.mark.parametrize("name,spec", CASES[:2])
+def test_mixed_path(gpu, name, spec):
+    """MIXED: FP64 expansion (charges/forces/energy at FP64 tolerances),
+    FP32 response products (kernel to FP32-level relative accuracy)."""
+    s = _system(name, spec)
+    m = R.Model(s)
+    g = gpu.XLBOMD(s, precision=gpu.MIXED, scf_tol=1e-9)
+    n = _rand_n(s.n_atoms, 3)
+    q, rep = g.solve(n)
+    el = R.electronic(m, s.pos, n)
+    dq = np.abs(q - el.q).max()
+    V = np.random.default_rng(2).standard_normal((1, s.n_atoms))
+    V /= np.linalg.norm(V)
+    dv = g.response(V)[0]
+    ref = R.response(m, el, V[0])
+    err = np.abs(dv - ref).max() / np.abs(ref).max()
+    print(f"{name} MIXED: max|dq| {dq:.2e}, response rel err {err:.2e}")
+    assert dq < 1e-8
+    assert err < 1e-4
+    g.close()
