@@ -183,6 +183,14 @@ int xlbomd_kernel_apply(xlbomd_system *h, int32_t rank, const double *r,
  *    entries), number of launches, shortest launch ms, longest launch ms}. */
 int xlbomd_profile(xlbomd_system *h, int32_t enable, double *out);
 
+/* Kernel-level test hook: C = A B with the library's dense product kernel
+ * (A must be symmetric; it is read as A^T).  n x n row-major host arrays,
+ * n a positive multiple of 128; precision XLBOMD_FP64 or XLBOMD_FP32 (the
+ * inputs are rounded to it); sym != 0 computes only the upper block
+ * triangle and mirrors it (valid when A B is symmetric).  Synchronous. */
+int xlbomd_selftest_gemm(int32_t n, int32_t precision, int32_t sym, const double *A,
+                         const double *B, double *C);
+
 void xlbomd_destroy(xlbomd_system *h);
 
 /* Message of the last failed call on this thread ("" if none). */

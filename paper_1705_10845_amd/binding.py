@@ -81,6 +81,8 @@ def lib():
         L.xlbomd_response.argtypes = [vp, ctypes.c_int32, _dp, _dp]
         L.xlbomd_kernel_apply.argtypes = [vp, ctypes.c_int32, _dp, _dp]
         L.xlbomd_profile.argtypes = [vp, ctypes.c_int32, _dp]
+        L.xlbomd_selftest_gemm.argtypes = [ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, _dp, _dp, _dp]
         L.xlbomd_destroy.argtypes = [vp]
         L.xlbomd_destroy.restype = None
         L.xlbomd_last_error.restype = ctypes.c_char_p
@@ -93,7 +95,8 @@ EXPORTED = ("xlbomd_init_system", "xlbomd_step", "xlbomd_step_batch",
             "xlbomd_kernel_update",
             "xlbomd_forces", "xlbomd_get_charges", "xlbomd_set_state",
             "xlbomd_get_state", "xlbomd_solve", "xlbomd_response",
-            "xlbomd_kernel_apply", "xlbomd_profile", "xlbomd_destroy", "xlbomd_last_error",
+            "xlbomd_kernel_apply", "xlbomd_profile", "xlbomd_selftest_gemm",
+            "xlbomd_destroy", "xlbomd_last_error",
             "xlbomd_version")
 
 
@@ -115,6 +118,16 @@ def _c(a, shape=None):
     if shape is not None:
         a = a.reshape(shape)
     return a
+
+
+def selftest_gemm(A, B, precision=FP64, sym=False):
+    """C = A B through the library's MFMA product kernel (test hook)."""
+    A, B = _c(A), _c(B)
+    n = A.shape[0]
+    C = np.zeros((n, n))
+    _check(lib().xlbomd_selftest_gemm(n, precision, 1 if sym else 0,
+                                      _ptr(A), _ptr(B), _ptr(C)))
+    return C
 
 
 def step_batch(systems, n_steps=1):

@@ -28,6 +28,9 @@ template <> struct MF<float> {
     static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    // row within the 16x16 block of accumulator element r of lane group g
+    // (g = lane / 16; the column is lane % 16)
+    static __device__ __forceinline__ int out_row(int g, int r) { return 4 * g + r; }
 };
 template <> struct MF<double> {
     using acc_t = f64x4;
@@ -36,6 +39,8 @@ template <> struct MF<double> {
     static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    // the FP64 instruction interleaves: element r of lane group g is row 4r + g
+    static __device__ __forceinline__ int out_row(int g, int r) { return 4 * r + g; }
 };
 
 // C = alpha * sum_s A_s^T B_s + beta * X + beta2 * X2 + gamma * I ; optionally
@@ -148,7 +153,8 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(GemmArgs<T> p) {
         __syncthreads();
     }
 
-    // epilogue: lane (fr, fc) of block (x, y) holds rows 4 fr + r, column fc
+    // epilogue: lane (fr, fc) of block (x, y) holds rows M::out_row(fr, r),
+    // column fc
     T *C = p.C + bz * p.sC;
     T *C2 = p.C2 ? p.C2 + bz * p.sC2 : nullptr;
     const T *X = p.X ? p.X + bz * p.sX : nullptr;
@@ -159,7 +165,7 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(GemmArgs<T> p) {
         for (int y = 0; y < 4; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = i0 + wr * 64 + x * 16 + 4 * fr + r;
+                const int row = i0 + wr * 64 + x * 16 + M::out_row(fr, r);
                 const int col = j0 + wc * 64 + y * 16 + fc;
                 const long o = (long)row * ld + col;
                 T val = p.alpha * acc[x][y][r];

@@ -34,6 +34,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <atomic>
@@ -47,6 +48,11 @@ using namespace xl;
 namespace {
 
 thread_local std::string g_err;
+
+bool debug() {
+    static const bool on = std::getenv("XLBOMD_DEBUG") != nullptr;
+    return on;
+}
 
 // Table I: kappa, alpha and c_0..c_K of the dissipative term of Eq. 23.
 struct DampRow {
@@ -308,10 +314,14 @@ struct SysBase {
         for (int it = 0;; ++it) {
             mu0 = std::min(std::max(mu0, elo), ehi);
             foe(mu0);
-            XL_HIP(hipMemcpyAsync(hscal, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+            XL_HIP(hipMemcpyAsync(hscal, scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
             sync();
             trd = hscal[0];
             dmu = hscal[2];   // root of the quadratic model of the count
+            if (debug())
+                std::fprintf(stderr, "[xlbomd] solve it %d mu0 %.10f elo %.6f ehi %.6f L %d "
+                             "N0 %.10f dN %.6e dmu %.3e d2N %.6e\n", it, mu0, elo, ehi, L,
+                             hscal[0], hscal[1], hscal[2], hscal[3]);
             if (!std::isfinite(dmu)) throw Diverged("non-finite chemical potential step");
             if (beta * std::fabs(dmu) <= tau) break;
             if (it >= 60) throw NoConv("chemical potential did not converge");
@@ -1093,6 +1103,34 @@ int xlbomd_profile(xlbomd_system *h, int32_t enable, double *out) {
                 if (acc[p][2] == 0.0) acc[p][3] = 0.0;
                 for (int k = 0; k < 5; ++k) out[5 * p + k] = acc[p][k];
             }
+    });
+}
+
+int xlbomd_selftest_gemm(int32_t n, int32_t precision, int32_t sym, const double *A,
+                         const double *B, double *C) {
+    if (n <= 0 || n % 128 || !A || !B || !C) return fail(XLBOMD_E_INVALID, "bad self-test args");
+    return guarded([&] {
+        const size_t nn = (size_t)n * n;
+        double *dA = dalloc<double>(nn), *dB = dalloc<double>(nn), *dC = dalloc<double>(nn);
+        DevFree fr;
+        fr.ptrs = {dA, dB, dC};
+        XL_HIP(hipMemcpy(dA, A, nn * 8, hipMemcpyHostToDevice));
+        XL_HIP(hipMemcpy(dB, B, nn * 8, hipMemcpyHostToDevice));
+        auto go = [&](auto tag) {
+            using T = decltype(tag);
+            T *a = dalloc<T>(nn), *b = dalloc<T>(nn), *c = dalloc<T>(nn);
+            fr.ptrs.push_back(a); fr.ptrs.push_back(b); fr.ptrs.push_back(c);
+            const int g = ceil_div((long)nn, 256);
+            hipLaunchKernelGGL((convert_kernel<double, T>), dim3(g), dim3(256), 0, 0, (long)nn, dA, 1.0, a);
+            hipLaunchKernelGGL((convert_kernel<double, T>), dim3(g), dim3(256), 0, 0, (long)nn, dB, 1.0, b);
+            GemmArgs<T> ga;
+            ga.n = n; ga.ld = n; ga.A0 = a; ga.B0 = b; ga.C = c;
+            gemm(ga, sym != 0, 0);
+            hipLaunchKernelGGL((convert_kernel<T, double>), dim3(g), dim3(256), 0, 0, (long)nn, c, 1.0, dC);
+        };
+        if (precision == XLBOMD_FP64) go(double{}); else go(float{});
+        XL_HIP(hipDeviceSynchronize());
+        XL_HIP(hipMemcpy(C, dC, nn * 8, hipMemcpyDeviceToHost));
     });
 }
 
