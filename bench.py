@@ -46,7 +46,7 @@ def time_path(system, precision, steps, warmup, label):
     from paper_1705_10845_amd import XLBOMD
     t0 = time.perf_counter()
     g = XLBOMD(system, precision=precision, stream=_stream(),
-               scf_tol=1e-6 if precision == 1 else 1e-9)
+               scf_tol=2e-5 if precision == 1 else 1e-9)
     t_init = time.perf_counter() - t0
     print(f"[bench] {label}: init (SCF) {t_init:.1f}s", file=sys.stderr, flush=True)
     if warmup:

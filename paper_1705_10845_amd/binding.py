@@ -83,6 +83,7 @@ def lib():
         L.xlbomd_profile.argtypes = [vp, ctypes.c_int32, _dp]
         L.xlbomd_selftest_gemm.argtypes = [ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_int32, _dp, _dp, _dp]
+        L.xlbomd_selftest_gemm_time.argtypes = [ctypes.c_int32] * 5 + [_dp]
         L.xlbomd_destroy.argtypes = [vp]
         L.xlbomd_destroy.restype = None
         L.xlbomd_last_error.restype = ctypes.c_char_p
@@ -96,7 +97,7 @@ EXPORTED = ("xlbomd_init_system", "xlbomd_step", "xlbomd_step_batch",
             "xlbomd_forces", "xlbomd_get_charges", "xlbomd_set_state",
             "xlbomd_get_state", "xlbomd_solve", "xlbomd_response",
             "xlbomd_kernel_apply", "xlbomd_profile", "xlbomd_selftest_gemm",
-            "xlbomd_destroy", "xlbomd_last_error",
+            "xlbomd_selftest_gemm_time", "xlbomd_destroy", "xlbomd_last_error",
             "xlbomd_version")
 
 
@@ -128,6 +129,14 @@ def selftest_gemm(A, B, precision=FP64, sym=False):
     _check(lib().xlbomd_selftest_gemm(n, precision, 1 if sym else 0,
                                       _ptr(A), _ptr(B), _ptr(C)))
     return C
+
+
+def selftest_gemm_time(n, precision=FP64, sym=False, dual=False, reps=10):
+    """Milliseconds per launch of the product kernel (benchmark hook)."""
+    out = np.zeros(1)
+    _check(lib().xlbomd_selftest_gemm_time(n, precision, int(sym), int(dual),
+                                           reps, _ptr(out)))
+    return float(out[0])
 
 
 def step_batch(systems, n_steps=1):

@@ -558,7 +558,23 @@ template <typename TF, typename TR> struct Sys : SysBase {
         bcap = nb;
     }
 
-    template <typename U> void run_gemm(const GemmArgs<U> &a, bool sym) {
+    // split-k workspace per precision (allocated on first use)
+    void *ws_d = nullptr, *ws_f = nullptr;
+    long ws_dn = 0, ws_fn = 0;
+    template <typename U> void attach_ws(GemmArgs<U> &a) {
+        void *&w = sizeof(U) == 8 ? ws_d : ws_f;
+        long &wn = sizeof(U) == 8 ? ws_dn : ws_fn;
+        if (!w) {
+            wn = std::max(split_ws_elems<U>(Np, true, 1, 1), split_ws_elems<U>(Np, false, 1, 1));
+            w = dalloc<U>(wn);
+            mem.ptrs.push_back(w);
+        }
+        a.ws = (U *)w;
+        a.ws_elems = wn;
+    }
+
+    template <typename U> void run_gemm(GemmArgs<U> a, bool sym) {
+        attach_ws(a);
         prof_begin();
         gemm(a, sym, st);
         prof_end(gemm_flops(sym, a.A1 ? 2 : 1) * a.batch, sizeof(U) == 8);
@@ -1125,12 +1141,52 @@ int xlbomd_selftest_gemm(int32_t n, int32_t precision, int32_t sym, const double
             hipLaunchKernelGGL((convert_kernel<double, T>), dim3(g), dim3(256), 0, 0, (long)nn, dB, 1.0, b);
             GemmArgs<T> ga;
             ga.n = n; ga.ld = n; ga.A0 = a; ga.B0 = b; ga.C = c;
+            ga.ws_elems = split_ws_elems<T>(n, sym != 0, 0, 1);
+            ga.ws = dalloc<T>(ga.ws_elems);
+            fr.ptrs.push_back(ga.ws);
             gemm(ga, sym != 0, 0);
             hipLaunchKernelGGL((convert_kernel<T, double>), dim3(g), dim3(256), 0, 0, (long)nn, c, 1.0, dC);
         };
         if (precision == XLBOMD_FP64) go(double{}); else go(float{});
         XL_HIP(hipDeviceSynchronize());
         XL_HIP(hipMemcpy(C, dC, nn * 8, hipMemcpyDeviceToHost));
+    });
+}
+
+int xlbomd_selftest_gemm_time(int32_t n, int32_t precision, int32_t sym, int32_t dual,
+                              int32_t reps, double *ms_per_launch) {
+    if (n <= 0 || n % 128 || reps <= 0 || !ms_per_launch)
+        return fail(XLBOMD_E_INVALID, "bad self-test args");
+    return guarded([&] {
+        const size_t nn = (size_t)n * n;
+        DevFree fr;
+        auto go = [&](auto tag) {
+            using T = decltype(tag);
+            T *a = dalloc<T>(nn), *b = dalloc<T>(nn), *c = dalloc<T>(nn);
+            fr.ptrs = {a, b, c};
+            XL_HIP(hipMemset(a, 0, nn * sizeof(T)));
+            XL_HIP(hipMemset(b, 0, nn * sizeof(T)));
+            GemmArgs<T> ga;
+            ga.n = n; ga.ld = n; ga.A0 = a; ga.B0 = b; ga.C = c;
+            if (dual) { ga.A1 = b; ga.B1 = a; }
+            ga.ws_elems = split_ws_elems<T>(n, sym != 0, dual, 1);
+            ga.ws = dalloc<T>(ga.ws_elems);
+            fr.ptrs.push_back(ga.ws);
+            gemm(ga, sym != 0, 0);
+            hipEvent_t e0, e1;
+            XL_HIP(hipEventCreate(&e0));
+            XL_HIP(hipEventCreate(&e1));
+            XL_HIP(hipEventRecord(e0, 0));
+            for (int r = 0; r < reps; ++r) gemm(ga, sym != 0, 0);
+            XL_HIP(hipEventRecord(e1, 0));
+            XL_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            XL_HIP(hipEventElapsedTime(&ms, e0, e1));
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            *ms_per_launch = ms / reps;
+        };
+        if (precision == XLBOMD_FP64) go(double{}); else go(float{});
     });
 }
 

@@ -13,7 +13,7 @@ def B():
     return binding
 
 
-@pytest.mark.parametrize("n", [128, 256, 384])
+@pytest.mark.parametrize("n", [128, 256, 384, 1024])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("sym", [False, True])
 def test_gemm(B, n, prec, sym):
