@@ -593,7 +593,9 @@ template <typename TF, typename TR> struct Sys : SysBase {
 
     void foe(double mu0) override {
         const double xmax = beta * std::max(std::fabs(elo - mu0), std::fabs(ehi - mu0)) * 1.02 + 1e-12;
-        L = choose_levels(xmax, 2e-10);
+        // truncation bound of the expansion vs the Fermi function: 2e-10 for
+        // the all-FP64 mode, 1e-9 (charges within 1e-8) otherwise
+        L = choose_levels(xmax, d.precision == XLBOMD_FP64 ? 2e-10 : 1e-9);
         alloc_matrices(L);
         Lr = -1;
         sc = std::ldexp(beta, -(L + 1));
@@ -612,20 +614,42 @@ template <typename TF, typename TR> struct Sys : SysBase {
             a.C = Z[0];
             run_gemm(a, true);
         }
-        const double nstol = (sizeof(TF) == 8) ? 2e-16 : 1e-8;
+        // Newton-Schulz target per level: far below the truncation bound
+        const double nstol = (sizeof(TF) == 8) ? 1e-12 : 1e-8;
         double t = t0max;
         for (int k = 0; k < L; ++k) {
-            const double b = t * t;            // spectrum of A_k within [1, 1 + b]
-            const double c = 2.0 + b, den = 2.0 * c * c - b * b;
-            const double al = 8.0 * c / den, ga = -8.0 / den;
-            double e = b * b / den;
-            int ns = 0;
-            while (e > nstol && ns < 8) { e = e * e; ++ns; }
+            // spectrum of A_k within [1, 1 + b]; Chebyshev-optimal first
+            // guesses of degree 1 (residual b^2/(2c^2 - b^2), free in the
+            // epilogue of Z^2) or degree 2 (residual 1/|T3(u0)|, one GEMM)
+            const double b = t * t, c = 2.0 + b;
+            const double den = 2.0 * c * c - b * b;
+            auto steps = [&](double e) {
+                int ns = 0;
+                while (e > nstol && ns < 10) { e = e * e; ++ns; }
+                return ns;
+            };
+            const int ns1 = steps(b * b / den);
+            const double al = 2.0 / b, be = -c / b;
+            const double D3 = 4.0 * be * be * be - 3.0 * be;
+            const int ns2 = b > 0.0 ? steps(1.0 / std::fabs(D3)) : ns1;
+            const bool quad = (1 + 2 * ns2) < 2 * ns1;
+            const int ns = quad ? ns2 : ns1;
             ns_total += ns;
             auto a = base<TF>();
             a.A0 = Z[k]; a.B0 = Z[k]; a.alpha = (TF)4.0; a.gamma = (TF)1.0; a.C = Am;
-            a.C2 = Yk[k]; a.p0 = (TF)al; a.p1 = (TF)ga;
+            if (!quad) {
+                a.C2 = Yk[k]; a.p0 = (TF)(8.0 * c / den); a.p1 = (TF)(-8.0 / den);
+            }
             run_gemm(a, true);
+            if (quad) {
+                // Y = p0 I + p1 A + p2 A^2,  p(a) = (1 - T3(u(a))/T3(u0)) / a
+                auto q = base<TF>();
+                q.A0 = Am; q.B0 = Am; q.C = Yk[k];
+                q.alpha = (TF)(-4.0 * al * al * al / D3);
+                q.X = Am; q.beta = (TF)(-12.0 * al * al * be / D3);
+                q.gamma = (TF)(-(12.0 * al * be * be - 3.0 * al) / D3);
+                run_gemm(q, true);
+            }
             for (int j = 0; j < ns; ++j) {
                 auto e1 = base<TF>();   // E = 2I - A Y
                 e1.A0 = Am; e1.B0 = Yk[k]; e1.alpha = (TF)-1.0; e1.gamma = (TF)2.0; e1.C = E;
