@@ -134,8 +134,9 @@ __device__ __forceinline__ void epilogue(const GemmArgs<T> &p, long bz, int ti, 
 
 
 template <typename T, bool SYM>
-__global__ __launch_bounds__(256) void gemm_tn_kernel(GemmArgs<T> p, int ntiles, int per_xcd,
-                                                      int nsplit) {
+__global__ __launch_bounds__(256) void gemm_tn_kernel(GemmArgs<T> p, int ntiles, int nfull,
+                                                      int nsplit, int per_xcd) {
+    // per_xcd: tail units per XCD
     using M = MF<T>;
     using acc_t = typename M::acc_t;
     using vec_t = typename M::vec_t;
@@ -149,11 +150,27 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(GemmArgs<T> p, int ntiles,
 
     // XCD-aware remap: block b runs on XCD b % NXCD; give each XCD a
     // contiguous run of tiles
-    // unit = (tile, k-split); the splits of one tile are consecutive units
+    // units: tiles [0, nfull) whole, then each remaining tile as nsplit
+    // k-range units (filling the last round of workgroups).  Blocks are
+    // dispatched in order, whole tiles first; within each region every XCD
+    // (block b runs on XCD b % NXCD) gets a contiguous run of units.
     const int b = blockIdx.x;
-    const int unit = (b % NXCD) * per_xcd + b / NXCD;
-    if (unit >= ntiles * nsplit) return;
-    const int u = unit / nsplit, split = unit % nsplit;
+    const int ntail = ntiles - nfull;
+    const int nfull_pad = ((nfull + NXCD - 1) / NXCD) * NXCD;
+    int unit;
+    if (b < nfull_pad) {
+        unit = (b % NXCD) * (nfull_pad / NXCD) + b / NXCD;
+        if (unit >= nfull) return;
+    } else {
+        const int bb = b - nfull_pad;
+        unit = nfull + (bb % NXCD) * per_xcd + bb / NXCD;
+        if (unit >= nfull + ntail * nsplit) return;
+    }
+    const bool part = unit >= nfull;
+    const int w = unit - nfull;                         // tail unit index
+    const int u = part ? nfull + w / nsplit : unit;
+    const int split = part ? w % nsplit : 0;
+    const int ns = part ? nsplit : 1;
     const int nt = p.n / GT;
     int ti, tj;
     tile_of<SYM>(u, nt, ti, tj);
@@ -175,8 +192,8 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(GemmArgs<T> p, int ntiles,
 
     const int nk1 = p.n / BK;
     const int nktot = A1 ? 2 * nk1 : nk1;
-    const int kt0 = (int)((long)nktot * split / nsplit);
-    const int kt1 = (int)((long)nktot * (split + 1) / nsplit);
+    const int kt0 = (int)((long)nktot * split / ns);
+    const int kt1 = (int)((long)nktot * (split + 1) / ns);
 
     // NV 16-byte vectors of A and NV of B per thread per k-tile
     vec_t ra[NV], rb[NV];
@@ -238,15 +255,15 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(GemmArgs<T> p, int ntiles,
         __syncthreads();
     }
 
-    if (nsplit > 1) {
-        // partial tile: each thread stores its 64 accumulators contiguously
-        T *w = p.ws + ((long)bz * ntiles * nsplit + unit) * (GT * GT) + (long)tid * 64;
+    if (part) {
+        // partial tile: accumulator block g = 4x + y of thread tid as one
+        // 4-vector at [(g * 256 + tid) * 4] (vector stores, contiguous
+        // across the workgroup)
+        acc_t *wp = reinterpret_cast<acc_t *>(p.ws + ((long)bz * ntail * nsplit + w) * (GT * GT)) + tid;
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-            for (int y = 0; y < 4; ++y)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) w[(x * 4 + y) * 4 + r] = acc[x][y][r];
+            for (int y = 0; y < 4; ++y) wp[(x * 4 + y) * 256] = acc[x][y];
         return;
     }
 
@@ -257,9 +274,11 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(GemmArgs<T> p, int ntiles,
 // thread layout as the product kernel, so every thread reads back exactly
 // the accumulators its counterpart wrote (contiguous 64 per thread).
 template <typename T, bool SYM>
-__global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs<T> p, int ntiles, int nsplit) {
+__global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs<T> p, int ntiles, int nfull,
+                                                         int nsplit) {
     using acc_t = typename MF<T>::acc_t;
-    const int u = blockIdx.x;
+    const int ntail = ntiles - nfull;
+    const int u = nfull + blockIdx.x;
     const long bz = blockIdx.z;
     const int nt = p.n / GT;
     int ti, tj;
@@ -272,14 +291,13 @@ __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs<T> p, int ntil
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
     for (int s = 0; s < nsplit; ++s) {
-        const T *w = p.ws + ((long)bz * ntiles * nsplit + (long)u * nsplit + s) * (GT * GT) +
-                     (long)tid * 64;
+        const acc_t *wp = reinterpret_cast<const acc_t *>(
+                              p.ws + ((long)bz * ntail * nsplit + (long)blockIdx.x * nsplit + s) *
+                                         (GT * GT)) + tid;
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-            for (int y = 0; y < 4; ++y)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) acc[x][y][r] += w[(x * 4 + y) * 4 + r];
+            for (int y = 0; y < 4; ++y) acc[x][y] += wp[(x * 4 + y) * 256];
     }
     epilogue<T, SYM>(p, bz, ti, tj, wr, wc, fr, fc, acc);
 }
@@ -296,29 +314,47 @@ inline int device_cus() {
     return cus;
 }
 
-// Number of k-splits for a launch: the smallest split count whose last
-// round of workgroups is nearly full (the product kernels run one (FP64) or
-// two (FP32) workgroups per CU).
-template <typename T> int choose_split(int ntiles, int nkt, long batch) {
-    const long slots = (long)device_cus() * (sizeof(T) == 8 ? 1 : 2);
+// Work schedule of one launch.  FP64 runs one workgroup per CU: when the
+// tiles exceed one round, whole tiles fill complete rounds and only the
+// tiles of the last partial round are split along k over the idle CUs.
+// Otherwise (FP32: two workgroups per CU, or fewer tiles than slots) every
+// tile is split into the same number of k-ranges, the smallest count whose
+// last round is nearly full; the small units also balance dynamically.
+// Split partial tiles are summed by a fix-up kernel.  Batched launches have
+// tiles enough: no split.
+struct Sched {
+    int nfull, nsplit;
+};
+template <typename T> Sched schedule(int ntiles, int nkt, long batch) {
+    const bool f64 = sizeof(T) == 8;
+    const long slots = (long)device_cus() * (f64 ? 1 : 2);
+    if (batch > 1) return {ntiles, 1};
+    if (f64 && ntiles > slots) {
+        const long rounds = ntiles / slots;
+        const int tail = (int)(ntiles - rounds * slots);
+        if (tail == 0) return {ntiles, 1};
+        const int s = (int)std::min<long>(slots / tail, nkt / 8);
+        if (s < 2) return {ntiles, 1};
+        return {(int)(rounds * slots), s};
+    }
     double best = -1.0;
     int bs = 1;
     for (int s : {1, 2, 3, 4, 6, 8}) {
         if (s > 1 && nkt / s < 8) break;
-        const double units = (double)ntiles * s * batch;
+        const double units = (double)ntiles * s;
         const double rounds = std::ceil(units / slots);
-        double eff = units / (rounds * slots);
-        eff *= 1.0 - 0.01 * (s - 1);          // partial-tile traffic
+        const double eff = units / (rounds * slots) * (1.0 - 0.01 * (s - 1));
         if (eff > best + 1e-9) { best = eff; bs = s; }
     }
-    return bs;
+    return {bs > 1 ? 0 : ntiles, bs};
 }
 
 template <typename T> long split_ws_elems(int n, bool sym, int dual, long batch) {
     const int nt = n / GT;
     const int ntiles = sym ? nt * (nt + 1) / 2 : nt * nt;
     const int nkt = (n / MF<T>::BK) * (dual ? 2 : 1);
-    return (long)ntiles * choose_split<T>(ntiles, nkt, batch) * batch * GT * GT;
+    const Sched s = schedule<T>(ntiles, nkt, batch);
+    return std::max(1L, (long)(ntiles - s.nfull) * s.nsplit * batch * GT * GT);
 }
 
 template <typename T>
@@ -328,22 +364,28 @@ void gemm(const GemmArgs<T> &a, bool sym, hipStream_t st) {
     const int nt = a.n / GT;
     const int ntiles = sym ? nt * (nt + 1) / 2 : nt * nt;
     const int nkt = (a.n / MF<T>::BK) * (a.A1 ? 2 : 1);
-    int nsplit = a.ws ? choose_split<T>(ntiles, nkt, a.batch) : 1;
-    if (nsplit > 1 && (long)ntiles * nsplit * a.batch * GT * GT > a.ws_elems) nsplit = 1;
-    const int units = ntiles * nsplit;
-    const int per = (units + NXCD - 1) / NXCD;
-    dim3 grid(per * NXCD, 1, a.batch);
+    Sched s = a.ws ? schedule<T>(ntiles, nkt, a.batch) : Sched{ntiles, 1};
+    if (s.nsplit > 1 && (long)(ntiles - s.nfull) * s.nsplit * a.batch * GT * GT > a.ws_elems)
+        s = Sched{ntiles, 1};
+    const int nfull_pad = ((s.nfull + NXCD - 1) / NXCD) * NXCD;
+    const int tail_units = (ntiles - s.nfull) * s.nsplit;
+    const int per = (tail_units + NXCD - 1) / NXCD;     // tail units per XCD
+    dim3 grid(nfull_pad + per * NXCD, 1, a.batch);
     if (sym)
-        hipLaunchKernelGGL((gemm_tn_kernel<T, true>), grid, dim3(256), 0, st, a, ntiles, per, nsplit);
+        hipLaunchKernelGGL((gemm_tn_kernel<T, true>), grid, dim3(256), 0, st, a, ntiles, s.nfull,
+                           s.nsplit, per);
     else
-        hipLaunchKernelGGL((gemm_tn_kernel<T, false>), grid, dim3(256), 0, st, a, ntiles, per, nsplit);
+        hipLaunchKernelGGL((gemm_tn_kernel<T, false>), grid, dim3(256), 0, st, a, ntiles, s.nfull,
+                           s.nsplit, per);
     XL_LAUNCH_CHECK();
-    if (nsplit > 1) {
-        dim3 g2(ntiles, 1, a.batch);
+    if (s.nfull < ntiles) {
+        dim3 g2(ntiles - s.nfull, 1, a.batch);
         if (sym)
-            hipLaunchKernelGGL((gemm_fixup_kernel<T, true>), g2, dim3(256), 0, st, a, ntiles, nsplit);
+            hipLaunchKernelGGL((gemm_fixup_kernel<T, true>), g2, dim3(256), 0, st, a, ntiles,
+                               s.nfull, s.nsplit);
         else
-            hipLaunchKernelGGL((gemm_fixup_kernel<T, false>), g2, dim3(256), 0, st, a, ntiles, nsplit);
+            hipLaunchKernelGGL((gemm_fixup_kernel<T, false>), g2, dim3(256), 0, st, a, ntiles,
+                               s.nfull, s.nsplit);
         XL_LAUNCH_CHECK();
     }
 }
