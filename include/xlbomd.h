@@ -119,9 +119,10 @@ typedef struct {
  * computes F(t0) and the kernel at t0.  On success *out owns the handle. */
 int xlbomd_init_system(const xlbomd_desc *desc, xlbomd_system **out);
 
-/* Advance n_steps XL-BOMD steps (Eqs. 22-23).  If last != NULL the report
- * of the final step is written (with energies if that step evaluated
- * them).  Returns XLBOMD_E_DIVERGED if a non-finite value or a residual
+/* Advance n_steps XL-BOMD steps (Eqs. 22-23).  The free energy is
+ * evaluated on steps whose index is a multiple of desc.energy_every.  If
+ * last != NULL the report of the final step is written (its energy fields
+ * are valid when has_energy is 1; xlbomd_forces evaluates them on demand).  Returns XLBOMD_E_DIVERGED if a non-finite value or a residual
  * above 1e3 appears; the state is then the last good step. */
 int xlbomd_step(xlbomd_system *h, int32_t n_steps, xlbomd_report *last);
 

@@ -134,7 +134,7 @@ __device__ __forceinline__ void epilogue(const GemmArgs<T> &p, long bz, int ti, 
 
 
 template <typename T, bool SYM>
-__global__ __launch_bounds__(256) void gemm_tn_kernel(GemmArgs<T> p, int ntiles, int nfull,
+__global__ __launch_bounds__(256, 2) void gemm_tn_kernel(GemmArgs<T> p, int ntiles, int nfull,
                                                       int nsplit, int per_xcd) {
     // per_xcd: tail units per XCD
     using M = MF<T>;
@@ -314,22 +314,20 @@ inline int device_cus() {
     return cus;
 }
 
-// Work schedule of one launch.  FP64 runs one workgroup per CU: when the
-// tiles exceed one round, whole tiles fill complete rounds and only the
-// tiles of the last partial round are split along k over the idle CUs.
-// Otherwise (FP32: two workgroups per CU, or fewer tiles than slots) every
-// tile is split into the same number of k-ranges, the smallest count whose
-// last round is nearly full; the small units also balance dynamically.
-// Split partial tiles are summed by a fix-up kernel.  Batched launches have
-// tiles enough: no split.
+// Work schedule of one launch (two workgroups per CU for both precisions).
+// More tiles than workgroup slots: whole tiles fill complete rounds and only
+// the tiles of the last, partial round are split along k over the
+// otherwise idle slots.  Fewer tiles than slots: every tile is split into
+// the same number of k-ranges, the smallest count whose round is nearly
+// full.  Split partial tiles are summed by a fix-up kernel.  Batched
+// launches have tiles enough: no split.
 struct Sched {
     int nfull, nsplit;
 };
 template <typename T> Sched schedule(int ntiles, int nkt, long batch) {
-    const bool f64 = sizeof(T) == 8;
-    const long slots = (long)device_cus() * (f64 ? 1 : 2);
+    const long slots = (long)device_cus() * 2;
     if (batch > 1) return {ntiles, 1};
-    if (f64 && ntiles > slots) {
+    if (ntiles > slots) {
         const long rounds = ntiles / slots;
         const int tail = (int)(ntiles - rounds * slots);
         if (tail == 0) return {ntiles, 1};

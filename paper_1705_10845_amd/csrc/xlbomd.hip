@@ -941,7 +941,7 @@ int xlbomd_step(xlbomd_system *h, int32_t n_steps, xlbomd_report *last) {
         for (int i = 0; i < n_steps; ++i) {
             const int ev = s.d.energy_every;
             const bool is_last = (i + 1 == n_steps);
-            const bool want = (ev > 0 && ((s.step_no + 1) % ev == 0)) || (is_last && last);
+            const bool want = ev > 0 && ((s.step_no + 1) % ev == 0);
             s.md_step(want, is_last ? last : nullptr);
         }
         s.sync();
