@@ -264,6 +264,9 @@ def jacobian(model, el):
     return J
 
 
+R_FLOOR = 1e-8     # RMS residual below which the kernel is K0
+
+
 @dataclass
 class KernelResult:
     K: np.ndarray          # explicit N_at x N_at kernel K_m
@@ -281,7 +284,8 @@ def _orth(x, V):
     return y, nrm
 
 
-def kernel_sm(model, el, gamma, m, mode=0, v_prev=None, resp=None):
+def kernel_sm(model, el, gamma, m, mode=0, v_prev=None, resp=None,
+              floor=R_FLOOR):
     """Rank-m kernel by the Sherman-Morrison sequence (Eq. 50).
 
     K0 = -gamma I, i.e. J0 = (1 - 1/gamma) I (Eqs. 48-49).  Directions:
@@ -290,7 +294,11 @@ def kernel_sm(model, el, gamma, m, mode=0, v_prev=None, resp=None):
       mode 1: v_1 as above, then the previous build's directions
               v_prev[:, 0..m-2], orthogonalised in that order.
     A direction whose orthogonalised norm falls below 1e-10 of its raw norm
-    ends the sequence (the space is exhausted).  `resp` overrides the
+    ends the sequence (the space is exhausted).  For a kernel that the
+    dynamics will apply to later residuals, a residual with RMS at or below
+    `floor` gives the rank-0 kernel K0: its direction is rounding noise
+    (e.g. right after a converged SCF).  The SCF, which applies each kernel
+    to the residual that built it, passes floor = 0.  `resp` overrides the
     response function (defaults to the closed-form canonical response).
     """
     nat = model.nat
@@ -309,6 +317,8 @@ def kernel_sm(model, el, gamma, m, mode=0, v_prev=None, resp=None):
             cand = K @ r
         raw = np.linalg.norm(cand)
         if raw == 0.0:
+            break
+        if i == 0 and raw / (gamma * np.sqrt(nat)) <= floor:
             break
         v, nrm = _orth(cand, Vs)
         if nrm <= 1e-10 * raw:
@@ -353,7 +363,7 @@ def scf(model, pos, gamma, m, tol=1e-10, max_iter=200, n0=None,
         hist.append(rms)
         if rms <= tol:
             return el, hist
-        kr = kernel_sm(model, el, gamma, m, mode=0)
+        kr = kernel_sm(model, el, gamma, m, mode=0, floor=0.0)
         n = n - kr.K @ el.r
     raise RuntimeError(f"SCF did not converge: {hist[-5:]}")
 

@@ -350,7 +350,10 @@ struct SysBase {
     }
 
     // ---- low-rank kernel (Eqs. 48-51) at the last solve, applied to r ----
-    int build_kernel(int m, int mode, bool use_prev) {
+    // floor: a kernel for the dynamics (applied to later residuals) is K0
+    // when the residual's RMS is at or below 1e-8 (its direction is rounding
+    // noise); the SCF applies each kernel to its own residual (no floor).
+    int build_kernel(int m, int mode, bool use_prev, bool floor = true) {
         m = std::min(m, mcap);
         if (d.kernel_rank <= 0) m = 0;
         const double gam = d.k0_gamma;
@@ -362,7 +365,8 @@ struct SysBase {
             XL_LAUNCH_CHECK();
             XL_HIP(hipMemcpyAsync(hscal + 24, scal + 24, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
             sync();
-            if (hscal[24 + 1] > 0.0) rank = 1;
+            const double rms_r = hscal[24] / (gam * std::sqrt((double)nat));
+            if (hscal[24 + 1] > 0.0 && (!floor || rms_r > 1e-8)) rank = 1;
         }
         if (rank > 0 && mode == 1) {
             // block mode: v_1 plus the previous build's directions,
@@ -491,7 +495,7 @@ struct SysBase {
             if (scf_iters >= maxit) throw NoConv("initial SCF did not reach the tolerance");
             // n <- n - K_j (q[n] - n), fresh rank-m kernel each iteration
             rank_prev = 0;
-            build_kernel(d.kernel_rank, 0, false);
+            build_kernel(d.kernel_rank, 0, false, false);
             apply_kernel(r, vtmp);
             hipLaunchKernelGGL(axpy_kernel, dim3(ceil_div(nat, 256)), dim3(256), 0, st, nat, -1.0,
                                vtmp, ncur);
@@ -1106,7 +1110,7 @@ int xlbomd_kernel_apply(xlbomd_system *h, int32_t rank, const double *rr, double
         if (rank < 0 || rank > s.mcap) throw InvalidArg("rank above capacity");
         XL_HIP(hipMemcpyAsync(s.r, rr, s.nat * sizeof(double), hipMemcpyHostToDevice, s.st));
         s.rank_prev = 0;
-        s.build_kernel(rank, 0, false);
+        s.build_kernel(rank, 0, false, false);
         s.apply_kernel(s.r, s.vtmp);
         XL_HIP(hipMemcpyAsync(kr_out, s.vtmp, s.nat * sizeof(double), hipMemcpyDeviceToHost, s.st));
         s.sync();

@@ -354,3 +354,12 @@ def test_no_systematic_energy_drift():
     slope = np.polyfit(t, et, 1)[0]
     assert abs(slope) * len(et) < 2.0 * et.std() + 1e-6
     assert et.std() < 1e-2
+
+
+def test_kernel_of_a_zero_residual_is_K0():
+    # the direction of a numerically zero residual is noise: rank-0 kernel
+    m, s, el = _small_case()
+    el.q = el.n + 1e-12 * np.random.default_rng(0).standard_normal(m.nat)
+    k = R.kernel_sm(m, el, 0.2, 3)
+    assert k.rank == 0
+    assert np.allclose(k.K, -0.2 * np.eye(m.nat))
