@@ -97,6 +97,25 @@ def cpu_baseline(n_atoms=128):
                       f"of the same model took {dt:.2f}s; scaled by (4096/{m.N})^3"}
 
 
+def serving(n_requests=256, slots=16, budget_gib=96):
+    """The serving workload: Poisson stream (200/s) of independent systems,
+    16-512 atoms x 4 orbitals, Te U[0.02, 0.1], rank 2-6, 100 steps each,
+    admitted by HBM footprint; MIXED path."""
+    from synth import serving_stream
+    from paper_1705_10845_amd.serve import Server
+    from paper_1705_10845_amd import MIXED
+    stream = serving_stream(n_requests)
+    srv = Server(hbm_budget=budget_gib << 30, max_slots=slots, precision=MIXED, steps=100,
+                 verbose=True)
+    stats, summ = srv.run(stream)
+    if summ["errors"]:
+        print("[bench] serving errors:", [s.error for s in stats if s.error][:3], file=sys.stderr)
+    summ["slots"] = slots
+    summ["workload"] = (f"{n_requests} systems, 16-512 atoms x 4 orbitals (log-uniform), "
+                        "Poisson 200/s, Te U[0.02,0.1], rank U{2..6}, 100 steps each, MIXED")
+    return summ
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +125,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serving", action="store_true",
+                    help="also run the serving workload (p50/p99 step latency)")
+    ap.add_argument("--serving-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the hot path is single-GPU "
@@ -116,6 +138,12 @@ def main():
     from synth import make_system
     from paper_1705_10845_amd import FP32, FP64, MIXED
     s = make_system("c2")
+    if args.serving_only:
+        t0 = time.perf_counter()
+        summ = serving()
+        summ["wall_total_s"] = time.perf_counter() - t0
+        print(json.dumps({"serving": summ}), flush=True)
+        return
 
     mixed = time_path(s, MIXED, args.steps, args.warmup, "mixed")
     fp64 = None if args.no_fp64 else time_path(s, FP64, args.fp64_steps, 1, "fp64")
@@ -171,6 +199,8 @@ def main():
         out["mixed_over_fp64"] = mixed["steps_per_s"] / fp64["steps_per_s"]
     if fp32 is not None:
         out["fp32"] = summary(fp32, args.steps)
+    if args.serving:
+        out["serving"] = serving()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

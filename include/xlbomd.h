@@ -89,7 +89,12 @@ typedef struct {
     int32_t kernel_rank;          /* m >= 0 (0 = K0 only), m <= n_atoms     */
     int32_t kernel_every;         /* rebuild the kernel every k steps (>=1) */
     int32_t krylov_mode;          /* 0 sequential Krylov, 1 block           */
-    double k0_gamma;              /* K0 = -k0_gamma I, in (0, 1]            */
+    double k0_gamma;              /* K0 = -k0_gamma I, in (0, 1]; 0 = choose
+                                     at init from the stiffest response mode:
+                                     20 power iterations v <- -Jv/|Jv| from
+                                     r/|r| give |lambda|, and gamma =
+                                     floor(150/(1+|lambda|))/100 in
+                                     [0.01, 1]                              */
     int32_t precision;            /* xlbomd_precision                       */
     double scf_tol;               /* RMS residual of the initial SCF        */
     int32_t scf_max_iter;
@@ -111,6 +116,7 @@ typedef struct {
     int32_t step;      /* steps taken since init                            */
     int32_t foe_levels, ns_iters, mu_reruns, scf_iters, kernel_rank;
     int32_t has_energy;/* 1 if the energy fields are valid                  */
+    double k0_gamma;   /* the K0 constant in use                            */
 } xlbomd_report;
 
 /* Create a system: copies the descriptor's arrays to the device, solves the

@@ -350,6 +350,31 @@ class State:
     energy: Dict[str, float] = field(default_factory=dict)
 
 
+AUTO_GAMMA_ITERS = 20
+
+
+def auto_gamma(model, el, iters=AUTO_GAMMA_ITERS):
+    """K0 = -gamma I with gamma from the stiffest charge-response mode.
+
+    Power iteration v <- -J v / |J v| from v = r/|r| (e_0 if r = 0) gives
+    |lambda_max(J)| ~ |J v|; gamma = floor(100 * 1.5 / (1 + |lambda|)) / 100
+    clipped to [0.01, 1] keeps every eigenvalue of K0 (J - I) below 1.5, so
+    the kernel SCF contracts and the electronic Verlet stays stable on modes
+    the low-rank update does not capture.  The 0.01 grid makes the choice
+    insensitive to rounding.
+    """
+    r = el.r
+    v = r.copy() if np.linalg.norm(r) > 0 else np.eye(model.nat)[0]
+    v = v / np.linalg.norm(v)
+    lam = 0.0
+    for _ in range(iters):
+        w = response(model, el, v)
+        lam = np.linalg.norm(w)
+        v = -w / lam
+    g = np.floor(100.0 * 1.5 / (1.0 + lam)) / 100.0
+    return float(min(1.0, max(0.01, g))), float(lam)
+
+
 def scf(model, pos, gamma, m, tol=1e-10, max_iter=200, n0=None,
         mode=0):
     """Ground state by the kernel SCF of Eq. 52, from n = 0."""
@@ -375,6 +400,9 @@ def init_state(model, pos=None, vel=None, scf_tol=1e-10, gamma=None,
     vel = _f64(s.vel if vel is None else vel).copy()
     gamma = s.k0_gamma if gamma is None else gamma
     rank = s.rank if rank is None else rank
+    if gamma <= 0.0:      # automatic stability rule at n = 0
+        gamma, _ = auto_gamma(model, electronic(model, pos, np.zeros(model.nat)))
+        model.gamma_used = gamma
     el, _ = scf(model, pos, gamma, rank, tol=scf_tol)
     hist = np.tile(el.n, (s.kmax + 1, 1))            # Eq. 20: ndot(t0) = 0
     kres = kernel_sm(model, el, gamma, rank, mode=s.krylov_mode)
@@ -395,7 +423,8 @@ def energy_report(model, st):
 def md_step(model, st, gamma=None, rank=None, want_energy=True):
     """One XL-BOMD step, t -> t + dt (Eqs. 22, 23)."""
     s = model.s
-    gamma = s.k0_gamma if gamma is None else gamma
+    if gamma is None:
+        gamma = s.k0_gamma if s.k0_gamma > 0 else model.gamma_used
     rank = s.rank if rank is None else rank
     kappa, alpha, ck = TABLE_I[s.kmax]
     dt = s.dt

@@ -311,8 +311,11 @@ struct SysBase {
         const double tau = (d.precision == XLBOMD_FP64) ? 1e-6 : 1e-3;
         reruns = 0;
         ns_total = 0;
+        // N(mu) = Tr D is strictly increasing: keep a bracket [mlo, mhi]
+        // with N(mlo) < N_e < N(mhi) and take the model step only inside it
+        double mlo = elo - 40.0 / beta, mhi = ehi + 40.0 / beta;
+        mu0 = std::min(std::max(mu0, mlo), mhi);
         for (int it = 0;; ++it) {
-            mu0 = std::min(std::max(mu0, elo), ehi);
             foe(mu0);
             XL_HIP(hipMemcpyAsync(hscal, scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
             sync();
@@ -322,12 +325,13 @@ struct SysBase {
                 std::fprintf(stderr, "[xlbomd] solve it %d mu0 %.10f elo %.6f ehi %.6f L %d "
                              "N0 %.10f dN %.6e dmu %.3e d2N %.6e\n", it, mu0, elo, ehi, L,
                              hscal[0], hscal[1], hscal[2], hscal[3]);
-            if (!std::isfinite(dmu)) throw Diverged("non-finite chemical potential step");
-            if (beta * std::fabs(dmu) <= tau) break;
+            if (!std::isfinite(trd)) throw Diverged("non-finite electron count");
+            if (trd < d.n_electrons) mlo = std::max(mlo, mu0); else mhi = std::min(mhi, mu0);
+            if (std::isfinite(dmu) && beta * std::fabs(dmu) <= tau) break;
             if (it >= 60) throw NoConv("chemical potential did not converge");
-            // damped Newton far from the root
-            const double cap = 0.25 * (ehi - elo);
-            mu0 += std::max(-cap, std::min(cap, dmu));
+            double next = mu0 + (std::isfinite(dmu) ? dmu : 0.0);
+            if (!(next > mlo && next < mhi) || !std::isfinite(dmu)) next = 0.5 * (mlo + mhi);
+            mu0 = next;
             ++reruns;
         }
         mu = mu0 + dmu;
@@ -436,6 +440,7 @@ struct SysBase {
     }
 
     void fill_report(xlbomd_report *rep) {
+        rep->k0_gamma = d.k0_gamma;
         rep->rms_res = rms;
         rep->mu = mu;
         rep->d_nelec = sumq;   // sum of net charges = Tr D - N_e
@@ -482,15 +487,55 @@ struct SysBase {
         }
     }
 
+    // K0 = -gamma I with gamma from the stiffest charge-response mode (the
+    // descriptor's k0_gamma == 0): power iteration v <- -J v / |J v| from
+    // v = r/|r| gives |lambda_max(J)| ~ |J v|, and gamma =
+    // floor(100 * 1.5 / (1 + |lambda|)) / 100 in [0.01, 1] keeps every
+    // eigenvalue of K0 (J - I) below 1.5.  At the solve of the current n.
+    double auto_gamma(int iters = 20) {
+        // v = r / |r| (scale 1); r = 0 falls back to e_0
+        hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(1024), 0, st, nat, 0, V, r, 1.0, vin,
+                           scal + 24);
+        XL_LAUNCH_CHECK();
+        XL_HIP(hipMemcpyAsync(hscal + 24, scal + 24, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        if (!(hscal[25] > 0.0)) {
+            std::vector<double> e0(nat, 0.0);
+            e0[0] = 1.0;
+            XL_HIP(hipMemcpyAsync(vin, e0.data(), nat * sizeof(double), hipMemcpyHostToDevice, st));
+            sync();
+        }
+        double lam = 0.0;
+        for (int it = 0; it < iters; ++it) {
+            responses(1, vin, qp, nullptr);            // qp = J v
+            hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(1024), 0, st, nat, 0, V, qp, -1.0, vin,
+                               scal + 24);
+            XL_LAUNCH_CHECK();
+            XL_HIP(hipMemcpyAsync(hscal + 24, scal + 24, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+            sync();
+            lam = hscal[24];
+        }
+        const double g = std::floor(100.0 * 1.5 / (1.0 + lam)) / 100.0;
+        if (debug()) std::fprintf(stderr, "[xlbomd] auto gamma: |lambda| %.4f gamma %.2f\n", lam, g);
+        return std::min(1.0, std::max(0.01, g));
+    }
+
     // ---- initial state (Eqs. 20, 52) ----
     void init() {
         XL_HIP(hipMemsetAsync(ncur, 0, nat * sizeof(double), st));
+        if (d.k0_gamma <= 0.0) {
+            solve(ncur, 0.0, false);
+            d.k0_gamma = auto_gamma();
+        }
         const double tol = d.scf_tol > 0 ? d.scf_tol : 1e-10;
         const int maxit = d.scf_max_iter > 0 ? d.scf_max_iter : 200;
         bool have = false;
         for (scf_iters = 0;; ++scf_iters) {
             solve(ncur, mu, have);
             have = true;
+            if (debug())
+                std::fprintf(stderr, "[xlbomd] scf it %d rms %.3e mu %.8f reruns %d rank %d\n",
+                             scf_iters, rms, mu, reruns, rank_built);
             if (rms <= tol) break;
             if (scf_iters >= maxit) throw NoConv("initial SCF did not reach the tolerance");
             // n <- n - K_j (q[n] - n), fresh rank-m kernel each iteration
@@ -907,7 +952,8 @@ void validate(const xlbomd_desc *d) {
         throw InvalidArg("kernel_rank must be in 0..min(n_atoms, 16)");
     if (d->kernel_every < 1) throw InvalidArg("kernel_every must be >= 1");
     if (d->krylov_mode != 0 && d->krylov_mode != 1) throw InvalidArg("krylov_mode is 0 or 1");
-    if (!(d->k0_gamma > 0.0 && d->k0_gamma <= 1.0)) throw InvalidArg("k0_gamma must be in (0, 1]");
+    if (!(d->k0_gamma >= 0.0 && d->k0_gamma <= 1.0))
+        throw InvalidArg("k0_gamma must be in (0, 1], or 0 for the automatic rule");
     if (d->precision < XLBOMD_FP64 || d->precision > XLBOMD_MIXED)
         throw InvalidArg("precision must be XLBOMD_FP64, XLBOMD_FP32 or XLBOMD_MIXED");
     if (!(d->hop_decay > 0.0) || !(d->hop_cutoff > 0.0) || d->taper_width < 0.0 ||

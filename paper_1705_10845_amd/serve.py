@@ -13,6 +13,7 @@ Only scheduling lives here; every step runs in the HIP library.
 """
 from __future__ import annotations
 
+import sys
 import threading
 import time
 from dataclasses import dataclass, field
@@ -58,7 +59,10 @@ class RequestStats:
 
 class Server:
     def __init__(self, hbm_budget: int, max_slots: int = 8, precision=MIXED,
-                 steps: int = 100, scf_tol: Optional[float] = None):
+                 steps: int = 100, scf_tol: Optional[float] = None,
+                 verbose: bool = False):
+        self.verbose = verbose
+        self._done = 0
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.precision = precision
@@ -91,7 +95,13 @@ class Server:
             with self._lock:
                 self._used -= need
                 self._active -= 1
+                self._done += 1
+                done = self._done
                 self._lock.notify_all()
+            if self.verbose:
+                print(f"[serve] t={st.finished:7.2f}s done {done}: {st.name} "
+                      f"({'error ' + st.error if st.error else 'ok'})",
+                      file=sys.stderr, flush=True)
 
     def run(self, requests: Sequence[Tuple[float, object]], realtime=True):
         """Serve a stream of (arrival_s, System); returns (stats, summary)."""

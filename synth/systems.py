@@ -158,7 +158,7 @@ CONFIGS = {
                hop_decay=1.2, hop_cutoff=5.0, taper_width=0.5,
                u_range=(0.8, 1.2), gamma_soft=1.0, rep_a=5.8, rep_decay=0.6,
                te=0.05, dt=0.5, kmax=5, rank=4, kernel_every=1,
-               krylov_mode=0, k0_gamma=0.1, steps=100),
+               krylov_mode=0, k0_gamma=0.0, steps=100),
     # 4096 randomly packed atoms, N = 16384.
     "c5": dict(index=5, dims=None, spacing=None, jitter=0.0, n_orb=4,
                onsite=_SP_ONSITE, onsite_jitter=0.0, hop_block="rand",

@@ -37,4 +37,4 @@ def test_struct_layout_matches_header():
     # 2 int32 + 6 pointers + 3 doubles + pointer + 6 doubles + 4 int32 +
     # double + int32 (+pad) + double + 2 int32 + pointer
     assert ctypes.sizeof(binding.Desc) == 8 + 48 + 24 + 8 + 48 + 16 + 8 + 8 + 8 + 8 + 8
-    assert ctypes.sizeof(binding.Report) == 10 * 8 + 7 * 4 + 4
+    assert ctypes.sizeof(binding.Report) == 10 * 8 + 7 * 4 + 4 + 8

@@ -96,3 +96,18 @@ def test_energy_conservation_10k_steps_c1(P):
           f"linear drift over run {drift:.2e}, mean RMS residual {np.mean(res):.2e}")
     assert drift < 2.0 * E.std() + 1e-6
     assert E.std() < 5e-3
+
+
+def test_auto_gamma_matches_oracle(P):
+    s = lattice_system(40, "c4", seed=17, rank=3)
+    assert s.k0_gamma == 0.0
+    m = R.Model(s)
+    st = R.init_state(m, scf_tol=1e-10)
+    g = P.XLBOMD(s, precision=P.FP64, scf_tol=1e-10)
+    rep = g.step(2)
+    st = R.md_step(m, R.md_step(m, st, want_energy=False), want_energy=False)
+    n, q = g.charges()
+    print("auto gamma", rep["k0_gamma"], "oracle", m.gamma_used, "dq", np.abs(q - st.el.q).max())
+    assert rep["k0_gamma"] == m.gamma_used
+    assert np.abs(q - st.el.q).max() < 1e-8
+    g.close()

@@ -363,3 +363,18 @@ def test_kernel_of_a_zero_residual_is_K0():
     k = R.kernel_sm(m, el, 0.2, 3)
     assert k.rank == 0
     assert np.allclose(k.K, -0.2 * np.eye(m.nat))
+
+
+def test_auto_gamma_bounds_the_stiffest_mode():
+    # the power-iteration estimate approaches the largest |eigenvalue| of J
+    # from below, and the chosen gamma keeps gamma (1 - lambda_J) near or
+    # below 1.5 for every mode (exact spectrum from a library eigensolver)
+    s = lattice_system(24, "c4", seed=31)
+    m = R.Model(s)
+    el = R.electronic(m, s.pos, np.zeros(m.nat))
+    g, lam = R.auto_gamma(m, el)
+    J = R.jacobian(m, el)
+    lam_exact = np.abs(np.linalg.eigvals(J)).max()
+    assert 0.97 * lam_exact <= lam <= lam_exact * (1 + 1e-12)
+    assert g * (1.0 + lam_exact) <= 1.55
+    assert g >= 0.95 * 1.5 / (1.0 + lam_exact) - 0.01
