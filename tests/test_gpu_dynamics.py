@@ -37,7 +37,7 @@ def _traj(P, s, steps, precision, check_every=1):
 def test_block_krylov_mode_trajectory(P):
     """krylov_mode 1: v1 plus the previous build's directions, one batched
     response launch (small-gap model, rank 3)."""
-    s = lattice_system(40, "c3", seed=12, rank=3, krylov_mode=1)
+    s = lattice_system(40, "c3", seed=12, rank=3, krylov_mode=1, k0_gamma=0.1)
     w = _traj(P, s, 30, P.FP64)
     print("block mode 30 steps:", {k: f"{v:.2e}" for k, v in w.items()})
     # small-gap model: the charge Jacobian reaches |J| ~ 90, so the charges
