@@ -4,9 +4,11 @@ Workload: 1024 atoms x 4 orbitals (s + 3p) on a jittered 8x8x16 cubic
 lattice, Te = 0.05, rank-4 sequential-Krylov kernel rebuilt every step,
 Table I K_max = 5 integrator.  `value` is the mixed path: the density-matrix
 expansion in FP64 MFMA (it fixes charges, forces and energy, which then meet
-the FP64 tolerances) and the kernel's response products in FP32 MFMA; the
-chemical potential, Krylov solve, Verlet and energy sums are FP64.  The
-FP64-plain path and the all-FP32 path are timed the same way beside it.
+the FP64 tolerances) and the kernel's response products as split bf16x3
+products on the bf16 matrix cores (FP32 accumulation); the chemical
+potential, Krylov solve, Verlet and energy sums are FP64.  The same path
+with FP32 response products, the FP64-plain path and the all-FP32 path are
+timed the same way beside it.
 
 Prints one JSON line.  The oracle (test infrastructure) is used only for the
 CPU baseline leg.
@@ -20,7 +22,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f32": 157.3, "f64": 78.6}     # dense MFMA TFLOP/s, MI355X
+# dense MFMA TFLOP/s, MI355X; a split bf16x3 product is three bf16 products,
+# so its algorithmic peak is a third of the bf16 rate
+PEAK = {"f32": 157.3, "f64": 78.6, "bf3": 2500.0 / 3}
+KERNEL = {"f64": "gemm_tn_kernel<double>", "f32": "gemm_tn_kernel<float>",
+          "bf3": "gemm_bf3_kernel"}
 
 
 def _sync():
@@ -123,6 +129,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-mixed-fp32", action="store_true",
+                    help="skip the mixed path with FP32 response products")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving", action="store_true",
@@ -136,7 +144,7 @@ def main():
         sys.exit(2)
 
     from synth import make_system
-    from paper_1705_10845_amd import FP32, FP64, MIXED
+    from paper_1705_10845_amd import FP32, FP64, MIXED, MIXED_BF16X3
     s = make_system("c2")
     if args.serving_only:
         t0 = time.perf_counter()
@@ -145,26 +153,28 @@ def main():
         print(json.dumps({"serving": summ}), flush=True)
         return
 
-    mixed = time_path(s, MIXED, args.steps, args.warmup, "mixed")
+    mixed = time_path(s, MIXED_BF16X3, args.steps, args.warmup, "mixed (bf16x3 responses)")
+    mixed32 = None if args.no_mixed_fp32 else time_path(s, MIXED, args.steps, 1,
+                                                        "mixed (FP32 responses)")
     fp64 = None if args.no_fp64 else time_path(s, FP64, args.fp64_steps, 1, "fp64")
     fp32 = None if args.no_fp32 else time_path(s, FP32, args.steps, 1, "fp32")
 
     def roof(prof, steps):
         # the dominant product class of the step (the most kernel time)
-        key = max(("f64", "f32"), key=lambda k: prof[k]["ms"])
+        key = max(PEAK, key=lambda k: prof[k]["ms"])
         p = prof[key]
         ach = p["flops"] / (p["ms"] * 1e-3) / 1e12 if p["ms"] > 0 else 0.0
         return {"bound": "mfma", "achieved": ach, "peak": PEAK[key], "unit": "TFLOP/s",
-                "frac": ach / PEAK[key], "traffic": None,
-                "kernel": f"gemm_tn_kernel<{'double' if key == 'f64' else 'float'}>",
+                "frac": ach / PEAK[key], "traffic": None, "kernel": KERNEL[key],
                 "launches": p["launches"], "avg_launch_ms": p["ms"] / max(1, p["launches"]),
                 "gemm_ms_per_step": p["ms"] / steps,
-                "other_class_ms_per_step": prof["f32" if key == "f64" else "f64"]["ms"] / steps}
+                "other_classes_ms_per_step": {k: prof[k]["ms"] / steps for k in PEAK
+                                              if k != key and prof[k]["ms"] > 0}}
 
     def summary(r, steps):
         out = {"value": r["steps_per_s"], "ms_per_step": r["ms_per_step"], "steps": steps,
                "foe_levels": r["report"]["foe_levels"], "mu_reruns_last": r["report"]["mu_reruns"]}
-        for k in ("f64", "f32"):
+        for k in PEAK:
             p = r["prof"][k]
             if p["ms"] > 0:
                 out[f"mfma_{k}_tflops"] = p["flops"] / (p["ms"] * 1e-3) / 1e12
@@ -182,18 +192,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32",
+        "dtype": "f64+bf16x3",
         "data": "synthetic",
         "config": {"workload": "c2: 1024 atoms x 4 orbitals (N=4096) jittered cubic "
                                "lattice, Te=0.05, rank-4 sequential Krylov kernel every "
                                "step, K_max=5; mixed path: FP64 MFMA density-matrix "
-                               "expansion, FP32 MFMA kernel responses, FP64 mu/Krylov/"
-                               "Verlet/energy sums",
+                               "expansion, split bf16x3 MFMA kernel responses (FP32 "
+                               "accumulation), FP64 mu/Krylov/Verlet/energy sums",
                    "n_orbitals": 4096, "kernel_rank": 4, "energy_every": ENERGY_EVERY,
                    "foe_levels": mixed["report"]["foe_levels"]},
         "roofline": roof(mixed["prof"], args.steps),
         "mixed": summary(mixed, args.steps),
     }
+    if mixed32 is not None:
+        out["mixed_fp32_responses"] = summary(mixed32, args.steps)
     if fp64 is not None:
         out["fp64_plain"] = summary(fp64, args.fp64_steps)
         out["mixed_over_fp64"] = mixed["steps_per_s"] / fp64["steps_per_s"]

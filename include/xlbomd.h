@@ -59,9 +59,15 @@ typedef enum {
     XLBOMD_FP64 = 0,         /* every dense product in FP64 (FP64 MFMA)   */
     XLBOMD_FP32 = 1,         /* dense products in FP32 MFMA; mu, kernel
                                 solve, Verlet and energy sums in FP64     */
-    XLBOMD_MIXED = 2         /* density-matrix expansion in FP64 MFMA (it
+    XLBOMD_MIXED = 2,        /* density-matrix expansion in FP64 MFMA (it
                                 fixes charges, forces, energy); the
                                 kernel's response products in FP32 MFMA   */
+    XLBOMD_MIXED_BF16X3 = 3  /* as XLBOMD_MIXED, but the response products
+                                are split-precision bf16x3: each FP32
+                                operand is split into bf16 hi + lo parts
+                                and hi*hi + hi*lo + lo*hi is accumulated
+                                in FP32 on the bf16 matrix cores (relative
+                                error ~2^-16 per operand); storage FP32   */
 } xlbomd_precision;
 
 /* System descriptor.  Model (orthogonal SCC tight binding):
@@ -183,8 +189,9 @@ int xlbomd_kernel_apply(xlbomd_system *h, int32_t rank, const double *r,
 
 /* Live timing of the dense MFMA products.  enable != 0 starts recording a
  * HIP event pair on the handle's stream around every product launched by
- * later calls; enable == 0 stops and, if out != NULL, writes 10 doubles:
- * out[0..4] for FP64 products and out[5..9] for FP32 products, each
+ * later calls; enable == 0 stops and, if out != NULL, writes 15 doubles:
+ * out[0..4] for FP64 products, out[5..9] for FP32 products and out[10..14]
+ * for split bf16x3 products, each
  *   {total kernel milliseconds, total algorithmic flops (2 n_k flops per
  *    output entry on the real n x n block; symmetric outputs count n(n+1)/2
  *    entries), number of launches, shortest launch ms, longest launch ms}. */
@@ -192,8 +199,9 @@ int xlbomd_profile(xlbomd_system *h, int32_t enable, double *out);
 
 /* Kernel-level test hook: C = A B with the library's dense product kernel
  * (A must be symmetric; it is read as A^T).  n x n row-major host arrays,
- * n a positive multiple of 128; precision XLBOMD_FP64 or XLBOMD_FP32 (the
- * inputs are rounded to it); sym != 0 computes only the upper block
+ * n a positive multiple of 128; precision XLBOMD_FP64, XLBOMD_FP32 (the
+ * inputs are rounded to it) or XLBOMD_MIXED_BF16X3 (inputs rounded to FP32,
+ * split bf16x3 product); sym != 0 computes only the upper block
  * triangle and mirrors it (valid when A B is symmetric).  Synchronous. */
 int xlbomd_selftest_gemm(int32_t n, int32_t precision, int32_t sym, const double *A,
                          const double *B, double *C);

@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libxlbomd.so")
 
-FP64, FP32, MIXED = 0, 1, 2
+FP64, FP32, MIXED, MIXED_BF16X3 = 0, 1, 2, 3
 _dp = ctypes.POINTER(ctypes.c_double)
 
 
@@ -240,11 +240,12 @@ class XLBOMD:
         _check(lib().xlbomd_profile(self._h, 1, None))
 
     def profile_stop(self):
-        """GEMM timing since profile_start: {'f64': {...}, 'f32': {...}}."""
-        out = np.zeros(10)
+        """GEMM timing since profile_start: {'f64': {...}, 'f32': {...},
+        'bf3': {...}} (split bf16x3 products in 'bf3')."""
+        out = np.zeros(15)
         _check(lib().xlbomd_profile(self._h, 0, _ptr(out)))
         res = {}
-        for key, o in (("f64", out[:5]), ("f32", out[5:])):
+        for key, o in (("f64", out[:5]), ("f32", out[5:10]), ("bf3", out[10:])):
             res[key] = dict(ms=o[0], flops=o[1], launches=int(o[2]),
                             min_ms=o[3], max_ms=o[4])
         return res

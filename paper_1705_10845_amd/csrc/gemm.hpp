@@ -17,6 +17,7 @@
 #include "common.hpp"
 
 #include <cmath>
+#include <type_traits>
 
 namespace xl {
 
@@ -63,6 +64,7 @@ template <typename T> struct GemmArgs {
     long sA0 = 0, sB0 = 0, sA1 = 0, sB1 = 0, sX = 0, sX2 = 0, sC = 0, sC2 = 0, sK = 0;
     T *ws = nullptr;        // split-k partial tiles (nullptr: no split)
     long ws_elems = 0;
+    bool split3 = false;    // FP32 only: bf16x3 products (gemm_bf3_kernel)
 };
 
 constexpr int GT = 128;   // output tile edge
@@ -270,6 +272,170 @@ __global__ __launch_bounds__(256, 2) void gemm_tn_kernel(GemmArgs<T> p, int ntil
     epilogue<T, SYM>(p, bz, ti, tj, wr, wc, fr, fc, acc);
 }
 
+// ---------------------------------------------------------------------------
+// Split-precision FP32 product on the bf16 matrix cores.  Each FP32 operand
+// x is written as hi + lo with hi = bf16(x) and lo = bf16(x - hi) (the
+// residual is exact in FP32), and the product is hi*hi + hi*lo + lo*hi with
+// FP32 accumulation; the dropped lo*lo term and the rounding of lo leave a
+// relative error of about 2^-16 per operand, against 2^-8 for plain bf16.
+// Three 16x16x32 bf16 MFMAs replace eight 16x16x4 FP32 MFMAs per 16x16x32
+// block: at the bf16 rate this is 16/3 of the FP32 matrix-core rate.
+//
+// Operands stay FP32 in HBM (same arguments, schedule, epilogue and split-k
+// partials as the FP32 kernel).  Each thread loads a 4 (k) x 4 (i) block of
+// each operand tile with four 16-byte row loads, splits it, and stores it
+// transposed into LDS as [i][k] rows of hi and of lo parts, so a lane's MFMA
+// fragment (8 consecutive k of one row) is one 16-byte LDS read.  Row pitch
+// 40 bf16 (80 bytes): the 16-byte fragment reads of 16 consecutive rows and
+// the 8-byte stores of a 16-lane group fall in distinct banks.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// hi and lo bf16 pairs of two FP32 values (element 0 in the low half)
+__device__ __forceinline__ void split_pair(float x0, float x1, unsigned &hi, unsigned &lo) {
+    const f32x2 x = {x0, x1};
+    hi = __builtin_bit_cast(unsigned, __builtin_convertvector(x, bf16x2));
+    const f32x2 h = {__builtin_bit_cast(float, hi << 16),
+                     __builtin_bit_cast(float, hi & 0xffff0000u)};
+    lo = __builtin_bit_cast(unsigned, __builtin_convertvector(x - h, bf16x2));
+}
+
+constexpr int B3K = 32;          // k per tile = k of one bf16 MFMA
+constexpr int B3P = 20;          // LDS row pitch in 32-bit words (40 bf16)
+
+template <bool SYM>
+__global__ __launch_bounds__(256, 2) void gemm_bf3_kernel(GemmArgs<float> p, int ntiles, int nfull,
+                                                       int nsplit, int per_xcd) {
+    using acc_t = f32x4;
+    // [buffer][hi, lo][row i][k pairs]
+    __shared__ __attribute__((aligned(16))) unsigned As[2][2][GT][B3P];
+    __shared__ __attribute__((aligned(16))) unsigned Bs[2][2][GT][B3P];
+
+    // unit -> tile, as in gemm_tn_kernel
+    const int b = blockIdx.x;
+    const int ntail = ntiles - nfull;
+    const int nfull_pad = ((nfull + NXCD - 1) / NXCD) * NXCD;
+    int unit;
+    if (b < nfull_pad) {
+        unit = (b % NXCD) * (nfull_pad / NXCD) + b / NXCD;
+        if (unit >= nfull) return;
+    } else {
+        const int bb = b - nfull_pad;
+        unit = nfull + (bb % NXCD) * per_xcd + bb / NXCD;
+        if (unit >= nfull + ntail * nsplit) return;
+    }
+    const bool part = unit >= nfull;
+    const int w = unit - nfull;
+    const int u = part ? nfull + w / nsplit : unit;
+    const int split = part ? w % nsplit : 0;
+    const int ns = part ? nsplit : 1;
+    const int nt = p.n / GT;
+    int ti, tj;
+    tile_of<SYM>(u, nt, ti, tj);
+    const long bz = blockIdx.z;
+    const float *A0 = p.A0 + bz * p.sA0, *B0 = p.B0 + bz * p.sB0;
+    const float *A1 = p.A1 ? p.A1 + bz * p.sA1 : nullptr;
+    const float *B1 = p.B1 ? p.B1 + bz * p.sB1 : nullptr;
+    const double *ks = p.kscale ? p.kscale + bz * p.sK : nullptr;
+    const int ld = p.ld;
+    const int i0 = ti * GT, j0 = tj * GT;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wr = wid >> 1, wc = wid & 1;
+
+    acc_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = acc_t{0, 0, 0, 0};
+
+    const int nk1 = p.n / B3K;
+    const int nktot = A1 ? 2 * nk1 : nk1;
+    const int kt0 = (int)((long)nktot * split / ns);
+    const int kt1 = (int)((long)nktot * (split + 1) / ns);
+
+    // loader: k rows 4 kq .. 4 kq + 3, tile columns 4 xv .. 4 xv + 3
+    // (loads run one k-tile ahead; two ahead measured no faster)
+    const int kq = tid & 7, xv = tid >> 3;
+    f32x4 ra[4], rb[4];
+    auto gload = [&](f32x4 (&a)[4], f32x4 (&bv)[4], int kt) {
+        const bool second = kt >= nk1;
+        const float *Ap = second ? A1 : A0;
+        const float *Bp = second ? B1 : B0;
+        const int kb = (second ? kt - nk1 : kt) * B3K + 4 * kq;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const long k = kb + v;
+            a[v] = *reinterpret_cast<const f32x4 *>(Ap + k * ld + i0 + 4 * xv);
+            bv[v] = *reinterpret_cast<const f32x4 *>(Bp + k * ld + j0 + 4 * xv);
+            if (ks && !second) bv[v] *= (float)ks[k];
+        }
+    };
+    // column e of the 4 x 4 block: k-consecutive, split, one 8-byte store
+    // per part
+    auto sstore = [&](const f32x4 (&a)[4], const f32x4 (&bv)[4], int buf) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            unsigned h0, h1, l0, l1;
+            split_pair(a[0][e], a[1][e], h0, l0);
+            split_pair(a[2][e], a[3][e], h1, l1);
+            *reinterpret_cast<u32x2 *>(&As[buf][0][4 * xv + e][2 * kq]) = u32x2{h0, h1};
+            *reinterpret_cast<u32x2 *>(&As[buf][1][4 * xv + e][2 * kq]) = u32x2{l0, l1};
+            split_pair(bv[0][e], bv[1][e], h0, l0);
+            split_pair(bv[2][e], bv[3][e], h1, l1);
+            *reinterpret_cast<u32x2 *>(&Bs[buf][0][4 * xv + e][2 * kq]) = u32x2{h0, h1};
+            *reinterpret_cast<u32x2 *>(&Bs[buf][1][4 * xv + e][2 * kq]) = u32x2{l0, l1};
+        }
+    };
+    const int fr = lane >> 4, fc = lane & 15;
+    auto compute = [&](int buf) {
+        // fragment of lane (fr, fc): row fc of the 16-row block, k 8 fr .. 8 fr + 7
+        bf16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int ra_ = wr * 64 + q * 16 + fc, rb_ = wc * 64 + q * 16 + fc;
+            ah[q] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(&As[buf][0][ra_][4 * fr]));
+            al[q] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(&As[buf][1][ra_][4 * fr]));
+            bh[q] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(&Bs[buf][0][rb_][4 * fr]));
+            bl[q] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(&Bs[buf][1][rb_][4 * fr]));
+        }
+        // small terms first
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], bh[y], acc[x][y], 0, 0, 0);
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bl[y], acc[x][y], 0, 0, 0);
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
+            }
+    };
+
+    gload(ra, rb, kt0);
+    sstore(ra, rb, 0);
+    __syncthreads();
+    for (int kt = kt0; kt < kt1; ++kt) {
+        const int buf = (kt - kt0) & 1;
+        if (kt + 1 < kt1) gload(ra, rb, kt + 1);
+        compute(buf);
+        if (kt + 1 < kt1) sstore(ra, rb, buf ^ 1);
+        __syncthreads();
+    }
+
+    if (part) {
+        acc_t *wp = reinterpret_cast<acc_t *>(p.ws + ((long)bz * ntail * nsplit + w) * (GT * GT)) + tid;
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) wp[(x * 4 + y) * 256] = acc[x][y];
+        return;
+    }
+    // the 16x16 bf16 MFMA leaves its accumulators in the FP32 16x16x4 layout
+    epilogue<float, SYM>(p, bz, ti, tj, wr, wc, fr, fc, acc);
+}
+
 // Sum the k-split partial tiles of each tile and apply the epilogue.  Same
 // thread layout as the product kernel, so every thread reads back exactly
 // the accumulators its counterpart wrote (contiguous 64 per thread).
@@ -359,6 +525,8 @@ template <typename T>
 void gemm(const GemmArgs<T> &a, bool sym, hipStream_t st) {
     if (a.n % GT != 0 || a.ld % 4 != 0)
         throw InvalidArg("gemm: n must be a multiple of 128");
+    if (a.split3 && !std::is_same<T, float>::value)
+        throw InvalidArg("gemm: split bf16x3 products take FP32 operands");
     const int nt = a.n / GT;
     const int ntiles = sym ? nt * (nt + 1) / 2 : nt * nt;
     const int nkt = (a.n / MF<T>::BK) * (a.A1 ? 2 : 1);
@@ -369,12 +537,24 @@ void gemm(const GemmArgs<T> &a, bool sym, hipStream_t st) {
     const int tail_units = (ntiles - s.nfull) * s.nsplit;
     const int per = (tail_units + NXCD - 1) / NXCD;     // tail units per XCD
     dim3 grid(nfull_pad + per * NXCD, 1, a.batch);
-    if (sym)
-        hipLaunchKernelGGL((gemm_tn_kernel<T, true>), grid, dim3(256), 0, st, a, ntiles, s.nfull,
-                           s.nsplit, per);
-    else
-        hipLaunchKernelGGL((gemm_tn_kernel<T, false>), grid, dim3(256), 0, st, a, ntiles, s.nfull,
-                           s.nsplit, per);
+    if constexpr (std::is_same<T, float>::value) {
+        if (a.split3) {
+            if (sym)
+                hipLaunchKernelGGL((gemm_bf3_kernel<true>), grid, dim3(256), 0, st, a, ntiles,
+                                   s.nfull, s.nsplit, per);
+            else
+                hipLaunchKernelGGL((gemm_bf3_kernel<false>), grid, dim3(256), 0, st, a, ntiles,
+                                   s.nfull, s.nsplit, per);
+        }
+    }
+    if (!a.split3) {
+        if (sym)
+            hipLaunchKernelGGL((gemm_tn_kernel<T, true>), grid, dim3(256), 0, st, a, ntiles,
+                               s.nfull, s.nsplit, per);
+        else
+            hipLaunchKernelGGL((gemm_tn_kernel<T, false>), grid, dim3(256), 0, st, a, ntiles,
+                               s.nfull, s.nsplit, per);
+    }
     XL_LAUNCH_CHECK();
     if (s.nfull < ntiles) {
         dim3 g2(ntiles - s.nfull, 1, a.batch);

@@ -164,7 +164,7 @@ struct SysBase {
         bool on = false;
         std::vector<hipEvent_t> ev;
         std::vector<double> flops;
-        std::vector<int> f64;
+        std::vector<int> cls;      // 0 FP64, 1 FP32, 2 split bf16x3
         size_t used = 0;
     } prof;
 
@@ -179,11 +179,11 @@ struct SysBase {
         }
         XL_HIP(hipEventRecord(prof.ev[prof.used], st));
     }
-    void prof_end(double flops, bool is64) {
+    void prof_end(double flops, int cls) {
         if (!prof.on) return;
         XL_HIP(hipEventRecord(prof.ev[prof.used + 1], st));
         prof.flops.push_back(flops);
-        prof.f64.push_back(is64 ? 1 : 0);
+        prof.cls.push_back(cls);
         prof.used += 2;
     }
     // algorithmic flops of one product on the real n x n block: each output
@@ -569,6 +569,7 @@ struct SysBase {
 // ---------------------------------------------------------------------------
 template <typename TF, typename TR> struct Sys : SysBase {
     static constexpr bool SAME = std::is_same<TF, TR>::value;
+    bool resp_split = false;       // response products as split bf16x3 (TR = float)
     std::vector<TF *> Z, Yk;       // Z_0..Z_L, Y_0..Y_{L-1}
     TF *Ys = nullptr, *Y2 = nullptr, *Am = nullptr, *E = nullptr, *Wk = nullptr;
     TF *Dc = nullptr, *ZL2 = nullptr;
@@ -626,7 +627,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
         attach_ws(a);
         prof_begin();
         gemm(a, sym, st);
-        prof_end(gemm_flops(sym, a.A1 ? 2 : 1) * a.batch, sizeof(U) == 8);
+        prof_end(gemm_flops(sym, a.A1 ? 2 : 1) * a.batch, sizeof(U) == 8 ? 0 : (a.split3 ? 2 : 1));
     }
     template <typename U> GemmArgs<U> base() const {
         GemmArgs<U> a;
@@ -781,6 +782,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
         {   // G = Y diag(u) Y, then Z'_0
             auto a = base<TR>();
             a.batch = nb; a.A0 = Ysr; a.B0 = Ysr; a.kscale = ub; a.sK = Np;
+            a.split3 = resp_split;
             a.C = Tb; a.sC = sm;
             run_gemm(a, true);
             hipLaunchKernelGGL((seed_resp_kernel<TR>), dim3(ceil_div(Np, 256), Np, nb), dim3(256),
@@ -791,17 +793,17 @@ template <typename TF, typename TR> struct Sys : SysBase {
             auto a = base<TR>();           // A' = 4 (Z Z' + Z' Z)
             a.batch = nb;
             a.A0 = Zr[k]; a.B0 = Zp; a.sB0 = sm; a.A1 = Zp; a.sA1 = sm; a.B1 = Zr[k];
-            a.alpha = (TR)4.0; a.C = Ap; a.sC = sm;
+            a.alpha = (TR)4.0; a.C = Ap; a.sC = sm; a.split3 = resp_split;
             run_gemm(a, true);
             auto b = base<TR>();           // T = 2 Z' - A' Z_{k+1}
             b.batch = nb;
             b.A0 = Ap; b.sA0 = sm; b.B0 = Zr[k + 1]; b.alpha = (TR)-1.0;
-            b.X = Zp; b.sX = sm; b.beta = (TR)2.0; b.C = Tb; b.sC = sm;
+            b.X = Zp; b.sX = sm; b.beta = (TR)2.0; b.C = Tb; b.sC = sm; b.split3 = resp_split;
             run_gemm(b, false);
             if (k + 1 < L) {
                 auto c = base<TR>();       // Z'_{k+1} = Y_k T
                 c.batch = nb;
-                c.A0 = Yr[k]; c.B0 = Tb; c.sB0 = sm; c.C = Zp; c.sC = sm;
+                c.A0 = Yr[k]; c.B0 = Tb; c.sB0 = sm; c.C = Zp; c.sC = sm; c.split3 = resp_split;
                 run_gemm(c, true);
             }
         }
@@ -954,8 +956,9 @@ void validate(const xlbomd_desc *d) {
     if (d->krylov_mode != 0 && d->krylov_mode != 1) throw InvalidArg("krylov_mode is 0 or 1");
     if (!(d->k0_gamma >= 0.0 && d->k0_gamma <= 1.0))
         throw InvalidArg("k0_gamma must be in (0, 1], or 0 for the automatic rule");
-    if (d->precision < XLBOMD_FP64 || d->precision > XLBOMD_MIXED)
-        throw InvalidArg("precision must be XLBOMD_FP64, XLBOMD_FP32 or XLBOMD_MIXED");
+    if (d->precision < XLBOMD_FP64 || d->precision > XLBOMD_MIXED_BF16X3)
+        throw InvalidArg("precision must be XLBOMD_FP64, XLBOMD_FP32, XLBOMD_MIXED or "
+                         "XLBOMD_MIXED_BF16X3");
     if (!(d->hop_decay > 0.0) || !(d->hop_cutoff > 0.0) || d->taper_width < 0.0 ||
         !(d->gamma_soft > 0.0) || (d->rep_a != 0.0 && !(d->rep_decay > 0.0)))
         throw InvalidArg("model lengths must be positive");
@@ -975,7 +978,11 @@ int xlbomd_init_system(const xlbomd_desc *desc, xlbomd_system **out) {
         validate(desc);
         if (desc->precision == XLBOMD_FP64) h->s.reset(new Sys<double, double>());
         else if (desc->precision == XLBOMD_FP32) h->s.reset(new Sys<float, float>());
-        else h->s.reset(new Sys<double, float>());
+        else {
+            auto *m = new Sys<double, float>();
+            m->resp_split = desc->precision == XLBOMD_MIXED_BF16X3;
+            h->s.reset(m);
+        }
         h->s->upload_model(desc);
         h->s->init();
     });
@@ -1172,15 +1179,15 @@ int xlbomd_profile(xlbomd_system *h, int32_t enable, double *out) {
             s.prof.on = true;
             s.prof.used = 0;
             s.prof.flops.clear();
-            s.prof.f64.clear();
+            s.prof.cls.clear();
             return;
         }
-        double acc[2][5] = {{0, 0, 0, 1e300, 0}, {0, 0, 0, 1e300, 0}};
+        double acc[3][5] = {{0, 0, 0, 1e300, 0}, {0, 0, 0, 1e300, 0}, {0, 0, 0, 1e300, 0}};
         const size_t n = s.prof.used / 2;
         for (size_t i = 0; i < n; ++i) {
             float e = 0.0f;
             XL_HIP(hipEventElapsedTime(&e, s.prof.ev[2 * i], s.prof.ev[2 * i + 1]));
-            double *a = acc[s.prof.f64[i] ? 0 : 1];
+            double *a = acc[s.prof.cls[i]];
             a[0] += e;
             a[1] += s.prof.flops[i];
             a[2] += 1.0;
@@ -1189,7 +1196,7 @@ int xlbomd_profile(xlbomd_system *h, int32_t enable, double *out) {
         }
         s.prof.on = false;
         if (out)
-            for (int p = 0; p < 2; ++p) {
+            for (int p = 0; p < 3; ++p) {
                 if (acc[p][2] == 0.0) acc[p][3] = 0.0;
                 for (int k = 0; k < 5; ++k) out[5 * p + k] = acc[p][k];
             }
@@ -1199,6 +1206,8 @@ int xlbomd_profile(xlbomd_system *h, int32_t enable, double *out) {
 int xlbomd_selftest_gemm(int32_t n, int32_t precision, int32_t sym, const double *A,
                          const double *B, double *C) {
     if (n <= 0 || n % 128 || !A || !B || !C) return fail(XLBOMD_E_INVALID, "bad self-test args");
+    if (precision != XLBOMD_FP64 && precision != XLBOMD_FP32 && precision != XLBOMD_MIXED_BF16X3)
+        return fail(XLBOMD_E_INVALID, "self-test precision: FP64, FP32 or MIXED_BF16X3");
     return guarded([&] {
         const size_t nn = (size_t)n * n;
         double *dA = dalloc<double>(nn), *dB = dalloc<double>(nn), *dC = dalloc<double>(nn);
@@ -1215,6 +1224,7 @@ int xlbomd_selftest_gemm(int32_t n, int32_t precision, int32_t sym, const double
             hipLaunchKernelGGL((convert_kernel<double, T>), dim3(g), dim3(256), 0, 0, (long)nn, dB, 1.0, b);
             GemmArgs<T> ga;
             ga.n = n; ga.ld = n; ga.A0 = a; ga.B0 = b; ga.C = c;
+            ga.split3 = precision == XLBOMD_MIXED_BF16X3;
             ga.ws_elems = split_ws_elems<T>(n, sym != 0, 0, 1);
             ga.ws = dalloc<T>(ga.ws_elems);
             fr.ptrs.push_back(ga.ws);
@@ -1231,6 +1241,8 @@ int xlbomd_selftest_gemm_time(int32_t n, int32_t precision, int32_t sym, int32_t
                               int32_t reps, double *ms_per_launch) {
     if (n <= 0 || n % 128 || reps <= 0 || !ms_per_launch)
         return fail(XLBOMD_E_INVALID, "bad self-test args");
+    if (precision != XLBOMD_FP64 && precision != XLBOMD_FP32 && precision != XLBOMD_MIXED_BF16X3)
+        return fail(XLBOMD_E_INVALID, "self-test precision: FP64, FP32 or MIXED_BF16X3");
     return guarded([&] {
         const size_t nn = (size_t)n * n;
         DevFree fr;
@@ -1243,6 +1255,7 @@ int xlbomd_selftest_gemm_time(int32_t n, int32_t precision, int32_t sym, int32_t
             GemmArgs<T> ga;
             ga.n = n; ga.ld = n; ga.A0 = a; ga.B0 = b; ga.C = c;
             if (dual) { ga.A1 = b; ga.B1 = a; }
+            ga.split3 = precision == XLBOMD_MIXED_BF16X3;
             ga.ws_elems = split_ws_elems<T>(n, sym != 0, dual, 1);
             ga.ws = dalloc<T>(ga.ws_elems);
             fr.ptrs.push_back(ga.ws);

@@ -111,3 +111,30 @@ def test_auto_gamma_matches_oracle(P):
     assert rep["k0_gamma"] == m.gamma_used
     assert np.abs(q - st.el.q).max() < 1e-8
     g.close()
+
+
+def test_mixed_split_one_step(P):
+    """MIXED_BF16X3: FP64 expansion, split bf16x3 response products.  One
+    step from the oracle's state: n, charges, forces and energy at FP64
+    tolerances (the step applies the kernel of the state it starts from);
+    the new K r, built from split responses, to 1e-3 relative."""
+    s = lattice_system(40, "c2", seed=3)
+    m = R.Model(s)
+    st = R.init_state(m, scf_tol=1e-11)
+    for _ in range(3):
+        st = R.md_step(m, st)
+    ref = R.md_step(m, st)
+    g = P.XLBOMD(s, precision=P.MIXED_BF16X3, scf_tol=1e-9)
+    g.set_state(pos=st.pos, vel=st.vel, n_hist=st.n_hist, kr=st.kr)
+    g.step(1, report=False)
+    state = g.get_state()
+    n, q = g.charges()
+    F, e = g.forces()
+    dq = np.abs(q - ref.el.q).max()
+    dn = np.abs(state["n_hist"][0] - ref.n_hist[0]).max()
+    dF = np.abs(F - ref.force).max()
+    dO = abs(e["omega"] - ref.energy["omega"]) / abs(ref.energy["omega"])
+    dkr = np.abs(state["kr"] - ref.kr).max() / np.abs(ref.kr).max()
+    print(f"MIXED_BF16X3 one step: dn {dn:.2e} dq {dq:.2e} dF {dF:.2e} "
+          f"rel dOmega {dO:.2e} rel dKr {dkr:.2e}")
+    assert dq < 1e-8 and dn < 1e-10 and dF < 1e-5 and dO < 1e-8 and dkr < 1e-3
