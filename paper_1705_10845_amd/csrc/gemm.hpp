@@ -89,13 +89,13 @@ __device__ __forceinline__ void tile_of(int u, int nt, int &ti, int &tj) {
     tj = row + (u - start);
 }
 
-// Write one 128 x 128 output tile from the accumulators of thread
-// (wr, wc, fr, fc): C = alpha acc + beta X + beta2 X2 + gamma I (+ C2), with
-// the symmetric mirror when SYM.
+// Write the 16 x 16 block (x, y) of a 128 x 128 output tile from the
+// accumulator of thread (wr, wc, fr, fc): C = alpha acc + beta X + beta2 X2
+// + gamma I (+ C2), with the symmetric mirror when SYM.
 template <typename T, bool SYM>
-__device__ __forceinline__ void epilogue(const GemmArgs<T> &p, long bz, int ti, int tj, int wr,
-                                         int wc, int fr, int fc,
-                                         const typename MF<T>::acc_t (&acc)[4][4]) {
+__device__ __forceinline__ void epilogue_block(const GemmArgs<T> &p, long bz, int ti, int tj,
+                                               int wr, int wc, int fr, int fc, int x, int y,
+                                               const typename MF<T>::acc_t &acc) {
     using M = MF<T>;
     const int ld = p.ld;
     const int i0 = ti * GT, j0 = tj * GT;
@@ -105,33 +105,41 @@ __device__ __forceinline__ void epilogue(const GemmArgs<T> &p, long bz, int ti, 
     const T *X = p.X ? p.X + bz * p.sX : nullptr;
     const T *X2 = p.X2 ? p.X2 + bz * p.sX2 : nullptr;
 #pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = i0 + wr * 64 + x * 16 + M::out_row(fr, r);
+        const int col = j0 + wc * 64 + y * 16 + fc;
+        const long o = (long)row * ld + col;
+        T val = p.alpha * acc[r];
+        if (X) val += p.beta * X[o];
+        if (X2) val += p.beta2 * X2[o];
+        if (row == col) val += p.gamma;
+        T val2 = 0;
+        if (C2) val2 = p.p1 * val + (row == col ? p.p0 : (T)0);
+        if (!SYM) {
+            C[o] = val;
+            if (C2) C2[o] = val2;
+        } else if (ti < tj || row <= col) {
+            const long ot = (long)col * ld + row;
+            C[o] = val;
+            C[ot] = val;
+            if (C2) {
+                C2[o] = val2;
+                C2[ot] = val2;
+            }
+        }
+    }
+}
+
+// Write one whole 128 x 128 output tile.
+template <typename T, bool SYM>
+__device__ __forceinline__ void epilogue(const GemmArgs<T> &p, long bz, int ti, int tj, int wr,
+                                         int wc, int fr, int fc,
+                                         const typename MF<T>::acc_t (&acc)[4][4]) {
+#pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = i0 + wr * 64 + x * 16 + M::out_row(fr, r);
-                const int col = j0 + wc * 64 + y * 16 + fc;
-                const long o = (long)row * ld + col;
-                T val = p.alpha * acc[x][y][r];
-                if (X) val += p.beta * X[o];
-                if (X2) val += p.beta2 * X2[o];
-                if (row == col) val += p.gamma;
-                T val2 = 0;
-                if (C2) val2 = p.p1 * val + (row == col ? p.p0 : (T)0);
-                if (!SYM) {
-                    C[o] = val;
-                    if (C2) C2[o] = val2;
-                } else if (ti < tj || row <= col) {
-                    const long ot = (long)col * ld + row;
-                    C[o] = val;
-                    C[ot] = val;
-                    if (C2) {
-                        C2[o] = val2;
-                        C2[ot] = val2;
-                    }
-                }
-            }
+            epilogue_block<T, SYM>(p, bz, ti, tj, wr, wc, fr, fc, x, y, acc[x][y]);
 }
 
 
@@ -436,36 +444,30 @@ __global__ __launch_bounds__(256, 2) void gemm_bf3_kernel(GemmArgs<float> p, int
     epilogue<float, SYM>(p, bz, ti, tj, wr, wc, fr, fc, acc);
 }
 
-// Sum the k-split partial tiles of each tile and apply the epilogue.  Same
-// thread layout as the product kernel, so every thread reads back exactly
-// the accumulators its counterpart wrote (contiguous 64 per thread).
+// Sum the k-split partial tiles of each tile and apply the epilogue.  One
+// workgroup per (tile, accumulator block g = 4x + y): every thread reads
+// back, from each partial, the one accumulator vector its counterpart in
+// the product kernel wrote for block g (4 KB contiguous per workgroup and
+// partial), so the reduction runs on 16 workgroups per tile.
 template <typename T, bool SYM>
 __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs<T> p, int ntiles, int nfull,
                                                          int nsplit) {
     using acc_t = typename MF<T>::acc_t;
     const int ntail = ntiles - nfull;
     const int u = nfull + blockIdx.x;
+    const int g = blockIdx.y, x = g >> 2, y = g & 3;
     const long bz = blockIdx.z;
     const int nt = p.n / GT;
     int ti, tj;
     tile_of<SYM>(u, nt, ti, tj);
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wr = wid >> 1, wc = wid & 1, fr = lane >> 4, fc = lane & 15;
-    acc_t acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-    for (int s = 0; s < nsplit; ++s) {
-        const acc_t *wp = reinterpret_cast<const acc_t *>(
-                              p.ws + ((long)bz * ntail * nsplit + (long)blockIdx.x * nsplit + s) *
-                                         (GT * GT)) + tid;
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) acc[x][y] += wp[(x * 4 + y) * 256];
-    }
-    epilogue<T, SYM>(p, bz, ti, tj, wr, wc, fr, fc, acc);
+    acc_t acc = acc_t{0, 0, 0, 0};
+    const acc_t *wp = reinterpret_cast<const acc_t *>(
+                          p.ws + ((long)bz * ntail * nsplit + (long)blockIdx.x * nsplit) *
+                                     (GT * GT)) + g * 256 + tid;
+    for (int s = 0; s < nsplit; ++s) acc += wp[(long)s * (GT * GT / 4)];
+    epilogue_block<T, SYM>(p, bz, ti, tj, wr, wc, fr, fc, x, y, acc);
 }
 
 inline int device_cus() {
@@ -557,7 +559,7 @@ void gemm(const GemmArgs<T> &a, bool sym, hipStream_t st) {
     }
     XL_LAUNCH_CHECK();
     if (s.nfull < ntiles) {
-        dim3 g2(ntiles - s.nfull, 1, a.batch);
+        dim3 g2(ntiles - s.nfull, 16, a.batch);
         if (sym)
             hipLaunchKernelGGL((gemm_fixup_kernel<T, true>), g2, dim3(256), 0, st, a, ntiles,
                                s.nfull, s.nsplit);

@@ -601,4 +601,21 @@ __global__ __launch_bounds__(256) void axpy_kernel(int n, double a, const double
     if (i < n) y[i] += a * x[i];
 }
 
+// out = wI I + sum_{m < M} w_m X_m over the whole ld x ld array (the
+// identity on the padded diagonal too; products of the padded arrays keep
+// the real block apart).
+struct LinComb {
+    const double *x[8];
+    double w[8];
+    int m;
+    double wI;
+};
+__global__ __launch_bounds__(256) void lincomb_kernel(long ld, LinComb lc, double *out) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ld * ld) return;
+    double v = (t / ld == t % ld) ? lc.wI : 0.0;
+    for (int m = 0; m < lc.m; ++m) v += lc.w[m] * lc.x[m][t];
+    out[t] = v;
+}
+
 }  // namespace xl

@@ -571,13 +571,14 @@ template <typename TF, typename TR> struct Sys : SysBase {
     static constexpr bool SAME = std::is_same<TF, TR>::value;
     bool resp_split = false;       // response products as split bf16x3 (TR = float)
     std::vector<TF *> Z, Yk;       // Z_0..Z_L, Y_0..Y_{L-1}
-    TF *Ys = nullptr, *Y2 = nullptr, *Am = nullptr, *E = nullptr, *Wk = nullptr;
+    std::vector<TF *> Ak;          // A_k = I + 4 Z_k^2, k < L (kept for the entropy)
+    TF *Ys = nullptr, *Y2 = nullptr, *E = nullptr, *Wk = nullptr;
     TF *Dc = nullptr, *ZL2 = nullptr;
     std::vector<TR *> Zr, Yr;      // response copies (alias when SAME)
     TR *Ysr = nullptr, *Y2r = nullptr;
     TR *Zp = nullptr, *Ap = nullptr, *Tb = nullptr;   // response batch buffers
     double *m3 = nullptr;
-    double *e64[8] = {};                              // FP64 energy workspace
+    double *e64[16] = {};                             // FP64 energy workspace
     int Lcap = 0, Lr = -1;                            // Lr: levels converted
 
     size_t mat() const { return (size_t)Np * Np; }
@@ -592,8 +593,9 @@ template <typename TF, typename TR> struct Sys : SysBase {
         if (cap <= Lcap) return;
         while ((int)Z.size() < cap + 1) Z.push_back(amat<TF>());
         while ((int)Yk.size() < cap) Yk.push_back(amat<TF>());
+        while ((int)Ak.size() < cap) Ak.push_back(amat<TF>());
         if (!Ys) {
-            Ys = amat<TF>(); Y2 = amat<TF>(); Am = amat<TF>(); E = amat<TF>();
+            Ys = amat<TF>(); Y2 = amat<TF>(); E = amat<TF>();
             Wk = amat<TF>(); Dc = amat<TF>(); ZL2 = amat<TF>();
             m3 = dalloc<double>(Np);
             mem.ptrs.push_back(m3);
@@ -686,6 +688,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
             const int ns = quad ? ns2 : ns1;
             ns_total += ns;
             auto a = base<TF>();
+            TF *Am = Ak[k];
             a.A0 = Z[k]; a.B0 = Z[k]; a.alpha = (TF)4.0; a.gamma = (TF)1.0; a.C = Am;
             if (!quad) {
                 a.C2 = Yk[k]; a.p0 = (TF)(8.0 * c / den); a.p1 = (TF)(-8.0 / den);
@@ -861,43 +864,83 @@ template <typename TF, typename TR> struct Sys : SysBase {
         const double ln2 = std::log(2.0);
         double lnF = std::ldexp(-N * ln2 + l0, L);
         for (int k = 0; k < L; ++k) {
-            const double *Zk = as64(Z[k], 2, 1.0);
-            GemmArgs<double> b = a;
-            b.A0 = Zk; b.B0 = Zk; b.alpha = 4.0; b.gamma = 1.0; b.C = C;
-            gemm(b, true, st);
+            if constexpr (std::is_same<TF, double>::value) {
+                // the expansion's own A_k (the factorisation overwrites its copy)
+                XL_HIP(hipMemcpyAsync(C, Ak[k], mat() * sizeof(double), hipMemcpyDeviceToDevice, st));
+            } else {
+                // FP32 expansion: A_k again in FP64 from Z_k
+                const double *Zk = as64(Z[k], 2, 1.0);
+                GemmArgs<double> b = a;
+                b.A0 = Zk; b.B0 = Zk; b.alpha = 4.0; b.gamma = 1.0; b.C = C;
+                gemm(b, true, st);
+            }
             lnF += std::ldexp(N * ln2 - logdet_lead(C), L - 1 - k);
         }
-        // series of atanh(T0): P_j = T0^(2j+1)
+        // X_eff = 2^(L+1) atanh(T0) = T0 q(W), W = T0^2, q(w) = sum_j c_j w^j
+        // with c_j = 2^(L+1) / (2j + 1), truncated where the next term is
+        // below 1e-14 in the trace; q by Paterson-Stockmeyer: baby steps
+        // W^0..W^s, then Horner in W^s over blocks of s coefficients
         const double *ZL = as64(Z[L], 2, 1.0);
-        double *Z2 = w64(3), *T0sq = w64(4), *P = w64(5), *Pn = w64(6);
+        double *Z2 = w64(3), *W = w64(4);
         {
             GemmArgs<double> b = a;
             b.A0 = ZL; b.B0 = ZL; b.C = Z2;
             gemm(b, true, st);
             b = a;
-            b.A0 = T0; b.B0 = T0; b.C = T0sq;
+            b.A0 = T0; b.B0 = T0; b.C = W;
             gemm(b, true, st);
         }
-        XL_HIP(hipMemcpyAsync(P, T0, mat() * sizeof(double), hipMemcpyDeviceToDevice, st));
-        double s1 = 0.0, s2 = 0.0;
         const double scale = std::ldexp(1.0, L + 1);
-        for (int j = 0; j < 64; ++j) {
-            const double cj = scale / (2 * j + 1);
-            hipLaunchKernelGGL(frob3_kernel, dim3(N), dim3(256), 0, st, N, Np, P, ZL, Z2, part);
-            XL_LAUNCH_CHECK();
-            hipLaunchKernelGGL(sum_rows_kernel, dim3(1), dim3(1024), 0, st, N, 3, part, scal + 52);
-            XL_LAUNCH_CHECK();
-            XL_HIP(hipMemcpyAsync(hscal + 52, scal + 52, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-            sync();
-            const double trP = hscal[52], zp = hscal[53], z2p = hscal[54];
-            s1 += cj * (0.5 * trP - zp);          // <1/2 I - Z_L, P>
-            s2 += cj * (trP - 4.0 * z2p);         // <P, I - 4 Z_L^2>
-            if (std::pow(t0max, 2 * j + 3) * scale / (2 * j + 3) * N < 1e-14) break;
+        int J = 0;
+        while (J < 63 && std::pow(t0max, 2 * J + 3) * scale / (2 * J + 3) * N >= 1e-14) ++J;
+        const int nc = J + 1;                                  // coefficients c_0..c_J
+        const int sps = std::max(1, (int)std::ceil(std::sqrt((double)nc)));
+        const int nblk = (nc + sps - 1) / sps;
+        std::vector<const double *> Wp(sps + 1, nullptr);      // Wp[l] = W^l (Wp[0] = I)
+        Wp[1] = W;
+        for (int l = 2; l <= sps; ++l) {
+            double *dst = w64(4 + l - 1);
             GemmArgs<double> b = a;
-            b.A0 = T0sq; b.B0 = P; b.C = Pn;
+            b.A0 = Wp[l - 1]; b.B0 = W; b.C = dst;
             gemm(b, true, st);
-            std::swap(P, Pn);
+            Wp[l] = dst;
         }
+        double *R = w64(4 + sps), *Rn = w64(5 + sps), *Bt = w64(6 + sps);
+        auto block = [&](int i, double *out) {   // sum_l c_{i s + l} W^l
+            LinComb lc{};
+            for (int l = 0; l < sps && i * sps + l < nc; ++l) {
+                const double c = scale / (2 * (i * sps + l) + 1);
+                if (l == 0) { lc.wI = c; continue; }
+                lc.x[lc.m] = Wp[l];
+                lc.w[lc.m] = c;
+                ++lc.m;
+            }
+            hipLaunchKernelGGL(lincomb_kernel, dim3(ceil_div((long)mat(), 256)), dim3(256), 0, st,
+                               (long)Np, lc, out);
+            XL_LAUNCH_CHECK();
+        };
+        block(nblk - 1, R);
+        for (int i = nblk - 2; i >= 0; --i) {
+            block(i, Bt);
+            GemmArgs<double> b = a;                   // R <- R W^s + B_i
+            b.A0 = R; b.B0 = Wp[sps]; b.X = Bt; b.beta = 1.0; b.C = Rn;
+            gemm(b, true, st);
+            std::swap(R, Rn);
+        }
+        {
+            GemmArgs<double> b = a;                   // X_eff = T0 q(W)
+            b.A0 = T0; b.B0 = R; b.C = Rn;
+            gemm(b, true, st);
+        }
+        hipLaunchKernelGGL(frob3_kernel, dim3(N), dim3(256), 0, st, N, Np, Rn, ZL, Z2, part);
+        XL_LAUNCH_CHECK();
+        hipLaunchKernelGGL(sum_rows_kernel, dim3(1), dim3(1024), 0, st, N, 3, part, scal + 52);
+        XL_LAUNCH_CHECK();
+        XL_HIP(hipMemcpyAsync(hscal + 52, scal + 52, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        const double trX = hscal[52], zx = hscal[53], z2x = hscal[54];
+        const double s1 = 0.5 * trX - zx;             // <1/2 I - Z_L, X_eff>
+        const double s2 = trX - 4.0 * z2x;            // <X_eff, I - 4 Z_L^2>
         const double S0 = 2.0 * (-lnF + s1);
         return S0 / beta + dmu * 0.5 * s2;
     }
