@@ -52,10 +52,13 @@ template <> struct MF<double> {
 // C = alpha * sum_s A_s^T B_s + beta * X + beta2 * X2 + gamma * I ; optionally
 // C2 = p0 * I + p1 * C.  A_s must be symmetric (A_s^T = A_s) for the result
 // to be the product A_s B_s.  kscale (optional) multiplies row k of B_0 by
-// kscale[k].  All matrices n x n with leading dimension ld; n % 128 == 0.
+// kscale[k].  Output n x n with leading dimension ld (also for X, X2, C2);
+// the operands are k x n with leading dimension lda (k = 0: k = n; lda = 0:
+// lda = ld).  n % 128 == 0, k % 32 == 0.
 // Batch index = blockIdx.z; strides in elements (0 = shared operand).
 template <typename T> struct GemmArgs {
     int n = 0, ld = 0, batch = 1;
+    int k = 0, lda = 0;     // contraction length and operand stride (0: n, ld)
     const T *A0 = nullptr, *B0 = nullptr, *A1 = nullptr, *B1 = nullptr;
     const T *X = nullptr, *X2 = nullptr;
     const double *kscale = nullptr;
@@ -189,7 +192,7 @@ __global__ __launch_bounds__(256, 2) void gemm_tn_kernel(GemmArgs<T> p, int ntil
     const T *A1 = p.A1 ? p.A1 + bz * p.sA1 : nullptr;
     const T *B1 = p.B1 ? p.B1 + bz * p.sB1 : nullptr;
     const double *ks = p.kscale ? p.kscale + bz * p.sK : nullptr;
-    const int ld = p.ld;
+    const int lda = p.lda ? p.lda : p.ld;
     const int i0 = ti * GT, j0 = tj * GT;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wr = wid >> 1, wc = wid & 1;
@@ -200,7 +203,7 @@ __global__ __launch_bounds__(256, 2) void gemm_tn_kernel(GemmArgs<T> p, int ntil
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
-    const int nk1 = p.n / BK;
+    const int nk1 = (p.k ? p.k : p.n) / BK;
     const int nktot = A1 ? 2 * nk1 : nk1;
     const int kt0 = (int)((long)nktot * split / ns);
     const int kt1 = (int)((long)nktot * (split + 1) / ns);
@@ -222,8 +225,8 @@ __global__ __launch_bounds__(256, 2) void gemm_tn_kernel(GemmArgs<T> p, int ntil
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const long k = kb + lrow[v];
-            ra[v] = *reinterpret_cast<const vec_t *>(Ap + k * ld + i0 + lcol[v]);
-            rb[v] = *reinterpret_cast<const vec_t *>(Bp + k * ld + j0 + lcol[v]);
+            ra[v] = *reinterpret_cast<const vec_t *>(Ap + k * lda + i0 + lcol[v]);
+            rb[v] = *reinterpret_cast<const vec_t *>(Bp + k * lda + j0 + lcol[v]);
             if (ks && !second) {
                 const T s = (T)ks[k];
 #pragma unroll
@@ -349,7 +352,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf3_kernel(GemmArgs<float> p, int
     const float *A1 = p.A1 ? p.A1 + bz * p.sA1 : nullptr;
     const float *B1 = p.B1 ? p.B1 + bz * p.sB1 : nullptr;
     const double *ks = p.kscale ? p.kscale + bz * p.sK : nullptr;
-    const int ld = p.ld;
+    const int lda = p.lda ? p.lda : p.ld;
     const int i0 = ti * GT, j0 = tj * GT;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wr = wid >> 1, wc = wid & 1;
@@ -360,16 +363,16 @@ __global__ __launch_bounds__(256, 2) void gemm_bf3_kernel(GemmArgs<float> p, int
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[a][c] = acc_t{0, 0, 0, 0};
 
-    const int nk1 = p.n / B3K;
+    const int nk1 = (p.k ? p.k : p.n) / B3K;
     const int nktot = A1 ? 2 * nk1 : nk1;
     const int kt0 = (int)((long)nktot * split / ns);
     const int kt1 = (int)((long)nktot * (split + 1) / ns);
 
     // loader: k rows 4 kq .. 4 kq + 3, tile columns 4 xv .. 4 xv + 3
-    // (loads run one k-tile ahead; two ahead measured no faster)
+    // (loads run one k-tile ahead)
     const int kq = tid & 7, xv = tid >> 3;
     f32x4 ra[4], rb[4];
-    auto gload = [&](f32x4 (&a)[4], f32x4 (&bv)[4], int kt) {
+    auto gload = [&](int kt) {
         const bool second = kt >= nk1;
         const float *Ap = second ? A1 : A0;
         const float *Bp = second ? B1 : B0;
@@ -377,29 +380,35 @@ __global__ __launch_bounds__(256, 2) void gemm_bf3_kernel(GemmArgs<float> p, int
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const long k = kb + v;
-            a[v] = *reinterpret_cast<const f32x4 *>(Ap + k * ld + i0 + 4 * xv);
-            bv[v] = *reinterpret_cast<const f32x4 *>(Bp + k * ld + j0 + 4 * xv);
-            if (ks && !second) bv[v] *= (float)ks[k];
+            ra[v] = *reinterpret_cast<const f32x4 *>(Ap + k * lda + i0 + 4 * xv);
+            rb[v] = *reinterpret_cast<const f32x4 *>(Bp + k * lda + j0 + 4 * xv);
+            if (ks && !second) rb[v] *= (float)ks[k];
         }
     };
     // column e of the 4 x 4 block: k-consecutive, split, one 8-byte store
     // per part
-    auto sstore = [&](const f32x4 (&a)[4], const f32x4 (&bv)[4], int buf) {
+    auto sstore = [&](int buf) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             unsigned h0, h1, l0, l1;
-            split_pair(a[0][e], a[1][e], h0, l0);
-            split_pair(a[2][e], a[3][e], h1, l1);
+            split_pair(ra[0][e], ra[1][e], h0, l0);
+            split_pair(ra[2][e], ra[3][e], h1, l1);
             *reinterpret_cast<u32x2 *>(&As[buf][0][4 * xv + e][2 * kq]) = u32x2{h0, h1};
             *reinterpret_cast<u32x2 *>(&As[buf][1][4 * xv + e][2 * kq]) = u32x2{l0, l1};
-            split_pair(bv[0][e], bv[1][e], h0, l0);
-            split_pair(bv[2][e], bv[3][e], h1, l1);
+            split_pair(rb[0][e], rb[1][e], h0, l0);
+            split_pair(rb[2][e], rb[3][e], h1, l1);
             *reinterpret_cast<u32x2 *>(&Bs[buf][0][4 * xv + e][2 * kq]) = u32x2{h0, h1};
             *reinterpret_cast<u32x2 *>(&Bs[buf][1][4 * xv + e][2 * kq]) = u32x2{l0, l1};
         }
     };
+
+    gload(kt0);
+    sstore(0);
+    __syncthreads();
     const int fr = lane >> 4, fc = lane & 15;
-    auto compute = [&](int buf) {
+    for (int kt = kt0; kt < kt1; ++kt) {
+        const int buf = (kt - kt0) & 1;
+        if (kt + 1 < kt1) gload(kt + 1);
         // fragment of lane (fr, fc): row fc of the 16-row block, k 8 fr .. 8 fr + 7
         bf16x8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
@@ -419,16 +428,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf3_kernel(GemmArgs<float> p, int
                 acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bl[y], acc[x][y], 0, 0, 0);
                 acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
             }
-    };
-
-    gload(ra, rb, kt0);
-    sstore(ra, rb, 0);
-    __syncthreads();
-    for (int kt = kt0; kt < kt1; ++kt) {
-        const int buf = (kt - kt0) & 1;
-        if (kt + 1 < kt1) gload(ra, rb, kt + 1);
-        compute(buf);
-        if (kt + 1 < kt1) sstore(ra, rb, buf ^ 1);
+        if (kt + 1 < kt1) sstore(buf ^ 1);
         __syncthreads();
     }
 
@@ -525,13 +525,14 @@ template <typename T> long split_ws_elems(int n, bool sym, int dual, long batch)
 
 template <typename T>
 void gemm(const GemmArgs<T> &a, bool sym, hipStream_t st) {
-    if (a.n % GT != 0 || a.ld % 4 != 0)
-        throw InvalidArg("gemm: n must be a multiple of 128");
+    const int K = a.k ? a.k : a.n;
+    if (a.n % GT != 0 || a.ld % 4 != 0 || K % 32 != 0 || (a.lda ? a.lda : a.ld) % 4 != 0)
+        throw InvalidArg("gemm: n must be a multiple of 128 and k of 32");
     if (a.split3 && !std::is_same<T, float>::value)
         throw InvalidArg("gemm: split bf16x3 products take FP32 operands");
     const int nt = a.n / GT;
     const int ntiles = sym ? nt * (nt + 1) / 2 : nt * nt;
-    const int nkt = (a.n / MF<T>::BK) * (a.A1 ? 2 : 1);
+    const int nkt = (K / MF<T>::BK) * (a.A1 ? 2 : 1);
     Sched s = a.ws ? schedule<T>(ntiles, nkt, a.batch) : Sched{ntiles, 1};
     if (s.nsplit > 1 && (long)(ntiles - s.nfull) * s.nsplit * a.batch * GT * GT > a.ws_elems)
         s = Sched{ntiles, 1};

@@ -844,9 +844,15 @@ template <typename TF, typename TR> struct Sys : SysBase {
         return dst;
     }
 
-    double logdet_lead(double *A) {   // ln det of the leading block, A destroyed
-        const int n32 = ((N + CB - 1) / CB) * CB;
-        chol_logdet(n32, Np, A, scal + 48, st);
+    double *cholP = nullptr;           // NB x Np panel workspace
+    double logdet(double *A) {         // ln det of the padded Np x Np array, A destroyed
+        if (!cholP) {
+            cholP = dalloc<double>((size_t)NB * Np);
+            mem.ptrs.push_back(cholP);
+        }
+        GemmArgs<double> w;
+        attach_ws(w);
+        chol_logdet(Np, Np, A, cholP, w.ws, w.ws_elems, scal + 48, st);
         XL_HIP(hipMemcpyAsync(hscal + 48, scal + 48, sizeof(double), hipMemcpyDeviceToHost, st));
         sync();
         return hscal[48];
@@ -855,12 +861,15 @@ template <typename TF, typename TR> struct Sys : SysBase {
     double entropy_ts() override {
         GemmArgs<double> a;
         a.n = Np; a.ld = Np;
+        attach_ws(a);                    // split-k for the N x N products
         const double *T0 = as64(Z[0], 0, 2.0);          // T0 = 2 Z_0
         double *C = w64(1);
+        // I + T0 over the padded array: the padding is an identity block
+        // (ln det 1 = 0), so the factorisation runs on whole 128-blocks
         hipLaunchKernelGGL(add_diag_copy_kernel, dim3(ceil_div((long)mat(), 256)), dim3(256), 0, st,
-                           Np, N, T0, 1.0, C);
+                           Np, Np, T0, 1.0, C);
         XL_LAUNCH_CHECK();
-        const double l0 = logdet_lead(C);                // ln det(I + T0)
+        const double l0 = logdet(C);                     // ln det(I + T0)
         const double ln2 = std::log(2.0);
         double lnF = std::ldexp(-N * ln2 + l0, L);
         for (int k = 0; k < L; ++k) {
@@ -874,7 +883,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
                 b.A0 = Zk; b.B0 = Zk; b.alpha = 4.0; b.gamma = 1.0; b.C = C;
                 gemm(b, true, st);
             }
-            lnF += std::ldexp(N * ln2 - logdet_lead(C), L - 1 - k);
+            lnF += std::ldexp(N * ln2 - logdet(C), L - 1 - k);
         }
         // X_eff = 2^(L+1) atanh(T0) = T0 q(W), W = T0^2, q(w) = sum_j c_j w^j
         // with c_j = 2^(L+1) / (2j + 1), truncated where the next term is
