@@ -14,6 +14,7 @@ Prints one JSON line.  The oracle (test infrastructure) is used only for the
 CPU baseline leg.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -49,6 +50,21 @@ def _stream():
 
 
 ENERGY_EVERY = 10   # free-energy report cadence (every 10th step, in the timed region)
+
+# HBM bytes per launch of each product class in this workload's timed
+# region (product kernel + its split-k fix-up, averaged over the launches),
+# from `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs of this
+# script scaled by the same counters' readings for a 1 GiB device copy
+# (profiles/gemm_counters_n4096.md).  Valid only for the product-kernel
+# source they were measured with.
+GEMM_SRC = os.path.join(ROOT, "paper_1705_10845_amd", "csrc", "gemm.hpp")
+TRAFFIC = {"sha256": None, "f64": None, "bf3": None}
+
+
+def traffic(key):
+    with open(GEMM_SRC, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()
+    return TRAFFIC.get(key) if h == TRAFFIC["sha256"] else None
 
 
 def time_path(system, precision, steps, warmup, label):
@@ -165,7 +181,7 @@ def main():
         p = prof[key]
         ach = p["flops"] / (p["ms"] * 1e-3) / 1e12 if p["ms"] > 0 else 0.0
         return {"bound": "mfma", "achieved": ach, "peak": PEAK[key], "unit": "TFLOP/s",
-                "frac": ach / PEAK[key], "traffic": None, "kernel": KERNEL[key],
+                "frac": ach / PEAK[key], "traffic": traffic(key), "kernel": KERNEL[key],
                 "launches": p["launches"], "avg_launch_ms": p["ms"] / max(1, p["launches"]),
                 "gemm_ms_per_step": p["ms"] / steps,
                 "other_classes_ms_per_step": {k: prof[k]["ms"] / steps for k in PEAK

@@ -4,9 +4,9 @@
 // spectrum in [1/2, 2], so no pivoting is needed.
 //
 // Outer panels of NB = 128 columns.  Inside a panel, inner panels of CB = 32
-// columns: one kernel factors the 32 x 32 diagonal block in LDS and solves
-// every row below it; a small kernel applies the inner panel to the rest of
-// the outer panel's columns.  The rank-128 update of the trailing matrix,
+// columns, one kernel launch each: it applies the panel's earlier inner
+// panels (left-looking), factors the 32 x 32 diagonal block in registers and
+// solves every row below it.  The rank-128 update of the trailing matrix,
 // which holds nearly all the flops, runs on the FP64 MFMA product kernel
 // (C = C - P^T P with P the transposed panel, symmetric output).
 #pragma once
@@ -18,79 +18,87 @@ namespace xl {
 constexpr int CB = 32;    // inner panel width
 constexpr int NB = 128;   // outer panel width
 
-// Factor the CB x CB diagonal block at (q, q) in LDS (lower), then solve
-// the rows below it: L_iq = A_iq L_qq^-T, one thread per row.  Every block
-// factors the diagonal block itself; block 0 writes it back and adds
-// 2 sum ln L_ii to *acc.  One wavefront per block (CHOL_PT threads), so the
-// 3 CB barriers of the factorisation are single-wave barriers.
+// lane value of a double held by lane `src` (a constant), broadcast
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Inner panel q (columns q .. q + CB) of the outer panel that starts at p,
+// left-looking over the outer panel's earlier inner panels (columns
+// p .. q, already final): one wavefront per block.
+//  1. the diagonal block A_qq - L_q,[p,q) L_q,[p,q)^T, row i in the
+//     registers of lane i, is factored in registers (pivot and column
+//     entries broadcast from their lanes);
+//  2. every row i below is updated the same way and solved against the
+//     factor: L_iq = (A_iq - L_i,[p,q) L_q,[p,q)^T) L_qq^-T.
+// Block 0 writes the factored diagonal block and adds 2 sum ln L_ii to *acc.
 constexpr int CHOL_PT = 64;
-__global__ __launch_bounds__(CHOL_PT) void chol_panel_kernel(int n, int ld, int q, double *A,
-                                                             double *acc) {
-    __shared__ double L[CB][CB + 1];
-    for (int t = threadIdx.x; t < CB * CB; t += blockDim.x)
-        L[t / CB][t % CB] = A[(long)(q + t / CB) * ld + q + t % CB];
+__global__ __launch_bounds__(CHOL_PT) void chol_panel_kernel(int n, int ld, int p, int q,
+                                                             double *A, double *acc) {
+    __shared__ double Lp[CB][NB - CB + 1];   // L[q + j][p + k], k < q - p
+    __shared__ double Ld[CB][CB + 1];        // factored diagonal block
+    const int w = q - p, lane = threadIdx.x;
+    for (int t = lane; t < CB * w; t += CHOL_PT)
+        Lp[t / w][t % w] = A[(long)(q + t / w) * ld + p + t % w];
     __syncthreads();
-    for (int k = 0; k < CB; ++k) {
-        const double d = sqrt(L[k][k]);
-        __syncthreads();                       // every thread has read L_kk
-        if (threadIdx.x == 0) L[k][k] = d;
-        if (threadIdx.x > k && threadIdx.x < CB) L[threadIdx.x][k] /= d;
-        __syncthreads();
-        for (int t = threadIdx.x; t < CB * CB; t += blockDim.x) {
-            const int i = t / CB, j = t % CB;
-            if (j > k && j <= i) L[i][j] -= L[i][k] * L[j][k];
-        }
-        __syncthreads();
+    double row[CB];
+    const int ri = lane < CB ? lane : CB - 1;   // lanes >= CB shadow the last row
+#pragma unroll
+    for (int j = 0; j < CB; ++j) row[j] = A[(long)(q + ri) * ld + q + j];
+    for (int k = 0; k < w; ++k) {
+        const double lik = Lp[ri][k];
+#pragma unroll
+        for (int j = 0; j < CB; ++j) row[j] -= lik * Lp[j][k];
     }
-    if (blockIdx.x == 0) {
-        for (int t = threadIdx.x; t < CB * CB; t += blockDim.x) {
-            const int i = t / CB, j = t % CB;
-            A[(long)(q + i) * ld + q + j] = (j <= i) ? L[i][j] : 0.0;
+#pragma unroll
+    for (int k = 0; k < CB; ++k) {
+        const double d = sqrt(lane_bcast(row[k], k));
+        row[k] = (lane == k) ? d : row[k] / d;         // L_ik for i > k
+#pragma unroll
+        for (int j = k + 1; j < CB; ++j) {
+            const double ljk = lane_bcast(row[k], j);
+            if (lane > k) row[j] -= row[k] * ljk;
         }
-        if (threadIdx.x == 0) {
+    }
+    if (lane < CB) {
+#pragma unroll
+        for (int j = 0; j < CB; ++j) Ld[lane][j] = (j <= lane) ? row[j] : 0.0;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        if (lane < CB) {
+#pragma unroll
+            for (int j = 0; j < CB; ++j) A[(long)(q + lane) * ld + q + j] = Ld[lane][j];
+        }
+        if (lane == 0) {
             double s = 0.0;
-            for (int k = 0; k < CB; ++k) s += log(L[k][k]);
+            for (int k = 0; k < CB; ++k) s += log(Ld[k][k]);
             acc[0] += 2.0 * s;
         }
     }
-    const int i = q + CB + blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = q + CB + blockIdx.x * CHOL_PT + lane;
     if (i >= n) return;
     double x[CB];
-    double *row = A + (long)i * ld + q;
+    double *rowp = A + (long)i * ld;
+#pragma unroll
+    for (int j = 0; j < CB; ++j) x[j] = rowp[q + j];
+    for (int k = 0; k < w; ++k) {
+        const double lik = rowp[p + k];
+#pragma unroll
+        for (int j = 0; j < CB; ++j) x[j] -= lik * Lp[j][k];
+    }
+#pragma unroll
     for (int k = 0; k < CB; ++k) {
-        double s = row[k];
-        for (int t = 0; t < k; ++t) s -= x[t] * L[k][t];
-        x[k] = s / L[k][k];
+        double s = x[k];
+#pragma unroll
+        for (int t = 0; t < k; ++t) s -= x[t] * Ld[k][t];
+        x[k] = s / Ld[k][k];
     }
-    for (int k = 0; k < CB; ++k) row[k] = x[k];
-}
-
-// Apply the inner panel (columns q .. q + CB) to the columns
-// [q + CB, jend) of the outer panel: A_ij -= sum_k L_ik L_jk for i >= j,
-// 64 x 64 tiles, 256 threads (4 x 4 per thread).
-__global__ __launch_bounds__(256) void chol_update_kernel(int n, int ld, int q, int jend,
-                                                          double *A) {
-    const int tj = blockIdx.x, ti = blockIdx.y;
-    const int base = q + CB;
-    const int i0 = base + ti * 64, j0 = base + tj * 64;
-    if (j0 >= i0 + 64) return;               // strictly upper tile
-    __shared__ double Li[64][CB + 1], Lj[64][CB + 1];
-    for (int t = threadIdx.x; t < 64 * CB; t += 256) {
-        const int r = t / CB, k = t % CB;
-        Li[r][k] = (i0 + r < n) ? A[(long)(i0 + r) * ld + q + k] : 0.0;
-        Lj[r][k] = (j0 + r < jend) ? A[(long)(j0 + r) * ld + q + k] : 0.0;
-    }
-    __syncthreads();
-    const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
-    double s[4][4] = {};
-    for (int k = 0; k < CB; ++k)
-        for (int a = 0; a < 4; ++a)
-            for (int b = 0; b < 4; ++b) s[a][b] += Li[tr + 16 * a][k] * Lj[tc + 16 * b][k];
-    for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b) {
-            const int i = i0 + tr + 16 * a, j = j0 + tc + 16 * b;
-            if (i < n && j < jend && j <= i) A[(long)i * ld + j] -= s[a][b];
-        }
+#pragma unroll
+    for (int j = 0; j < CB; ++j) rowp[q + j] = x[j];
 }
 
 // P[k][i] = A[(r0 + i) ld + c0 + k] for k < NB, i < m (P has leading
@@ -121,14 +129,8 @@ inline void chol_logdet(int n, int ld, double *A, double *P, double *ws, long ws
         for (int q = p; q < pe; q += CB) {
             const int rest = n - q - CB;
             hipLaunchKernelGGL(chol_panel_kernel, dim3(std::max(1, ceil_div(rest, CHOL_PT))),
-                               dim3(CHOL_PT), 0, st, n, ld, q, A, out);
+                               dim3(CHOL_PT), 0, st, n, ld, p, q, A, out);
             XL_LAUNCH_CHECK();
-            if (q + CB < pe) {
-                hipLaunchKernelGGL(chol_update_kernel,
-                                   dim3(ceil_div(pe - q - CB, 64), ceil_div(rest, 64)), dim3(256),
-                                   0, st, n, ld, q, pe, A);
-                XL_LAUNCH_CHECK();
-            }
         }
         const int m = n - pe;
         if (m <= 0) break;
