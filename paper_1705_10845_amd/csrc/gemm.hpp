@@ -63,6 +63,7 @@ template <typename T> struct GemmArgs {
     const T *X = nullptr, *X2 = nullptr;
     const double *kscale = nullptr;
     T *C = nullptr, *C2 = nullptr;
+    float *Cf = nullptr;    // optional FP32 copy of C (FP64 products only)
     T alpha = 1, beta = 0, beta2 = 0, gamma = 0, p0 = 0, p1 = 0;
     long sA0 = 0, sB0 = 0, sA1 = 0, sB1 = 0, sX = 0, sX2 = 0, sC = 0, sC2 = 0, sK = 0;
     T *ws = nullptr;        // split-k partial tiles (nullptr: no split)
@@ -107,6 +108,7 @@ __device__ __forceinline__ void epilogue_block(const GemmArgs<T> &p, long bz, in
     T *C2 = p.C2 ? p.C2 + bz * p.sC2 : nullptr;
     const T *X = p.X ? p.X + bz * p.sX : nullptr;
     const T *X2 = p.X2 ? p.X2 + bz * p.sX2 : nullptr;
+    float *Cf = p.Cf ? p.Cf + bz * p.sC : nullptr;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int row = i0 + wr * 64 + x * 16 + M::out_row(fr, r);
@@ -121,6 +123,7 @@ __device__ __forceinline__ void epilogue_block(const GemmArgs<T> &p, long bz, in
         if (!SYM) {
             C[o] = val;
             if (C2) C2[o] = val2;
+            if (Cf) Cf[o] = (float)val;
         } else if (ti < tj || row <= col) {
             const long ot = (long)col * ld + row;
             C[o] = val;
@@ -128,6 +131,10 @@ __device__ __forceinline__ void epilogue_block(const GemmArgs<T> &p, long bz, in
             if (C2) {
                 C2[o] = val2;
                 C2[ot] = val2;
+            }
+            if (Cf) {
+                Cf[o] = (float)val;
+                Cf[ot] = (float)val;
             }
         }
     }

@@ -643,6 +643,16 @@ template <typename TF, typename TR> struct Sys : SysBase {
         XL_LAUNCH_CHECK();
     }
 
+    // FP32 copies of the response operands, written by the expansion's own
+    // product epilogues when the two precisions differ (no separate pass)
+    static constexpr bool FUSE_COPY = !SAME && std::is_same<TF, double>::value &&
+                                      std::is_same<TR, float>::value;
+    void alloc_resp_copies() {
+        while ((int)Zr.size() < L + 1) Zr.push_back(amat<TR>());
+        while ((int)Yr.size() < L) Yr.push_back(amat<TR>());
+        if (!Ysr) { Ysr = amat<TR>(); Y2r = amat<TR>(); }
+    }
+
     void foe(double mu0) override {
         const double xmax = beta * std::max(std::fabs(elo - mu0), std::fabs(ehi - mu0)) * 1.02 + 1e-12;
         // truncation bound of the expansion vs the Fermi function: 2e-10 for
@@ -650,6 +660,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
         L = choose_levels(xmax, d.precision == XLBOMD_FP64 ? 2e-10 : 1e-9);
         alloc_matrices(L);
         Lr = -1;
+        if constexpr (FUSE_COPY) alloc_resp_copies();
         sc = std::ldexp(beta, -(L + 1));
         // Y = sc (H - mu0 I)
         hipLaunchKernelGGL((build_seed_kernel<TF>), dim3(ceil_div(Np, 256), Np), dim3(256), 0, st,
@@ -660,10 +671,12 @@ template <typename TF, typename TR> struct Sys : SysBase {
         {   // Y2 = Y Y ; Z0 = Y/2 - Y Y2 / 6
             auto a = base<TF>();
             a.A0 = Ys; a.B0 = Ys; a.C = Y2;
+            if constexpr (FUSE_COPY) a.Cf = Y2r;
             run_gemm(a, true);
             a = base<TF>();
             a.A0 = Ys; a.B0 = Y2; a.X = Ys; a.alpha = (TF)(-1.0 / 6.0); a.beta = (TF)0.5;
             a.C = Z[0];
+            if constexpr (FUSE_COPY) a.Cf = Zr[0];
             run_gemm(a, true);
         }
         // Newton-Schulz target per level: far below the truncation bound
@@ -701,6 +714,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
                 q.alpha = (TF)(-4.0 * al * al * al / D3);
                 q.X = Am; q.beta = (TF)(-12.0 * al * al * be / D3);
                 q.gamma = (TF)(-(12.0 * al * be * be - 3.0 * al) / D3);
+                if constexpr (FUSE_COPY) if (ns == 0) q.Cf = Yr[k];
                 run_gemm(q, true);
             }
             for (int j = 0; j < ns; ++j) {
@@ -709,11 +723,14 @@ template <typename TF, typename TR> struct Sys : SysBase {
                 run_gemm(e1, true);
                 auto e2 = base<TF>();   // Y <- Y E
                 e2.A0 = Yk[k]; e2.B0 = E; e2.C = Wk;
+                if constexpr (FUSE_COPY) if (j + 1 == ns) e2.Cf = Yr[k];
                 run_gemm(e2, true);
                 std::swap(Yk[k], Wk);
             }
+            if constexpr (FUSE_COPY) if (ns == 0 && !quad) convert(Yk[k], Yr[k], 1.0);
             auto z = base<TF>();        // Z_{k+1} = 2 Y_k Z_k
             z.A0 = Yk[k]; z.B0 = Z[k]; z.alpha = (TF)2.0; z.C = Z[k + 1];
+            if constexpr (FUSE_COPY) z.Cf = Zr[k + 1];
             run_gemm(z, true);
             t = 2.0 * t / (1.0 + t * t);
         }
@@ -728,6 +745,10 @@ template <typename TF, typename TR> struct Sys : SysBase {
         hipLaunchKernelGGL((mu_step_kernel<TF>), dim3(1), dim3(1024), 0, st, N, Np, Z[L], ZL2, m3,
                            beta, d.n_electrons, g, scal);
         XL_LAUNCH_CHECK();
+        if constexpr (FUSE_COPY) {
+            convert(Ys, Ysr, 1.0);
+            Lr = L;                     // response operands are current
+        }
     }
 
     void finish_density() override {
