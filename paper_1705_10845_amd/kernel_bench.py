@@ -25,15 +25,16 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--copy-gib", type=float, default=0.0)
     args = ap.parse_args(argv)
+    if args.copy_gib > 0:
+        import torch    # before the library: the copy runs on torch's runtime
     from . import binding as B
     B.lib()
     if args.copy_gib > 0:
-        import torch
         x = torch.ones(int(args.copy_gib * (1 << 30)) // 8, dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
-        y = torch.empty_like(x)
-        y.copy_(x)
+        y = x.clone()
         torch.cuda.synchronize()
+        del x, y
         print(f"copy: {args.copy_gib} GiB read, {args.copy_gib} GiB written", flush=True)
     n = args.n
     for prec in (int(p) for p in args.prec.split(",")):
