@@ -51,8 +51,8 @@ template <> struct MF<double> {
 
 // C = alpha * sum_s A_s^T B_s + beta * X + beta2 * X2 + gamma * I ; optionally
 // C2 = p0 * I + p1 * C.  A_s must be symmetric (A_s^T = A_s) for the result
-// to be the product A_s B_s.  kscale (optional) multiplies row k of B_0 by
-// kscale[k].  Output n x n with leading dimension ld (also for X, X2, C2);
+// to be the product A_s B_s.  kscale (optional) multiplies row k of B_0 (and
+// of B_1 with kscale_both) by kscale[k].  Output n x n with leading dimension ld (also for X, X2, C2);
 // the operands are k x n with leading dimension lda (k = 0: k = n; lda = 0:
 // lda = ld).  n % 128 == 0, k % 32 == 0.
 // Batch index = blockIdx.z; strides in elements (0 = shared operand).
@@ -62,6 +62,7 @@ template <typename T> struct GemmArgs {
     const T *A0 = nullptr, *B0 = nullptr, *A1 = nullptr, *B1 = nullptr;
     const T *X = nullptr, *X2 = nullptr;
     const double *kscale = nullptr;
+    bool kscale_both = false;   // also scale row k of B_1 (else B_0 only)
     T *C = nullptr, *C2 = nullptr;
     float *Cf = nullptr;    // optional FP32 copy of C (FP64 products only)
     T alpha = 1, beta = 0, beta2 = 0, gamma = 0, p0 = 0, p1 = 0;
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(256, 2) void gemm_tn_kernel(GemmArgs<T> p, int ntil
             const long k = kb + lrow[v];
             ra[v] = *reinterpret_cast<const vec_t *>(Ap + k * lda + i0 + lcol[v]);
             rb[v] = *reinterpret_cast<const vec_t *>(Bp + k * lda + j0 + lcol[v]);
-            if (ks && !second) {
+            if (ks && (!second || p.kscale_both)) {
                 const T s = (T)ks[k];
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) rb[v][e] *= s;
@@ -389,7 +390,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf3_kernel(GemmArgs<float> p, int
             const long k = kb + v;
             ra[v] = *reinterpret_cast<const f32x4 *>(Ap + k * lda + i0 + 4 * xv);
             rb[v] = *reinterpret_cast<const f32x4 *>(Bp + k * lda + j0 + 4 * xv);
-            if (ks && !second) rb[v] *= (float)ks[k];
+            if (ks && (!second || p.kscale_both)) rb[v] *= (float)ks[k];
         }
     };
     // column e of the 4 x 4 block: k-consecutive, split, one 8-byte store

@@ -327,13 +327,18 @@ __global__ __launch_bounds__(1024) void sum_rows_kernel(int n, int k,
     }
 }
 
-// Seed derivative of the response: with G = Y diag(u) Y and Y2 = Y^2,
-//   Z'_0 = 1/2 diag(u) - 1/6 [G + diag(u) Y2 + Y2 diag(u)].
+// Seed derivative of the response.  The seed is the quintic
+// Z_0 = Y/2 - Y^3/6 + Y^5/15, Y = sc (H - mu I); along Y' = diag(u):
+//   Z'_0 = 1/2 D - 1/6 [D Y2 + G + Y2 D]
+//        + 1/15 [D Y4 + H13 + H2 + Y4 D],  D = diag(u),
+// with G = Y D Y, H2 = Y2 D Y2, H13 = Y D Y3 + Y3 D Y (products done by the
+// caller).  Elementwise, so Zp may alias H13.
 template <typename T>
-__global__ __launch_bounds__(256) void seed_resp_kernel(int n, int ld,
-                                                        const T *G, const T *Y2,
-                                                        const double *u,
-                                                        long su, long sG, T *Zp) {
+__global__ __launch_bounds__(256) void seed_resp_kernel(int n, int ld, const T *G,
+                                                        const T *H2, const T *H13,
+                                                        const T *Y2, const T *Y4,
+                                                        const double *u, long su, long sG,
+                                                        T *Zp) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
     const long b = blockIdx.z;
@@ -342,7 +347,9 @@ __global__ __launch_bounds__(256) void seed_resp_kernel(int n, int ld,
     double val = 0.0;
     if (i < n && j < n) {
         const double ui = u[b * su + i], uj = u[b * su + j];
-        val = -(1.0 / 6.0) * ((double)G[b * sG + o] + (ui + uj) * (double)Y2[o]);
+        val = -(1.0 / 6.0) * ((double)G[b * sG + o] + (ui + uj) * (double)Y2[o]) +
+              (1.0 / 15.0) * ((double)H13[b * sG + o] + (double)H2[b * sG + o] +
+                              (ui + uj) * (double)Y4[o]);
         if (i == j) val += 0.5 * ui;
     }
     Zp[b * sG + o] = (T)val;

@@ -95,16 +95,18 @@ double fermi(double x) {
 // The scalar map the matrix expansion applies to each eigenvalue.
 double foe_scalar(double x, int L) {
     const double y = std::ldexp(x, -(L + 1));
-    double t = y - y * y * y / 3.0;
+    const double y2 = y * y;
+    double t = y * (1.0 - y2 / 3.0 + 2.0 * y2 * y2 / 15.0);   // tanh(y) to O(y^7)
     for (int k = 0; k < L; ++k) t = 2.0 * t / (1.0 + t * t);
     return 0.5 * (1.0 - t);
 }
 
-// Smallest L whose expansion keeps |y| <= 1/2 and stays within `tol` of the
-// Fermi function on [-xmax, xmax].
+// Smallest L whose expansion keeps |y| <= 1 (where the quintic seed is
+// increasing and below 1) and stays within `tol` of the Fermi function on
+// [-xmax, xmax].
 int choose_levels(double xmax, double tol) {
     for (int L = 1; L <= 40; ++L) {
-        if (std::ldexp(xmax, -(L + 1)) > 0.5) continue;
+        if (std::ldexp(xmax, -(L + 1)) > 1.0) continue;
         double err = 0.0;
         const int G = 2000;
         for (int g = 0; g <= G; ++g) {
@@ -572,10 +574,10 @@ template <typename TF, typename TR> struct Sys : SysBase {
     bool resp_split = false;       // response products as split bf16x3 (TR = float)
     std::vector<TF *> Z, Yk;       // Z_0..Z_L, Y_0..Y_{L-1}
     std::vector<TF *> Ak;          // A_k = I + 4 Z_k^2, k < L (kept for the entropy)
-    TF *Ys = nullptr, *Y2 = nullptr, *E = nullptr, *Wk = nullptr;
+    TF *Ys = nullptr, *Y2 = nullptr, *Y3 = nullptr, *E = nullptr, *Wk = nullptr;
     TF *Dc = nullptr, *ZL2 = nullptr;
     std::vector<TR *> Zr, Yr;      // response copies (alias when SAME)
-    TR *Ysr = nullptr, *Y2r = nullptr;
+    TR *Ysr = nullptr, *Y2r = nullptr, *Y3r = nullptr, *Y4r = nullptr;
     TR *Zp = nullptr, *Ap = nullptr, *Tb = nullptr;   // response batch buffers
     double *m3 = nullptr;
     double *e64[16] = {};                             // FP64 energy workspace
@@ -595,7 +597,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
         while ((int)Yk.size() < cap) Yk.push_back(amat<TF>());
         while ((int)Ak.size() < cap) Ak.push_back(amat<TF>());
         if (!Ys) {
-            Ys = amat<TF>(); Y2 = amat<TF>(); E = amat<TF>();
+            Ys = amat<TF>(); Y2 = amat<TF>(); Y3 = amat<TF>(); E = amat<TF>();
             Wk = amat<TF>(); Dc = amat<TF>(); ZL2 = amat<TF>();
             m3 = dalloc<double>(Np);
             mem.ptrs.push_back(m3);
@@ -650,7 +652,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
     void alloc_resp_copies() {
         while ((int)Zr.size() < L + 1) Zr.push_back(amat<TR>());
         while ((int)Yr.size() < L) Yr.push_back(amat<TR>());
-        if (!Ysr) { Ysr = amat<TR>(); Y2r = amat<TR>(); }
+        if (!Ysr) { Ysr = amat<TR>(); Y2r = amat<TR>(); Y3r = amat<TR>(); }
     }
 
     void foe(double mu0) override {
@@ -660,21 +662,27 @@ template <typename TF, typename TR> struct Sys : SysBase {
         L = choose_levels(xmax, d.precision == XLBOMD_FP64 ? 2e-10 : 1e-9);
         alloc_matrices(L);
         Lr = -1;
+        ++expansion_id;
         if constexpr (FUSE_COPY) alloc_resp_copies();
         sc = std::ldexp(beta, -(L + 1));
         // Y = sc (H - mu0 I)
         hipLaunchKernelGGL((build_seed_kernel<TF>), dim3(ceil_div(Np, 256), Np), dim3(256), 0, st,
                            md, vpot, mu0, sc, Ys);
         XL_LAUNCH_CHECK();
-        const double ymax = std::ldexp(xmax, -(L + 1));
-        t0max = ymax - ymax * ymax * ymax / 3.0;
-        {   // Y2 = Y Y ; Z0 = Y/2 - Y Y2 / 6
+        const double ymax = std::ldexp(xmax, -(L + 1)), ym2 = ymax * ymax;
+        t0max = ymax * (1.0 - ym2 / 3.0 + 2.0 * ym2 * ym2 / 15.0);
+        {   // Y2 = Y Y ; Y3 = Y Y2 ; Z0 = Y/2 - Y3/6 + Y3 Y2 / 15 (= tanh(Y)/2 to O(Y^7))
             auto a = base<TF>();
             a.A0 = Ys; a.B0 = Ys; a.C = Y2;
             if constexpr (FUSE_COPY) a.Cf = Y2r;
             run_gemm(a, true);
             a = base<TF>();
-            a.A0 = Ys; a.B0 = Y2; a.X = Ys; a.alpha = (TF)(-1.0 / 6.0); a.beta = (TF)0.5;
+            a.A0 = Ys; a.B0 = Y2; a.C = Y3;
+            if constexpr (FUSE_COPY) a.Cf = Y3r;
+            run_gemm(a, true);
+            a = base<TF>();
+            a.A0 = Y3; a.B0 = Y2; a.alpha = (TF)(1.0 / 15.0);
+            a.X = Y3; a.beta = (TF)(-1.0 / 6.0); a.X2 = Ys; a.beta2 = (TF)0.5;
             a.C = Z[0];
             if constexpr (FUSE_COPY) a.Cf = Zr[0];
             run_gemm(a, true);
@@ -773,23 +781,32 @@ template <typename TF, typename TR> struct Sys : SysBase {
 
     // response operands in TR (converted once per expansion when TF != TR)
     void response_operands() {
-        if (Lr == L) return;
-        if constexpr (SAME) {
-            Zr.assign(Z.begin(), Z.end());
-            Yr.assign(Yk.begin(), Yk.end());
-            Ysr = (TR *)Ys;
-            Y2r = (TR *)Y2;
-        } else {
-            while ((int)Zr.size() < L + 1) Zr.push_back(amat<TR>());
-            while ((int)Yr.size() < L) Yr.push_back(amat<TR>());
-            if (!Ysr) { Ysr = amat<TR>(); Y2r = amat<TR>(); }
-            for (int k = 0; k <= L; ++k) convert(Z[k], Zr[k], 1.0);
-            for (int k = 0; k < L; ++k) convert(Yk[k], Yr[k], 1.0);
-            convert(Ys, Ysr, 1.0);
-            convert(Y2, Y2r, 1.0);
+        if (Lr != L) {
+            if constexpr (SAME) {
+                Zr.assign(Z.begin(), Z.end());
+                Yr.assign(Yk.begin(), Yk.end());
+                Ysr = (TR *)Ys;
+                Y2r = (TR *)Y2;
+                Y3r = (TR *)Y3;
+            } else {
+                alloc_resp_copies();
+                for (int k = 0; k <= L; ++k) convert(Z[k], Zr[k], 1.0);
+                for (int k = 0; k < L; ++k) convert(Yk[k], Yr[k], 1.0);
+                convert(Ys, Ysr, 1.0);
+                convert(Y2, Y2r, 1.0);
+                convert(Y3, Y3r, 1.0);
+            }
+            Lr = L;
         }
-        Lr = L;
+        if (Y4_for != expansion_id) {   // Y^4 for the seed response, in TR
+            if (!Y4r) Y4r = amat<TR>();
+            auto a = base<TR>();
+            a.A0 = Y2r; a.B0 = Y2r; a.C = Y4r; a.split3 = resp_split;
+            run_gemm(a, true);
+            Y4_for = expansion_id;
+        }
     }
+    long expansion_id = 0, Y4_for = -1;    // expansion counter, Y^4 made for
 
     void responses(int nb, const double *v, double *qout, double *wout) override {
         if (nb <= 0) return;
@@ -803,14 +820,18 @@ template <typename TF, typename TR> struct Sys : SysBase {
         hipLaunchKernelGGL(expand_orbital_kernel, dim3(ceil_div((long)N * nb, 256)), dim3(256), 0,
                            st, nat, no, nb, sc, hb, (long)Np, ub);
         XL_LAUNCH_CHECK();
-        {   // G = Y diag(u) Y, then Z'_0
+        {   // G = Y D Y, H2 = Y2 D Y2, H13 = Y D Y3 + Y3 D Y, then Z'_0
             auto a = base<TR>();
             a.batch = nb; a.A0 = Ysr; a.B0 = Ysr; a.kscale = ub; a.sK = Np;
             a.split3 = resp_split;
             a.C = Tb; a.sC = sm;
             run_gemm(a, true);
+            a.A0 = Y2r; a.B0 = Y2r; a.C = Ap;
+            run_gemm(a, true);
+            a.A0 = Ysr; a.B0 = Y3r; a.A1 = Y3r; a.B1 = Ysr; a.kscale_both = true; a.C = Zp;
+            run_gemm(a, true);
             hipLaunchKernelGGL((seed_resp_kernel<TR>), dim3(ceil_div(Np, 256), Np, nb), dim3(256),
-                               0, st, N, Np, Tb, Y2r, ub, (long)Np, sm, Zp);
+                               0, st, N, Np, Tb, Ap, Zp, Y2r, Y4r, ub, (long)Np, sm, Zp);
             XL_LAUNCH_CHECK();
         }
         for (int k = 0; k < L; ++k) {
