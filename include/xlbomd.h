@@ -212,6 +212,17 @@ int xlbomd_selftest_gemm(int32_t n, int32_t precision, int32_t sym, const double
 int xlbomd_selftest_gemm_time(int32_t n, int32_t precision, int32_t sym, int32_t dual,
                               int32_t reps, double *ms_per_launch);
 
+/* Kernel-level test hook for the split product on pre-split operands (the
+ * MIXED_BF16X3 response recursion): A and B (n x n row-major host arrays,
+ * n a positive multiple of 128) are rounded to FP32 and stored as bf16
+ * hi/lo planes; C = A B^T, i.e. C[i][j] = sum_k A[i][k] B[j][k], with the
+ * result itself stored split and returned as hi + lo.  sym != 0 computes the
+ * upper block triangle and mirrors it (valid when A B^T is symmetric).  With
+ * reps > 0 the product is then launched reps more times and *ms_per_launch
+ * receives the average time.  Synchronous. */
+int xlbomd_selftest_gemm_presplit(int32_t n, int32_t sym, int32_t reps, const double *A,
+                                  const double *B, double *C, double *ms_per_launch);
+
 void xlbomd_destroy(xlbomd_system *h);
 
 /* Message of the last failed call on this thread ("" if none). */

@@ -84,6 +84,7 @@ def lib():
         L.xlbomd_selftest_gemm.argtypes = [ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_int32, _dp, _dp, _dp]
         L.xlbomd_selftest_gemm_time.argtypes = [ctypes.c_int32] * 5 + [_dp]
+        L.xlbomd_selftest_gemm_presplit.argtypes = [ctypes.c_int32] * 3 + [_dp, _dp, _dp, _dp]
         L.xlbomd_destroy.argtypes = [vp]
         L.xlbomd_destroy.restype = None
         L.xlbomd_last_error.restype = ctypes.c_char_p
@@ -97,7 +98,8 @@ EXPORTED = ("xlbomd_init_system", "xlbomd_step", "xlbomd_step_batch",
             "xlbomd_forces", "xlbomd_get_charges", "xlbomd_set_state",
             "xlbomd_get_state", "xlbomd_solve", "xlbomd_response",
             "xlbomd_kernel_apply", "xlbomd_profile", "xlbomd_selftest_gemm",
-            "xlbomd_selftest_gemm_time", "xlbomd_destroy", "xlbomd_last_error",
+            "xlbomd_selftest_gemm_time", "xlbomd_selftest_gemm_presplit",
+            "xlbomd_destroy", "xlbomd_last_error",
             "xlbomd_version")
 
 
@@ -137,6 +139,18 @@ def selftest_gemm_time(n, precision=FP64, sym=False, dual=False, reps=10):
     _check(lib().xlbomd_selftest_gemm_time(n, precision, int(sym), int(dual),
                                            reps, _ptr(out)))
     return float(out[0])
+
+
+def selftest_gemm_presplit(A, B, sym=False, reps=0):
+    """C = A B^T with the split product on pre-split operands (test hook).
+    Returns C, or (C, ms per launch) when reps > 0."""
+    A = _c(A); B = _c(B)
+    n = A.shape[0]
+    C = np.zeros((n, n))
+    ms = np.zeros(1)
+    _check(lib().xlbomd_selftest_gemm_presplit(n, 1 if sym else 0, reps, _ptr(A), _ptr(B),
+                                               _ptr(C), _ptr(ms)))
+    return (C, float(ms[0])) if reps > 0 else C
 
 
 def step_batch(systems, n_steps=1):

@@ -26,6 +26,39 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 typedef double f64x2v __attribute__((ext_vector_type(2)));
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// hi and lo bf16 pairs of two FP32 values (element 0 in the low half)
+__device__ __forceinline__ void split_pair(float x0, float x1, unsigned &hi, unsigned &lo) {
+    const f32x2 x = {x0, x1};
+    hi = __builtin_bit_cast(unsigned, __builtin_convertvector(x, bf16x2));
+    const f32x2 h = {__builtin_bit_cast(float, hi << 16),
+                     __builtin_bit_cast(float, hi & 0xffff0000u)};
+    lo = __builtin_bit_cast(unsigned, __builtin_convertvector(x - h, bf16x2));
+}
+
+
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+    const bf16x2 h = __builtin_convertvector(f32x2{x, 0.f}, bf16x2);
+    return (uint16_t)(__builtin_bit_cast(unsigned, h) & 0xffffu);
+}
+__device__ __forceinline__ float bf16_val(uint16_t b) {
+    return __builtin_bit_cast(float, (unsigned)b << 16);
+}
+// write x as the (hi, lo) pair of a split matrix (planes pl elements apart)
+__device__ __forceinline__ void put_split(uint16_t *C, long pl, long o, float x) {
+    const uint16_t h = bf16_bits(x);
+    C[o] = h;
+    C[o + pl] = bf16_bits(x - bf16_val(h));
+}
+__device__ __forceinline__ float get_split(const uint16_t *X, long pl, long o) {
+    return bf16_val(X[o]) + bf16_val(X[o + pl]);
+}
+
 template <typename T> struct MF;
 template <> struct MF<float> {
     using acc_t = f32x4;
@@ -65,6 +98,8 @@ template <typename T> struct GemmArgs {
     bool kscale_both = false;   // also scale row k of B_1 (else B_0 only)
     T *C = nullptr, *C2 = nullptr;
     float *Cf = nullptr;    // optional FP32 copy of C (FP64 products only)
+    uint16_t *Cs = nullptr; // optional split bf16 copy of C (planes Cs_pl apart)
+    long Cs_pl = 0;
     T alpha = 1, beta = 0, beta2 = 0, gamma = 0, p0 = 0, p1 = 0;
     long sA0 = 0, sB0 = 0, sA1 = 0, sB1 = 0, sX = 0, sX2 = 0, sC = 0, sC2 = 0, sK = 0;
     T *ws = nullptr;        // split-k partial tiles (nullptr: no split)
@@ -110,6 +145,7 @@ __device__ __forceinline__ void epilogue_block(const GemmArgs<T> &p, long bz, in
     const T *X = p.X ? p.X + bz * p.sX : nullptr;
     const T *X2 = p.X2 ? p.X2 + bz * p.sX2 : nullptr;
     float *Cf = p.Cf ? p.Cf + bz * p.sC : nullptr;
+    uint16_t *Cs = p.Cs;    // unbatched (expansion products)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int row = i0 + wr * 64 + x * 16 + M::out_row(fr, r);
@@ -125,6 +161,7 @@ __device__ __forceinline__ void epilogue_block(const GemmArgs<T> &p, long bz, in
             C[o] = val;
             if (C2) C2[o] = val2;
             if (Cf) Cf[o] = (float)val;
+            if (Cs) put_split(Cs, p.Cs_pl, o, (float)val);
         } else if (ti < tj || row <= col) {
             const long ot = (long)col * ld + row;
             C[o] = val;
@@ -136,6 +173,10 @@ __device__ __forceinline__ void epilogue_block(const GemmArgs<T> &p, long bz, in
             if (Cf) {
                 Cf[o] = (float)val;
                 Cf[ot] = (float)val;
+            }
+            if (Cs) {
+                put_split(Cs, p.Cs_pl, o, (float)val);
+                put_split(Cs, p.Cs_pl, ot, (float)val);
             }
         }
     }
@@ -308,21 +349,6 @@ __global__ __launch_bounds__(256, 2) void gemm_tn_kernel(GemmArgs<T> p, int ntil
 // 40 bf16 (80 bytes): the 16-byte fragment reads of 16 consecutive rows and
 // the 8-byte stores of a 16-lane group fall in distinct banks.
 // ---------------------------------------------------------------------------
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-
-// hi and lo bf16 pairs of two FP32 values (element 0 in the low half)
-__device__ __forceinline__ void split_pair(float x0, float x1, unsigned &hi, unsigned &lo) {
-    const f32x2 x = {x0, x1};
-    hi = __builtin_bit_cast(unsigned, __builtin_convertvector(x, bf16x2));
-    const f32x2 h = {__builtin_bit_cast(float, hi << 16),
-                     __builtin_bit_cast(float, hi & 0xffff0000u)};
-    lo = __builtin_bit_cast(unsigned, __builtin_convertvector(x - h, bf16x2));
-}
-
 constexpr int B3K = 32;          // k per tile = k of one bf16 MFMA
 constexpr int B3P = 20;          // LDS row pitch in 32-bit words (40 bf16)
 

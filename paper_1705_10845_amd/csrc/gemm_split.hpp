@@ -1,0 +1,259 @@
+// Split bf16x3 products on pre-split operands.
+//
+// Storage: an n x n "split matrix" is two bf16 planes, hi and lo, each row
+// major with leading dimension ld; plane lo starts `pl` elements after plane
+// hi (so a split matrix occupies the bytes of one FP32 matrix).  x = hi + lo
+// with hi = bf16(x), lo = bf16(x - hi) of the FP32 value.
+//
+// Product: C[i][j] = alpha sum_s sum_k A_s[i][k] B_s[j][k] + beta X[i][j],
+// i.e. both operands are read as rows with k contiguous ("NT").  Every
+// operand of the response recursion is symmetric, or is stored transposed
+// by the product that makes it, so this is the matrix product the recursion
+// needs.  C and X are split matrices too.
+//
+// Against gemm_bf3_kernel (FP32 operands split while staging) the k-tiles
+// here are copied into LDS as 16-byte chunks with no conversion work, the
+// workgroup has 8 waves (four per SIMD at two workgroups per CU), and
+// the chunk order within each 64-byte LDS row is permuted by a function of
+// the row (`swz`) so that both the chunk stores (4 lanes per row) and the
+// 16-byte fragment reads (16 consecutive rows, one chunk) hit distinct
+// banks for 8- and 16-lane service groups alike.
+#pragma once
+#include "gemm.hpp"
+
+namespace xl {
+
+struct SplitArgs {
+    int n = 0, ld = 0, batch = 1;
+    long pl = 0;                                  // plane offset (elements)
+    const uint16_t *A0 = nullptr, *B0 = nullptr, *A1 = nullptr, *B1 = nullptr;
+    const uint16_t *X = nullptr;
+    uint16_t *C = nullptr;
+    float alpha = 1.f, beta = 0.f;
+    long sA0 = 0, sB0 = 0, sA1 = 0, sB1 = 0, sX = 0, sC = 0;   // batch strides (elements)
+    float *ws = nullptr;                          // split-k partial tiles (FP32)
+    long ws_elems = 0;
+};
+
+// chunk permutation of LDS row r (values 0..3; a bijection on every 4 rows
+// of equal residue mod 4 and on the 4 rows of each parity in every 8)
+__device__ __forceinline__ int swz(int r) {
+    return ((r >> 2) & 1) | ((((r >> 1) ^ (r >> 3)) & 1) << 1);
+}
+
+// Write the 16 x 16 accumulator block whose first row / column within the
+// 128 x 128 tile are (r0, c0), from lane (fr, fc).
+template <bool SYM>
+__device__ __forceinline__ void epilogue_split_block(const SplitArgs &p, long bz, int ti,
+                                                     int tj, int r0, int c0, int fr, int fc,
+                                                     const f32x4 &acc) {
+    const int ld = p.ld;
+    uint16_t *C = p.C + bz * p.sC;
+    const uint16_t *X = p.X ? p.X + bz * p.sX : nullptr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = ti * GT + r0 + 4 * fr + r;
+        const int col = tj * GT + c0 + fc;
+        const long o = (long)row * ld + col;
+        float val = p.alpha * acc[r];
+        if (X) val += p.beta * get_split(X, p.pl, o);
+        if (!SYM) {
+            put_split(C, p.pl, o, val);
+        } else if (ti < tj || row <= col) {
+            put_split(C, p.pl, o, val);
+            put_split(C, p.pl, (long)col * ld + row, val);
+        }
+    }
+}
+
+// 512 threads = 8 waves in 2 (rows) x 4 (columns), 64 x 32 per wave
+// (4 x 2 accumulator blocks): two workgroups per CU put four waves on every
+// SIMD, which the bf16 matrix-core instruction needs to issue at full rate
+// (two waves per SIMD reach less than half of it).
+constexpr int BS_T = 512;
+
+template <bool SYM>
+__global__ __launch_bounds__(BS_T, 2) void gemm_bs_kernel(SplitArgs p, int ntiles, int nfull,
+                                                       int nsplit, int per_xcd) {
+    using acc_t = f32x4;
+    // [buffer][hi, lo][row][16-byte chunk]: 32 k per row
+    __shared__ __attribute__((aligned(16))) u32x4 As[2][2][GT][4];
+    __shared__ __attribute__((aligned(16))) u32x4 Bs[2][2][GT][4];
+
+    const int b = blockIdx.x;
+    const int ntail = ntiles - nfull;
+    const int nfull_pad = ((nfull + NXCD - 1) / NXCD) * NXCD;
+    int unit;
+    if (b < nfull_pad) {
+        unit = (b % NXCD) * (nfull_pad / NXCD) + b / NXCD;
+        if (unit >= nfull) return;
+    } else {
+        const int bb = b - nfull_pad;
+        unit = nfull + (bb % NXCD) * per_xcd + bb / NXCD;
+        if (unit >= nfull + ntail * nsplit) return;
+    }
+    const bool part = unit >= nfull;
+    const int w = unit - nfull;
+    const int u = part ? nfull + w / nsplit : unit;
+    const int split = part ? w % nsplit : 0;
+    const int ns = part ? nsplit : 1;
+    const int nt = p.n / GT;
+    int ti, tj;
+    tile_of<SYM>(u, nt, ti, tj);
+    const long bz = blockIdx.z;
+    const uint16_t *A0 = p.A0 + bz * p.sA0, *B0 = p.B0 + bz * p.sB0;
+    const uint16_t *A1 = p.A1 ? p.A1 + bz * p.sA1 : nullptr;
+    const uint16_t *B1 = p.B1 ? p.B1 + bz * p.sB1 : nullptr;
+    const int ld = p.ld;
+    const long pl = p.pl;
+    const int i0 = ti * GT, j0 = tj * GT;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wr = wid >> 2, wc = wid & 3;
+
+    acc_t acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = acc_t{0, 0, 0, 0};
+
+    const int nk1 = p.n / B3K;
+    const int nktot = A1 ? 2 * nk1 : nk1;
+    const int kt0 = (int)((long)nktot * split / ns);
+    const int kt1 = (int)((long)nktot * (split + 1) / ns);
+
+    // chunk v of thread tid: plane (idx >> 9), row ((idx >> 2) & 127),
+    // chunk (idx & 3) of the 128 x 32 k-tile, idx = tid + 512 v
+    u32x4 ra[2], rb[2];
+    auto gload = [&](int kt) {
+        const bool second = kt >= nk1;
+        const uint16_t *Ap = second ? A1 : A0;
+        const uint16_t *Bp = second ? B1 : B0;
+        const int kb = (second ? kt - nk1 : kt) * B3K;
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int idx = tid + BS_T * v;
+            const int pln = idx >> 9, row = (idx >> 2) & 127, ch = idx & 3;
+            const long off = pln * pl + kb + 8 * ch;
+            ra[v] = *reinterpret_cast<const u32x4 *>(Ap + off + (long)(i0 + row) * ld);
+            rb[v] = *reinterpret_cast<const u32x4 *>(Bp + off + (long)(j0 + row) * ld);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int idx = tid + BS_T * v;
+            const int pln = idx >> 9, row = (idx >> 2) & 127, ch = idx & 3;
+            As[buf][pln][row][ch ^ swz(row)] = ra[v];
+            Bs[buf][pln][row][ch ^ swz(row)] = rb[v];
+        }
+    };
+
+    gload(kt0);
+    sstore(0);
+    __syncthreads();
+    const int fr = lane >> 4, fc = lane & 15;
+    for (int kt = kt0; kt < kt1; ++kt) {
+        const int buf = (kt - kt0) & 1;
+        if (kt + 1 < kt1) gload(kt + 1);
+        // fragment of lane (fr, fc): row fc of the 16-row block, k 8 fr .. 8 fr + 7
+        bf16x8 ah[4], al[4], bh[2], bl[2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = wr * 64 + q * 16 + fc, c = fr ^ swz(r);
+            ah[q] = __builtin_bit_cast(bf16x8, As[buf][0][r][c]);
+            al[q] = __builtin_bit_cast(bf16x8, As[buf][1][r][c]);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int r = wc * 32 + q * 16 + fc, c = fr ^ swz(r);
+            bh[q] = __builtin_bit_cast(bf16x8, Bs[buf][0][r][c]);
+            bl[q] = __builtin_bit_cast(bf16x8, Bs[buf][1][r][c]);
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], bh[y], acc[x][y], 0, 0, 0);
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bl[y], acc[x][y], 0, 0, 0);
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
+            }
+        if (kt + 1 < kt1) sstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    if (part) {
+        // block g = 2x + y of thread tid at [(g * 512 + tid) * 4]
+        acc_t *wp = reinterpret_cast<acc_t *>(p.ws + ((long)bz * ntail * nsplit + w) * (GT * GT)) + tid;
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) wp[(x * 2 + y) * BS_T] = acc[x][y];
+        return;
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+            epilogue_split_block<SYM>(p, bz, ti, tj, wr * 64 + x * 16, wc * 32 + y * 16, fr, fc,
+                                      acc[x][y]);
+}
+
+// One workgroup per (tail tile, block g): thread tid sums the vectors its
+// counterpart wrote for block g in every partial.
+template <bool SYM>
+__global__ __launch_bounds__(BS_T) void gemm_bs_fixup_kernel(SplitArgs p, int ntiles, int nfull,
+                                                             int nsplit) {
+    const int ntail = ntiles - nfull;
+    const int u = nfull + blockIdx.x;
+    const int g = blockIdx.y, x = g >> 1, y = g & 1;
+    const long bz = blockIdx.z;
+    const int nt = p.n / GT;
+    int ti, tj;
+    tile_of<SYM>(u, nt, ti, tj);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wr = wid >> 2, wc = wid & 3, fr = lane >> 4, fc = lane & 15;
+    f32x4 acc = f32x4{0, 0, 0, 0};
+    const f32x4 *wp = reinterpret_cast<const f32x4 *>(
+                          p.ws + ((long)bz * ntail * nsplit + (long)blockIdx.x * nsplit) *
+                                     (GT * GT)) + g * BS_T + tid;
+    for (int s = 0; s < nsplit; ++s) acc += wp[(long)s * (GT * GT / 4)];
+    epilogue_split_block<SYM>(p, bz, ti, tj, wr * 64 + x * 16, wc * 32 + y * 16, fr, fc, acc);
+}
+
+inline long split_bs_ws_elems(int n, bool sym, int dual, long batch) {
+    return split_ws_elems<float>(n, sym, dual, batch);
+}
+
+inline void gemm_split(const SplitArgs &a, bool sym, hipStream_t st) {
+    if (a.n % GT != 0 || a.ld % 8 != 0 || a.pl % 8 != 0)
+        throw InvalidArg("gemm_split: n must be a multiple of 128");
+    const int nt = a.n / GT;
+    const int ntiles = sym ? nt * (nt + 1) / 2 : nt * nt;
+    const int nkt = (a.n / B3K) * (a.A1 ? 2 : 1);
+    Sched s = a.ws ? schedule<float>(ntiles, nkt, a.batch) : Sched{ntiles, 1};
+    if (s.nsplit > 1 && (long)(ntiles - s.nfull) * s.nsplit * a.batch * GT * GT > a.ws_elems)
+        s = Sched{ntiles, 1};
+    const int nfull_pad = ((s.nfull + NXCD - 1) / NXCD) * NXCD;
+    const int tail_units = (ntiles - s.nfull) * s.nsplit;
+    const int per = (tail_units + NXCD - 1) / NXCD;
+    dim3 grid(nfull_pad + per * NXCD, 1, a.batch);
+    if (sym)
+        hipLaunchKernelGGL((gemm_bs_kernel<true>), grid, dim3(BS_T), 0, st, a, ntiles, s.nfull,
+                           s.nsplit, per);
+    else
+        hipLaunchKernelGGL((gemm_bs_kernel<false>), grid, dim3(BS_T), 0, st, a, ntiles, s.nfull,
+                           s.nsplit, per);
+    XL_LAUNCH_CHECK();
+    if (s.nfull < ntiles) {
+        dim3 g2(ntiles - s.nfull, 8, a.batch);
+        if (sym)
+            hipLaunchKernelGGL((gemm_bs_fixup_kernel<true>), g2, dim3(BS_T), 0, st, a, ntiles,
+                               s.nfull, s.nsplit);
+        else
+            hipLaunchKernelGGL((gemm_bs_fixup_kernel<false>), g2, dim3(BS_T), 0, st, a, ntiles,
+                               s.nfull, s.nsplit);
+        XL_LAUNCH_CHECK();
+    }
+}
+
+}  // namespace xl

@@ -355,6 +355,60 @@ __global__ __launch_bounds__(256) void seed_resp_kernel(int n, int ld, const T *
     Zp[b * sG + o] = (T)val;
 }
 
+// Split-storage form of seed_resp_kernel: same inputs (FP32), Z'_0 written
+// as a split bf16 matrix (planes pl elements apart, batch stride 2 sG).
+__global__ __launch_bounds__(256) void seed_resp_split_kernel(int n, int ld, const float *G,
+                                                              const float *H2, const float *H13,
+                                                              const float *Y2, const float *Y4,
+                                                              const double *u, long su, long sG,
+                                                              uint16_t *Zp, long pl) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    const long b = blockIdx.z;
+    if (j >= ld) return;
+    const long o = (long)i * ld + j;
+    double val = 0.0;
+    if (i < n && j < n) {
+        const double ui = u[b * su + i], uj = u[b * su + j];
+        val = -(1.0 / 6.0) * ((double)G[b * sG + o] + (ui + uj) * (double)Y2[o]) +
+              (1.0 / 15.0) * ((double)H13[b * sG + o] + (double)H2[b * sG + o] +
+                              (ui + uj) * (double)Y4[o]);
+        if (i == j) val += 0.5 * ui;
+    }
+    put_split(Zp + b * 2 * sG, pl, o, (float)val);
+}
+
+// diag(Y T)_i = sum_l Y[i][l] T^T[i][l] for split Y and the stored transpose
+// T^T of T (batch stride sT): one block per (row, batch); the full row sum
+// goes to part[b * sP + i].
+__global__ __launch_bounds__(256) void coldot_split_kernel(int n, int ld, const uint16_t *Y,
+                                                           const uint16_t *Tt, long pl, long sT,
+                                                           double *part, long sP) {
+    __shared__ double sh[16];
+    const int i = blockIdx.x;
+    const long b = blockIdx.y;
+    const uint16_t *y = Y + (long)i * ld, *t = Tt + b * sT + (long)i * ld;
+    double s = 0.0;
+    for (int l = threadIdx.x; l < n; l += blockDim.x)
+        s += (double)get_split(y, pl, l) * (double)get_split(t, pl, l);
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) part[b * sP + i] = s;
+}
+
+// split bf16 matrix -> FP64 (hi + lo) over the whole array
+__global__ __launch_bounds__(256) void from_split_kernel(long n2, const uint16_t *in, long pl,
+                                                         double *out) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n2) out[t] = (double)get_split(in, pl, t);
+}
+
+// x (FP64) -> split bf16 matrix over the whole array (n2 elements)
+__global__ __launch_bounds__(256) void convert_split_kernel(long n2, const double *x, double scale,
+                                                            uint16_t *out, long pl) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n2) put_split(out, pl, t, (float)(scale * x[t]));
+}
+
 // Partial column sums of Y[l][i] * T[l][i] over row chunks of 64 rows:
 // part[b][chunk][i].  diag(Y T)_i = sum_l Y[i][l] T[l][i] with Y symmetric.
 template <typename T>

@@ -29,6 +29,7 @@
 #include "../../include/xlbomd.h"
 #include "common.hpp"
 #include "gemm.hpp"
+#include "gemm_split.hpp"
 #include "model.hpp"
 #include "chol.hpp"
 
@@ -609,7 +610,26 @@ template <typename TF, typename TR> struct Sys : SysBase {
         TR *zp = dalloc<TR>(mat() * nb), *ap = dalloc<TR>(mat() * nb), *tb = dalloc<TR>(mat() * nb);
         mem.ptrs.push_back(zp); mem.ptrs.push_back(ap); mem.ptrs.push_back(tb);
         Zp = zp; Ap = ap; Tb = tb;
+        if (resp_split) {
+            Xb = dalloc<TR>(mat() * nb);
+            mem.ptrs.push_back(Xb);
+        }
         bcap = nb;
+    }
+    TR *Xb = nullptr;                 // fourth response buffer (split path)
+    // split bf16 view of a TR matrix buffer (planes mat() elements apart)
+    uint16_t *s16(TR *p) const { return reinterpret_cast<uint16_t *>(p); }
+    // response operand copy written by an expansion product: split planes
+    // for the split path, FP32 otherwise
+    template <typename G> void copy_out(G &g, TR *dst) {
+        if constexpr (FUSE_COPY) {
+            if (resp_split) {
+                g.Cs = s16(dst);
+                g.Cs_pl = (long)mat();
+            } else {
+                g.Cf = dst;
+            }
+        }
     }
 
     // split-k workspace per precision (allocated on first use)
@@ -684,7 +704,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
             a.A0 = Y3; a.B0 = Y2; a.alpha = (TF)(1.0 / 15.0);
             a.X = Y3; a.beta = (TF)(-1.0 / 6.0); a.X2 = Ys; a.beta2 = (TF)0.5;
             a.C = Z[0];
-            if constexpr (FUSE_COPY) a.Cf = Zr[0];
+            copy_out(a, Zr[0]);
             run_gemm(a, true);
         }
         // Newton-Schulz target per level: far below the truncation bound
@@ -722,7 +742,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
                 q.alpha = (TF)(-4.0 * al * al * al / D3);
                 q.X = Am; q.beta = (TF)(-12.0 * al * al * be / D3);
                 q.gamma = (TF)(-(12.0 * al * be * be - 3.0 * al) / D3);
-                if constexpr (FUSE_COPY) if (ns == 0) q.Cf = Yr[k];
+                if (ns == 0) copy_out(q, Yr[k]);
                 run_gemm(q, true);
             }
             for (int j = 0; j < ns; ++j) {
@@ -731,14 +751,25 @@ template <typename TF, typename TR> struct Sys : SysBase {
                 run_gemm(e1, true);
                 auto e2 = base<TF>();   // Y <- Y E
                 e2.A0 = Yk[k]; e2.B0 = E; e2.C = Wk;
-                if constexpr (FUSE_COPY) if (j + 1 == ns) e2.Cf = Yr[k];
+                if (j + 1 == ns) copy_out(e2, Yr[k]);
                 run_gemm(e2, true);
                 std::swap(Yk[k], Wk);
             }
-            if constexpr (FUSE_COPY) if (ns == 0 && !quad) convert(Yk[k], Yr[k], 1.0);
+            if constexpr (FUSE_COPY) {
+                if (ns == 0 && !quad) {
+                    if (resp_split) {
+                        hipLaunchKernelGGL(convert_split_kernel, dim3(ceil_div((long)mat(), 256)),
+                                           dim3(256), 0, st, (long)mat(), (const double *)Yk[k],
+                                           1.0, s16(Yr[k]), (long)mat());
+                        XL_LAUNCH_CHECK();
+                    } else {
+                        convert(Yk[k], Yr[k], 1.0);
+                    }
+                }
+            }
             auto z = base<TF>();        // Z_{k+1} = 2 Y_k Z_k
             z.A0 = Yk[k]; z.B0 = Z[k]; z.alpha = (TF)2.0; z.C = Z[k + 1];
-            if constexpr (FUSE_COPY) z.Cf = Zr[k + 1];
+            copy_out(z, Zr[k + 1]);
             run_gemm(z, true);
             t = 2.0 * t / (1.0 + t * t);
         }
@@ -808,10 +839,82 @@ template <typename TF, typename TR> struct Sys : SysBase {
     }
     long expansion_id = 0, Y4_for = -1;    // expansion counter, Y^4 made for
 
+    template <typename U> void run_split(SplitArgs a, bool sym) {
+        GemmArgs<float> w;
+        attach_ws(w);
+        a.ws = w.ws;
+        a.ws_elems = w.ws_elems;
+        prof_begin();
+        gemm_split(a, sym, st);
+        prof_end(gemm_flops(sym, a.A1 ? 2 : 1) * a.batch, 2);
+    }
+
+    // Responses with the recursion's operands in split bf16 storage: the
+    // seed's row-scaled products on FP32 operands, then per level
+    // A' = 4 (Z Z' + Z' Z), T^T = 2 Z' - Z_{k+1} A' (T stored transposed),
+    // Z'_{k+1} = Y_k T, all on pre-split operands; last level diag(Y T).
+    void responses_split(int nb, const double *v, double *qout, double *wout) {
+        const long sm = (long)mat();
+        hipLaunchKernelGGL(gamma_matvec_kernel, dim3(ceil_div((long)nat * nb * 64, 256)),
+                           dim3(256), 0, st, md, nb, v, hb);
+        XL_LAUNCH_CHECK();
+        hipLaunchKernelGGL(expand_orbital_kernel, dim3(ceil_div((long)N * nb, 256)), dim3(256), 0,
+                           st, nat, no, nb, sc, hb, (long)Np, ub);
+        XL_LAUNCH_CHECK();
+        {   // G = Y D Y, H2 = Y2 D Y2, H13 = Y D Y3 + Y3 D Y (FP32 storage), then Z'_0
+            auto a = base<TR>();
+            a.batch = nb; a.A0 = Ysr; a.B0 = Ysr; a.kscale = ub; a.sK = Np;
+            a.split3 = true;
+            a.C = Tb; a.sC = sm;
+            run_gemm(a, true);
+            a.A0 = Y2r; a.B0 = Y2r; a.C = Ap;
+            run_gemm(a, true);
+            a.A0 = Ysr; a.B0 = Y3r; a.A1 = Y3r; a.B1 = Ysr; a.kscale_both = true; a.C = Xb;
+            run_gemm(a, true);
+            hipLaunchKernelGGL(seed_resp_split_kernel, dim3(ceil_div(Np, 256), Np, nb), dim3(256),
+                               0, st, N, Np, (const float *)Tb, (const float *)Ap,
+                               (const float *)Xb, (const float *)Y2r, (const float *)Y4r, ub,
+                               (long)Np, sm, s16(Zp), sm);
+            XL_LAUNCH_CHECK();
+        }
+        const long s2 = 2 * sm;            // batch stride of split buffers
+        for (int k = 0; k < L; ++k) {
+            SplitArgs a;                    // A' = 4 (Z Z' + Z' Z)
+            a.n = Np; a.ld = Np; a.pl = sm; a.batch = nb;
+            a.A0 = s16(Zr[k]); a.B0 = s16(Zp); a.sB0 = s2; a.A1 = s16(Zp); a.sA1 = s2;
+            a.B1 = s16(Zr[k]); a.alpha = 4.f; a.C = s16(Ap); a.sC = s2;
+            run_split<float>(a, true);
+            SplitArgs b;                    // T^T = 2 Z' - Z_{k+1} A'
+            b.n = Np; b.ld = Np; b.pl = sm; b.batch = nb;
+            b.A0 = s16(Zr[k + 1]); b.B0 = s16(Ap); b.sB0 = s2; b.alpha = -1.f;
+            b.X = s16(Zp); b.sX = s2; b.beta = 2.f; b.C = s16(Tb); b.sC = s2;
+            run_split<float>(b, false);
+            if (k + 1 < L) {
+                SplitArgs c;                // Z'_{k+1} = Y_k T
+                c.n = Np; c.ld = Np; c.pl = sm; c.batch = nb;
+                c.A0 = s16(Yr[k]); c.B0 = s16(Tb); c.sB0 = s2; c.C = s16(Zp); c.sC = s2;
+                run_split<float>(c, true);
+            }
+        }
+        hipLaunchKernelGGL(coldot_split_kernel, dim3(N, nb), dim3(256), 0, st, N, Np,
+                           (const uint16_t *)s16(Yr[L - 1]), (const uint16_t *)s16(Tb), sm, s2,
+                           part, (long)N);
+        XL_LAUNCH_CHECK();
+        hipLaunchKernelGGL(resp_charges_kernel, dim3(nb), dim3(1024), 0, st, nat, no, 1, part,
+                           (long)N, g, v, qout, wout);
+        XL_LAUNCH_CHECK();
+    }
+
     void responses(int nb, const double *v, double *qout, double *wout) override {
         if (nb <= 0) return;
         alloc_resp(nb);
         response_operands();
+        if constexpr (FUSE_COPY) {
+            if (resp_split) {
+                responses_split(nb, v, qout, wout);
+                return;
+            }
+        }
         const long sm = (long)mat();
         // h = Gamma v, u = sc * h per orbital
         hipLaunchKernelGGL(gamma_matvec_kernel, dim3(ceil_div((long)nat * nb * 64, 256)),
@@ -1368,6 +1471,48 @@ int xlbomd_selftest_gemm_time(int32_t n, int32_t precision, int32_t sym, int32_t
             *ms_per_launch = ms / reps;
         };
         if (precision == XLBOMD_FP64) go(double{}); else go(float{});
+    });
+}
+
+int xlbomd_selftest_gemm_presplit(int32_t n, int32_t sym, int32_t reps, const double *A,
+                                  const double *B, double *C, double *ms_per_launch) {
+    if (n <= 0 || n % 128 || reps < 0 || !A || !B || !C || (reps > 0 && !ms_per_launch))
+        return fail(XLBOMD_E_INVALID, "bad self-test args");
+    return guarded([&] {
+        const size_t nn = (size_t)n * n;
+        double *dA = dalloc<double>(nn), *dB = dalloc<double>(nn), *dC = dalloc<double>(nn);
+        uint16_t *a = dalloc<uint16_t>(2 * nn), *b = dalloc<uint16_t>(2 * nn),
+                 *c = dalloc<uint16_t>(2 * nn);
+        SplitArgs ga;
+        ga.n = n; ga.ld = n; ga.pl = (long)nn; ga.A0 = a; ga.B0 = b; ga.C = c;
+        ga.ws_elems = split_bs_ws_elems(n, sym != 0, 0, 1);
+        float *ws = dalloc<float>(ga.ws_elems);
+        ga.ws = ws;
+        DevFree fr;
+        fr.ptrs = {dA, dB, dC, a, b, c, ws};
+        XL_HIP(hipMemcpy(dA, A, nn * 8, hipMemcpyHostToDevice));
+        XL_HIP(hipMemcpy(dB, B, nn * 8, hipMemcpyHostToDevice));
+        const int g = ceil_div((long)nn, 256);
+        hipLaunchKernelGGL(convert_split_kernel, dim3(g), dim3(256), 0, 0, (long)nn, dA, 1.0, a, (long)nn);
+        hipLaunchKernelGGL(convert_split_kernel, dim3(g), dim3(256), 0, 0, (long)nn, dB, 1.0, b, (long)nn);
+        gemm_split(ga, sym != 0, 0);
+        hipLaunchKernelGGL(from_split_kernel, dim3(g), dim3(256), 0, 0, (long)nn, c, (long)nn, dC);
+        XL_HIP(hipDeviceSynchronize());
+        XL_HIP(hipMemcpy(C, dC, nn * 8, hipMemcpyDeviceToHost));
+        if (reps > 0) {
+            hipEvent_t e0, e1;
+            XL_HIP(hipEventCreate(&e0));
+            XL_HIP(hipEventCreate(&e1));
+            XL_HIP(hipEventRecord(e0, 0));
+            for (int r = 0; r < reps; ++r) gemm_split(ga, sym != 0, 0);
+            XL_HIP(hipEventRecord(e1, 0));
+            XL_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            XL_HIP(hipEventElapsedTime(&ms, e0, e1));
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            *ms_per_launch = ms / reps;
+        }
     });
 }
 

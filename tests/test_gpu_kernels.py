@@ -96,3 +96,27 @@ def test_split_gemm_dual_kscale_batch(B):
     print(f"response rel err: FP32 products {e32:.2e}, split bf16x3 products {e3:.2e}")
     assert e3 < 1e-3
     assert np.abs(out[P.MIXED_BF16X3].sum(axis=1)).max() < 1e-9
+
+
+@pytest.mark.parametrize("n", [128, 256, 384, 1024])
+@pytest.mark.parametrize("sym", [False, True])
+def test_gemm_presplit(B, n, sym):
+    """Split product on pre-split operands: C = A B^T from the bf16 hi/lo
+    planes of the FP32 roundings of A and B, stored split itself."""
+    rng = np.random.default_rng(3 * n + int(sym))
+    A = rng.standard_normal((n, n)); A = 0.5 * (A + A.T)
+    Bm = A @ A + 0.3 * A if sym else rng.standard_normal((n, n))
+    ah, al = split_bf16x3(A)
+    bh, bl = split_bf16x3(Bm)
+    ref = ah @ bh.T + ah @ bl.T + al @ bh.T
+    scale = np.abs(A).max() * np.abs(Bm).max()
+    C = B.selftest_gemm_presplit(A, Bm, sym=sym)
+    # FP32 accumulation, then the output's own hi + lo rounding (2^-17 relative)
+    tol = 2e-6 * np.sqrt(n) * scale + 2.0 ** -15 * np.abs(ref).max()
+    err = np.abs(C - ref).max()
+    exact = np.abs(C - A @ Bm.T).max()
+    print(f"presplit n={n} sym={sym}: vs emulation {err:.2e} (tol {tol:.1e}), vs exact {exact:.2e}")
+    assert err < tol
+    assert exact < 3e-5 * np.sqrt(n) * scale
+    if sym:
+        assert np.array_equal(C, C.T)
