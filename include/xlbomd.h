@@ -187,6 +187,24 @@ int xlbomd_response(xlbomd_system *h, int32_t count, const double *v,
 int xlbomd_kernel_apply(xlbomd_system *h, int32_t rank, const double *r,
                         double *kr_out);
 
+/* Ground state by the kernel SCF of Eq. 52 (Section V.F, Section VI), at
+ * the handle's current nuclear positions and independent of its MD state:
+ * starting from n0 (n_atoms host array; NULL = zeros) iterate
+ *   n <- n - K_m (q[n] - n)
+ * with a fresh rank-m kernel per iteration, built from sequential Krylov
+ * directions and canonical responses (rank 0: K0 = -gamma I alone, i.e.
+ * linear mixing), until RMS(q[n] - n) <= tol or max_iter kernel updates.
+ * rank <= min(kernel_rank, 16) of the descriptor; gamma in (0, 1] replaces
+ * the handle's K0 constant for this call (0 keeps it).
+ * Outputs (each nullable except n_eval): n_out (n_atoms) the last n;
+ * rms_hist (max_iter + 1 entries) the RMS residual of every evaluated n;
+ * *n_eval the number of evaluations.  XLBOMD_E_NOCONV if tol was not
+ * reached (the outputs are still written).  The MD history and K r are not
+ * touched; the handle's electronic state (charges, density) is left at the
+ * last evaluated n. */
+int xlbomd_scf(xlbomd_system *h, const double *n0, int32_t rank, double gamma, double tol,
+               int32_t max_iter, double *n_out, double *rms_hist, int32_t *n_eval);
+
 /* Live timing of the dense MFMA products.  enable != 0 starts recording a
  * HIP event pair on the handle's stream around every product launched by
  * later calls; enable == 0 stops and, if out != NULL, writes 15 doubles:

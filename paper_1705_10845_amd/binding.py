@@ -80,6 +80,8 @@ def lib():
         L.xlbomd_solve.argtypes = [vp, _dp, _dp, ctypes.POINTER(Report)]
         L.xlbomd_response.argtypes = [vp, ctypes.c_int32, _dp, _dp]
         L.xlbomd_kernel_apply.argtypes = [vp, ctypes.c_int32, _dp, _dp]
+        L.xlbomd_scf.argtypes = [vp, _dp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_int32, _dp, _dp, ctypes.POINTER(ctypes.c_int32)]
         L.xlbomd_profile.argtypes = [vp, ctypes.c_int32, _dp]
         L.xlbomd_selftest_gemm.argtypes = [ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_int32, _dp, _dp, _dp]
@@ -97,7 +99,7 @@ EXPORTED = ("xlbomd_init_system", "xlbomd_step", "xlbomd_step_batch",
             "xlbomd_kernel_update",
             "xlbomd_forces", "xlbomd_get_charges", "xlbomd_set_state",
             "xlbomd_get_state", "xlbomd_solve", "xlbomd_response",
-            "xlbomd_kernel_apply", "xlbomd_profile", "xlbomd_selftest_gemm",
+            "xlbomd_kernel_apply", "xlbomd_scf", "xlbomd_profile", "xlbomd_selftest_gemm",
             "xlbomd_selftest_gemm_time", "xlbomd_selftest_gemm_presplit",
             "xlbomd_destroy", "xlbomd_last_error",
             "xlbomd_version")
@@ -263,6 +265,19 @@ class XLBOMD:
             res[key] = dict(ms=o[0], flops=o[1], launches=int(o[2]),
                             min_ms=o[3], max_ms=o[4])
         return res
+
+    def scf(self, n0=None, rank=1, gamma=0.0, tol=1e-10, max_iter=100):
+        """Kernel SCF (Eq. 52) at the current positions.  Returns
+        (n, rms history, converged)."""
+        n0 = None if n0 is None else _c(n0, (self.nat,))
+        n = np.zeros(self.nat)
+        hist = np.zeros(max_iter + 1)
+        ne = ctypes.c_int32(0)
+        rc = lib().xlbomd_scf(self._h, _ptr(n0), rank, gamma, tol, max_iter, _ptr(n),
+                              _ptr(hist), ctypes.byref(ne))
+        if rc not in (0, -3):
+            _check(rc)
+        return n, hist[:ne.value].copy(), rc == 0
 
     def kernel_apply(self, rank, r):
         r = _c(r, (self.nat,))

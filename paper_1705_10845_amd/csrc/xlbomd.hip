@@ -563,6 +563,40 @@ struct SysBase {
         step_no = 0;
         sync();
     }
+
+    // Kernel SCF (Eq. 52) at the current positions from n0 (device copy in
+    // ncur): n <- n - K_m (q[n] - n) with a fresh rank-m kernel (sequential
+    // directions) per iteration; rank 0 is K0 alone (linear mixing).  The
+    // MD history and K r are left as they are.  Returns true if RMS(r) <= tol.
+    bool scf_run(int rank, double gamma, double tol, int max_iter, double *rms_hist,
+                 int *n_eval) {
+        const double g_saved = d.k0_gamma;
+        if (gamma > 0.0) d.k0_gamma = gamma;
+        bool have = false, ok = false;
+        int it = 0;
+        try {
+            for (;; ++it) {
+                solve(ncur, mu, have);
+                have = true;
+                if (rms_hist) rms_hist[it] = rms;
+                if (rms <= tol) { ok = true; break; }
+                if (it >= max_iter || !std::isfinite(rms)) break;
+                rank_prev = 0;
+                build_kernel(rank, 0, false, false);
+                apply_kernel(r, vtmp);
+                hipLaunchKernelGGL(axpy_kernel, dim3(ceil_div(nat, 256)), dim3(256), 0, st, nat,
+                                   -1.0, vtmp, ncur);
+                XL_LAUNCH_CHECK();
+            }
+        } catch (...) {
+            d.k0_gamma = g_saved;
+            throw;
+        }
+        d.k0_gamma = g_saved;
+        *n_eval = it + 1;
+        sync();
+        return ok;
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -1365,6 +1399,30 @@ int xlbomd_kernel_apply(xlbomd_system *h, int32_t rank, const double *rr, double
         XL_HIP(hipMemcpyAsync(kr_out, s.vtmp, s.nat * sizeof(double), hipMemcpyDeviceToHost, s.st));
         s.sync();
     });
+}
+
+int xlbomd_scf(xlbomd_system *h, const double *n0, int32_t rank, double gamma, double tol,
+               int32_t max_iter, double *n_out, double *rms_hist, int32_t *n_eval) {
+    if (!h || !h->s || !n_eval) return fail(XLBOMD_E_INVALID, "null argument");
+    if (max_iter < 0 || !(tol > 0.0) || !(gamma >= 0.0 && gamma <= 1.0))
+        return fail(XLBOMD_E_INVALID, "scf: max_iter >= 0, tol > 0, gamma in [0, 1]");
+    bool ok = false;
+    const int rc = guarded([&] {
+        SysBase &s = *h->s;
+        if (rank < 0 || rank > s.mcap) throw InvalidArg("scf: rank above the kernel capacity");
+        if (n0)
+            XL_HIP(hipMemcpyAsync(s.ncur, n0, s.nat * sizeof(double), hipMemcpyHostToDevice, s.st));
+        else
+            XL_HIP(hipMemsetAsync(s.ncur, 0, s.nat * sizeof(double), s.st));
+        int ne = 0;
+        ok = s.scf_run(rank, gamma, tol, max_iter, rms_hist, &ne);
+        *n_eval = ne;
+        if (n_out)
+            XL_HIP(hipMemcpyAsync(n_out, s.ncur, s.nat * sizeof(double), hipMemcpyDeviceToHost, s.st));
+        s.sync();
+    });
+    if (rc == XLBOMD_OK && !ok) return fail(XLBOMD_E_NOCONV, "scf: tolerance not reached");
+    return rc;
 }
 
 int xlbomd_profile(xlbomd_system *h, int32_t enable, double *out) {

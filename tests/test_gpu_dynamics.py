@@ -138,3 +138,12 @@ def test_mixed_split_one_step(P):
     print(f"MIXED_BF16X3 one step: dn {dn:.2e} dq {dq:.2e} dF {dF:.2e} "
           f"rel dOmega {dO:.2e} rel dKr {dkr:.2e}")
     assert dq < 1e-8 and dn < 1e-10 and dF < 1e-5 and dO < 1e-8 and dkr < 1e-3
+
+
+@pytest.mark.parametrize("kmax", [6, 7])
+def test_table_I_rows_trajectory(P, kmax):
+    """Table I rows K_max = 6 and 7 (kappa, alpha, c_k) against the oracle."""
+    s = make_system("c1", kmax=kmax)
+    w = _traj(P, s, 40, P.FP64)
+    print(f"K_max {kmax}, 40 steps:", {k: f"{v:.2e}" for k, v in w.items()})
+    assert w["dq"] < 1e-8 and w["dF"] < 1e-5 and w["dn"] < 1e-8
