@@ -94,7 +94,11 @@ typedef struct {
     int32_t kmax;                 /* 5, 6 or 7: Table I row                 */
     int32_t kernel_rank;          /* m >= 0 (0 = K0 only), m <= n_atoms     */
     int32_t kernel_every;         /* rebuild the kernel every k steps (>=1) */
-    int32_t krylov_mode;          /* 0 sequential Krylov, 1 block           */
+    int32_t krylov_mode;          /* 0 sequential Krylov, 1 block, 2 full
+                                     kernel (J - I)^-1 from n_atoms responses
+                                     in batches of min(kernel_rank, 16),
+                                     rebuilt every kernel_every steps; the
+                                     initial SCF still uses rank kernel_rank */
     double k0_gamma;              /* K0 = -k0_gamma I, in (0, 1]; 0 = choose
                                      at init from the stiffest response mode:
                                      20 power iterations v <- -Jv/|Jv| from
@@ -183,7 +187,8 @@ int xlbomd_response(xlbomd_system *h, int32_t count, const double *v,
                     double *dq_out);
 
 /* Apply the rank-m kernel built at the last xlbomd_solve to r (n_atoms):
- * kr_out = K_m r (Eq. 50 in closed Woodbury form). */
+ * kr_out = K_m r (Eq. 50 in closed Woodbury form); rank = -1 applies the
+ * full kernel (J - I)^-1 of Eq. 43 (krylov_mode 2 construction). */
 int xlbomd_kernel_apply(xlbomd_system *h, int32_t rank, const double *r,
                         double *kr_out);
 

@@ -264,6 +264,13 @@ def jacobian(model, el):
     return J
 
 
+def kernel_full(model, el):
+    """The exact kernel K = (J - I)^{-1} of Eq. 43 (krylov_mode 2: all
+    N_at responses, dense inverse)."""
+    J = jacobian(model, el)
+    return np.linalg.inv(J - np.eye(model.nat))
+
+
 R_FLOOR = 1e-8     # RMS residual below which the kernel is K0
 
 
@@ -405,9 +412,13 @@ def init_state(model, pos=None, vel=None, scf_tol=1e-10, gamma=None,
         model.gamma_used = gamma
     el, _ = scf(model, pos, gamma, rank, tol=scf_tol)
     hist = np.tile(el.n, (s.kmax + 1, 1))            # Eq. 20: ndot(t0) = 0
-    kres = kernel_sm(model, el, gamma, rank, mode=s.krylov_mode)
+    if s.krylov_mode == 2:
+        K, V = kernel_full(model, el), None
+    else:
+        kres = kernel_sm(model, el, gamma, rank, mode=s.krylov_mode)
+        K, V = kres.K, kres.V
     st = State(pos=pos, vel=vel, force=forces(model, pos, el), n_hist=hist,
-               kr=kres.K @ el.r, K=kres.K, V=kres.V, el=el)
+               kr=K @ el.r, K=K, V=V, el=el)
     st.energy = energy_report(model, st)
     return st
 
@@ -439,7 +450,9 @@ def md_step(model, st, gamma=None, rank=None, want_energy=True):
     el = electronic(model, pos, n_new)
     F = forces(model, pos, el)
     step = st.step + 1
-    if step % s.kernel_every == 0 or st.K is None:
+    if (step % s.kernel_every == 0 or st.K is None) and s.krylov_mode == 2:
+        K, V = kernel_full(model, el), None
+    elif step % s.kernel_every == 0 or st.K is None:
         kres = kernel_sm(model, el, gamma, rank, mode=s.krylov_mode,
                          v_prev=st.V)
         K, V = kres.K, kres.V

@@ -409,6 +409,95 @@ __global__ __launch_bounds__(256) void convert_split_kernel(long n2, const doubl
     if (t < n2) put_split(out, pl, t, (float)(scale * x[t]));
 }
 
+// ---- full kernel K = (J - I)^-1 (krylov_mode 2) ----
+// dirs[b][j] = (j == i0 + b): unit charge directions for one response batch
+__global__ __launch_bounds__(256) void unit_dirs_kernel(int nat, int i0, int nb, double *dirs) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)nb * nat) return;
+    const int b = (int)(t / nat), j = (int)(t % nat);
+    dirs[t] = (j == i0 + b) ? 1.0 : 0.0;
+}
+
+// Rows i0 .. i0 + nb of the augmented array [J^T - I | I] (n x 2n) from the
+// responses q[b] = J e_{i0+b} (row i of J^T = column i of J).
+__global__ __launch_bounds__(256) void gj_rows_kernel(int n, int i0, int nb, const double *q,
+                                                      double *A) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)nb * 2 * n) return;
+    const int b = (int)(t / (2 * n)), c = (int)(t % (2 * n));
+    const int i = i0 + b;
+    double v;
+    if (c < n) v = q[(long)b * n + c] - (c == i ? 1.0 : 0.0);
+    else v = (c - n == i) ? 1.0 : 0.0;
+    A[(long)i * 2 * n + c] = v;
+}
+
+// Gauss-Jordan column k on [M | I] (one block): partial pivot (largest
+// |A[i][k]|, i >= k), row swap, row k scaled to a unit pivot, and the
+// elimination factors f[i] = A[i][k] (f[k] = 0) for gj_update_kernel.
+// flag[0] is set when the pivot is zero.
+__global__ __launch_bounds__(1024) void gj_pivot_kernel(int n, int k, double *A, double *f,
+                                                        int *flag) {
+    __shared__ double bv[1024];
+    __shared__ int bi[1024];
+    const int tid = threadIdx.x;
+    const long w = 2L * n;
+    double best = -1.0;
+    int arg = k;
+    for (int i = k + tid; i < n; i += blockDim.x) {
+        const double a = fabs(A[(long)i * w + k]);
+        if (a > best) { best = a; arg = i; }
+    }
+    bv[tid] = best;
+    bi[tid] = arg;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s && (bv[tid + s] > bv[tid] || (bv[tid + s] == bv[tid] && bi[tid + s] < bi[tid]))) {
+            bv[tid] = bv[tid + s];
+            bi[tid] = bi[tid + s];
+        }
+        __syncthreads();
+    }
+    const int p = bi[0];
+    if (p != k)
+        for (long c = tid; c < w; c += blockDim.x) {
+            const double t = A[(long)k * w + c];
+            A[(long)k * w + c] = A[(long)p * w + c];
+            A[(long)p * w + c] = t;
+        }
+    __syncthreads();
+    const double piv = A[(long)k * w + k];
+    if (piv == 0.0) {
+        if (tid == 0) flag[0] = 1;
+        return;
+    }
+    __syncthreads();
+    for (long c = tid; c < w; c += blockDim.x) A[(long)k * w + c] /= piv;
+    for (int i = tid; i < n; i += blockDim.x) f[i] = (i == k) ? 0.0 : A[(long)i * w + k];
+}
+
+// A[i][c] -= f[i] A[k][c] for every row i != k (f[k] = 0 leaves row k).
+__global__ __launch_bounds__(256) void gj_update_kernel(int n, int k, double *A, const double *f) {
+    const long w = 2L * n;
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (c >= w) return;
+    const double fi = f[i];
+    if (fi != 0.0) A[(long)i * w + c] -= fi * A[(long)k * w + c];
+}
+
+// out = K r with K = (J - I)^-1 = (M^-1)^T, M^-1 the right half of the
+// reduced augmented array: out_i = sum_j M^-1[j][i] r_j.
+__global__ __launch_bounds__(256) void full_apply_kernel(int n, const double *A, const double *r,
+                                                         double *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long w = 2L * n;
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += A[(long)j * w + n + i] * r[j];
+    out[i] = s;
+}
+
 // Partial column sums of Y[l][i] * T[l][i] over row chunks of 64 rows:
 // part[b][chunk][i].  diag(Y T)_i = sum_l Y[i][l] T[l][i] with Y symmetric.
 template <typename T>

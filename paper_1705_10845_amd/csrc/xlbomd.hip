@@ -456,6 +456,55 @@ struct SysBase {
     }
 
     // ---- one XL-BOMD step (Eqs. 22-23) ----
+    // ---- full kernel K = (J - I)^-1 (krylov_mode 2, Eq. 43) ----
+    // J from N_at canonical responses to unit charge vectors, in batches of
+    // mcap directions; [J^T - I | I] reduced by Gauss-Jordan with partial
+    // pivoting in FP64; K r is then a dense product until the next rebuild.
+    double *gj = nullptr, *gjf = nullptr, *dirs = nullptr, *qdir = nullptr;
+    int *gjflag = nullptr;
+    bool full_built = false;
+    void build_full_kernel() {
+        if (!gj) {
+            gj = dalloc<double>((size_t)2 * nat * nat);
+            gjf = dalloc<double>(nat);
+            dirs = dalloc<double>((size_t)mcap * nat);
+            qdir = dalloc<double>((size_t)mcap * nat);
+            gjflag = dalloc<int>(1);
+            mem.ptrs.push_back(gj); mem.ptrs.push_back(gjf); mem.ptrs.push_back(dirs);
+            mem.ptrs.push_back(qdir); mem.ptrs.push_back(gjflag);
+        }
+        for (int i0 = 0; i0 < nat; i0 += mcap) {
+            const int nb = std::min(mcap, nat - i0);
+            hipLaunchKernelGGL(unit_dirs_kernel, dim3(ceil_div((long)nb * nat, 256)), dim3(256), 0,
+                               st, nat, i0, nb, dirs);
+            XL_LAUNCH_CHECK();
+            responses(nb, dirs, qdir, nullptr);
+            hipLaunchKernelGGL(gj_rows_kernel, dim3(ceil_div((long)nb * 2 * nat, 256)), dim3(256),
+                               0, st, nat, i0, nb, qdir, gj);
+            XL_LAUNCH_CHECK();
+        }
+        XL_HIP(hipMemsetAsync(gjflag, 0, sizeof(int), st));
+        for (int k = 0; k < nat; ++k) {
+            hipLaunchKernelGGL(gj_pivot_kernel, dim3(1), dim3(1024), 0, st, nat, k, gj, gjf, gjflag);
+            XL_LAUNCH_CHECK();
+            hipLaunchKernelGGL(gj_update_kernel, dim3(ceil_div(2L * nat, 256), nat), dim3(256), 0,
+                               st, nat, k, gj, gjf);
+            XL_LAUNCH_CHECK();
+        }
+        int flag = 0;
+        XL_HIP(hipMemcpyAsync(&flag, gjflag, sizeof(int), hipMemcpyDeviceToHost, st));
+        sync();
+        if (flag) throw Diverged("full kernel: J - I is singular");
+        full_built = true;
+        rank_built = nat;
+    }
+    void apply_full(const double *rin, double *out) {
+        hipLaunchKernelGGL(full_apply_kernel, dim3(ceil_div(nat, 256)), dim3(256), 0, st, nat, gj,
+                           rin, out);
+        XL_LAUNCH_CHECK();
+    }
+    bool full_mode() const { return d.krylov_mode == 2; }
+
     void md_step(bool want_energy, xlbomd_report *rep) {
         const double dt = d.dt;
         const int nthr3 = ceil_div(3 * nat, 256);
@@ -473,9 +522,14 @@ struct SysBase {
         push_mu();
         forces_parts();
         ++step_no;
-        if (step_no % std::max(1, d.kernel_every) == 0)
-            build_kernel(d.kernel_rank, d.krylov_mode, true);
-        apply_kernel(r, kr);
+        if (full_mode()) {
+            if (step_no % std::max(1, d.kernel_every) == 0 || !full_built) build_full_kernel();
+            apply_full(r, kr);
+        } else {
+            if (step_no % std::max(1, d.kernel_every) == 0)
+                build_kernel(d.kernel_rank, d.krylov_mode, true);
+            apply_kernel(r, kr);
+        }
         hipLaunchKernelGGL(kick_drift_kernel, dim3(nthr3), dim3(256), 0, st, nat, 0.5 * dt, 0.0,
                            force, mass, vel, (double *)nullptr);
         XL_LAUNCH_CHECK();
@@ -558,8 +612,13 @@ struct SysBase {
         push_mu();
         forces_parts();
         rank_prev = 0;
-        build_kernel(d.kernel_rank, d.krylov_mode, false);
-        apply_kernel(r, kr);
+        if (full_mode()) {
+            build_full_kernel();
+            apply_full(r, kr);
+        } else {
+            build_kernel(d.kernel_rank, d.krylov_mode, false);
+            apply_kernel(r, kr);
+        }
         step_no = 0;
         sync();
     }
@@ -1184,7 +1243,7 @@ void validate(const xlbomd_desc *d) {
     if (d->kernel_rank < 0 || d->kernel_rank > d->n_atoms || d->kernel_rank > 16)
         throw InvalidArg("kernel_rank must be in 0..min(n_atoms, 16)");
     if (d->kernel_every < 1) throw InvalidArg("kernel_every must be >= 1");
-    if (d->krylov_mode != 0 && d->krylov_mode != 1) throw InvalidArg("krylov_mode is 0 or 1");
+    if (d->krylov_mode < 0 || d->krylov_mode > 2) throw InvalidArg("krylov_mode is 0, 1 or 2");
     if (!(d->k0_gamma >= 0.0 && d->k0_gamma <= 1.0))
         throw InvalidArg("k0_gamma must be in (0, 1], or 0 for the automatic rule");
     if (d->precision < XLBOMD_FP64 || d->precision > XLBOMD_MIXED_BF16X3)
@@ -1391,11 +1450,16 @@ int xlbomd_kernel_apply(xlbomd_system *h, int32_t rank, const double *rr, double
     if (!h || !h->s || !rr || !kr_out) return fail(XLBOMD_E_INVALID, "null argument");
     return guarded([&] {
         SysBase &s = *h->s;
-        if (rank < 0 || rank > s.mcap) throw InvalidArg("rank above capacity");
+        if (rank < -1 || rank > s.mcap) throw InvalidArg("rank above capacity");
         XL_HIP(hipMemcpyAsync(s.r, rr, s.nat * sizeof(double), hipMemcpyHostToDevice, s.st));
         s.rank_prev = 0;
-        s.build_kernel(rank, 0, false, false);
-        s.apply_kernel(s.r, s.vtmp);
+        if (rank == -1) {
+            s.build_full_kernel();
+            s.apply_full(s.r, s.vtmp);
+        } else {
+            s.build_kernel(rank, 0, false, false);
+            s.apply_kernel(s.r, s.vtmp);
+        }
         XL_HIP(hipMemcpyAsync(kr_out, s.vtmp, s.nat * sizeof(double), hipMemcpyDeviceToHost, s.st));
         s.sync();
     });

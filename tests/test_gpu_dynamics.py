@@ -147,3 +147,29 @@ def test_table_I_rows_trajectory(P, kmax):
     w = _traj(P, s, 40, P.FP64)
     print(f"K_max {kmax}, 40 steps:", {k: f"{v:.2e}" for k, v in w.items()})
     assert w["dq"] < 1e-8 and w["dF"] < 1e-5 and w["dn"] < 1e-8
+
+
+def test_full_kernel_apply_matches_oracle(P):
+    """krylov_mode 2: K = (J - I)^-1 from all N_at responses, dense FP64
+    Gauss-Jordan, against the oracle's dense inverse."""
+    s = lattice_system(40, "c2", seed=9)
+    m = R.Model(s)
+    g = P.XLBOMD(s.replace(rank=8), precision=P.FP64, scf_tol=1e-9)
+    n = 0.05 * np.random.default_rng(4).standard_normal(s.n_atoms)
+    n -= n.mean()
+    g.solve(n)
+    el = R.electronic(m, s.pos, n)
+    kr = g.kernel_apply(-1, el.r)
+    ref = R.kernel_full(m, el) @ el.r
+    err = np.abs(kr - ref).max() / np.abs(ref).max()
+    print(f"full kernel K r rel err {err:.2e}")
+    g.close()
+    assert err < 1e-8
+
+
+def test_full_kernel_trajectory(P):
+    """Full kernel rebuilt every 5 steps in the dynamics (c1, 30 steps)."""
+    s = make_system("c1", krylov_mode=2, kernel_every=5, rank=16)
+    w = _traj(P, s, 30, P.FP64)
+    print("full kernel 30 steps:", {k: f"{v:.2e}" for k, v in w.items()})
+    assert w["dq"] < 1e-8 and w["dF"] < 1e-5 and w["dn"] < 1e-8

@@ -200,6 +200,17 @@ def test_full_rank_kernel_is_inverse_jacobian():
     assert np.abs(k.K - np.linalg.inv(J - np.eye(m.nat))).max() < 1e-10
 
 
+def test_kernel_full_matches_full_rank_sequence():
+    # the dense inverse of krylov_mode 2 against the Sherman-Morrison
+    # sequence of Eq. 50 run over all N_at directions (a different route)
+    m, s, el = _small_case()
+    Kf = R.kernel_full(m, el)
+    Ksm = R.kernel_sm(m, el, 0.25, m.nat).K
+    J = R.jacobian(m, el)
+    assert np.abs(Kf - Ksm).max() < 1e-9 * np.abs(Kf).max()
+    assert np.abs(Kf @ (J - np.eye(m.nat)) - np.eye(m.nat)).max() < 1e-10
+
+
 def test_kernel_woodbury_and_reproduction():
     # K_m from the Sherman-Morrison sequence equals the closed Woodbury form
     # a^-1 (I - W M V^T) + V M V^T, M = (V^T W)^-1, a = -1/gamma, and it maps
