@@ -129,12 +129,12 @@ __device__ __forceinline__ void tile_of(int u, int nt, int &ti, int &tj) {
     tj = row + (u - start);
 }
 
-// Write the 16 x 16 block (x, y) of a 128 x 128 output tile from the
-// accumulator of thread (wr, wc, fr, fc): C = alpha acc + beta X + beta2 X2
-// + gamma I (+ C2), with the symmetric mirror when SYM.
+// Write the 16 x 16 block at (r0, c0) of a 128 x 128 output tile from the
+// accumulator of lane (fr, fc): C = alpha acc + beta X + beta2 X2 + gamma I
+// (+ C2, + FP32 / split copies), with the symmetric mirror when SYM.
 template <typename T, bool SYM>
 __device__ __forceinline__ void epilogue_block(const GemmArgs<T> &p, long bz, int ti, int tj,
-                                               int wr, int wc, int fr, int fc, int x, int y,
+                                               int r0, int c0, int fr, int fc,
                                                const typename MF<T>::acc_t &acc) {
     using M = MF<T>;
     const int ld = p.ld;
@@ -148,8 +148,8 @@ __device__ __forceinline__ void epilogue_block(const GemmArgs<T> &p, long bz, in
     uint16_t *Cs = p.Cs;    // unbatched (expansion products)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int row = i0 + wr * 64 + x * 16 + M::out_row(fr, r);
-        const int col = j0 + wc * 64 + y * 16 + fc;
+        const int row = i0 + r0 + M::out_row(fr, r);
+        const int col = j0 + c0 + fc;
         const long o = (long)row * ld + col;
         T val = p.alpha * acc[r];
         if (X) val += p.beta * X[o];
@@ -182,30 +182,34 @@ __device__ __forceinline__ void epilogue_block(const GemmArgs<T> &p, long bz, in
     }
 }
 
-// Write one whole 128 x 128 output tile.
-template <typename T, bool SYM>
+// Write the 64 x (16 YB) output block of wave (wr, wc) of a tile.
+template <typename T, bool SYM, int YB>
 __device__ __forceinline__ void epilogue(const GemmArgs<T> &p, long bz, int ti, int tj, int wr,
                                          int wc, int fr, int fc,
-                                         const typename MF<T>::acc_t (&acc)[4][4]) {
+                                         const typename MF<T>::acc_t (&acc)[4][YB]) {
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y)
-            epilogue_block<T, SYM>(p, bz, ti, tj, wr, wc, fr, fc, x, y, acc[x][y]);
+        for (int y = 0; y < YB; ++y)
+            epilogue_block<T, SYM>(p, bz, ti, tj, wr * 64 + x * 16, wc * 16 * YB + y * 16, fr, fc,
+                                   acc[x][y]);
 }
 
 
-template <typename T, bool SYM>
-__global__ __launch_bounds__(256, 2) void gemm_tn_kernel(GemmArgs<T> p, int ntiles, int nfull,
-                                                      int nsplit, int per_xcd) {
+// NW waves per workgroup in 2 rows x NW/2 columns; each wave owns a
+// 64 x (256 / NW) block as 4 x YB 16x16 accumulator blocks (YB = 16 / NW).
+template <typename T, bool SYM, int NW = 4>
+__global__ __launch_bounds__(64 * NW, 2) void gemm_tn_kernel(GemmArgs<T> p, int ntiles, int nfull,
+                                                          int nsplit, int per_xcd) {
     // per_xcd: tail units per XCD
     using M = MF<T>;
     using acc_t = typename M::acc_t;
     using vec_t = typename M::vec_t;
+    constexpr int NTH = 64 * NW, WCN = NW / 2, YB = 16 / NW;
     constexpr int BK = M::BK;
     constexpr int VEC = 16 / sizeof(T);
     constexpr int VPR = GT / VEC;              // vectors per tile row
-    constexpr int NV = BK * GT / VEC / 256;    // 16-byte vectors per thread
+    constexpr int NV = BK * GT / VEC / NTH;    // 16-byte vectors per thread
     constexpr int PAD = 4;
     __shared__ __attribute__((aligned(16))) T As[2][BK][GT + PAD];
     __shared__ __attribute__((aligned(16))) T Bs[2][BK][GT + PAD];
@@ -244,13 +248,13 @@ __global__ __launch_bounds__(256, 2) void gemm_tn_kernel(GemmArgs<T> p, int ntil
     const int lda = p.lda ? p.lda : p.ld;
     const int i0 = ti * GT, j0 = tj * GT;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int wr = wid >> 1, wc = wid & 1;
+    const int wr = wid / WCN, wc = wid % WCN;
 
-    acc_t acc[4][4];
+    acc_t acc[4][YB];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+        for (int b = 0; b < YB; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
     const int nk1 = (p.k ? p.k : p.n) / BK;
     const int nktot = A1 ? 2 * nk1 : nk1;
@@ -262,7 +266,7 @@ __global__ __launch_bounds__(256, 2) void gemm_tn_kernel(GemmArgs<T> p, int ntil
     int lrow[NV], lcol[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        const int vi = tid + 256 * v;
+        const int vi = tid + NTH * v;
         lrow[v] = vi / VPR;
         lcol[v] = (vi % VPR) * VEC;
     }
@@ -302,34 +306,33 @@ __global__ __launch_bounds__(256, 2) void gemm_tn_kernel(GemmArgs<T> p, int ntil
         if (kt + 1 < kt1) gload(kt + 1);
 #pragma unroll
         for (int s = 0; s < BK / 4; ++s) {
-            T a[4], b[4];
+            T a[4], b[YB];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[q] = As[buf][4 * s + fr][wr * 64 + q * 16 + fc];
-                b[q] = Bs[buf][4 * s + fr][wc * 64 + q * 16 + fc];
-            }
+            for (int q = 0; q < 4; ++q) a[q] = As[buf][4 * s + fr][wr * 64 + q * 16 + fc];
+#pragma unroll
+            for (int q = 0; q < YB; ++q) b[q] = Bs[buf][4 * s + fr][wc * 16 * YB + q * 16 + fc];
 #pragma unroll
             for (int x = 0; x < 4; ++x)
 #pragma unroll
-                for (int y = 0; y < 4; ++y) acc[x][y] = M::mma(a[x], b[y], acc[x][y]);
+                for (int y = 0; y < YB; ++y) acc[x][y] = M::mma(a[x], b[y], acc[x][y]);
         }
         if (kt + 1 < kt1) sstore(buf ^ 1);
         __syncthreads();
     }
 
     if (part) {
-        // partial tile: accumulator block g = 4x + y of thread tid as one
-        // 4-vector at [(g * 256 + tid) * 4] (vector stores, contiguous
+        // partial tile: accumulator block g = YB x + y of thread tid as one
+        // 4-vector at [(g * NTH + tid) * 4] (vector stores, contiguous
         // across the workgroup)
         acc_t *wp = reinterpret_cast<acc_t *>(p.ws + ((long)bz * ntail * nsplit + w) * (GT * GT)) + tid;
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-            for (int y = 0; y < 4; ++y) wp[(x * 4 + y) * 256] = acc[x][y];
+            for (int y = 0; y < YB; ++y) wp[(x * YB + y) * NTH] = acc[x][y];
         return;
     }
 
-    epilogue<T, SYM>(p, bz, ti, tj, wr, wc, fr, fc, acc);
+    epilogue<T, SYM, YB>(p, bz, ti, tj, wr, wc, fr, fc, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -475,7 +478,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf3_kernel(GemmArgs<float> p, int
         return;
     }
     // the 16x16 bf16 MFMA leaves its accumulators in the FP32 16x16x4 layout
-    epilogue<float, SYM>(p, bz, ti, tj, wr, wc, fr, fc, acc);
+    epilogue<float, SYM, 4>(p, bz, ti, tj, wr, wc, fr, fc, acc);
 }
 
 // Sum the k-split partial tiles of each tile and apply the epilogue.  One
@@ -483,25 +486,26 @@ __global__ __launch_bounds__(256, 2) void gemm_bf3_kernel(GemmArgs<float> p, int
 // back, from each partial, the one accumulator vector its counterpart in
 // the product kernel wrote for block g (4 KB contiguous per workgroup and
 // partial), so the reduction runs on 16 workgroups per tile.
-template <typename T, bool SYM>
-__global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs<T> p, int ntiles, int nfull,
-                                                         int nsplit) {
+template <typename T, bool SYM, int NW = 4>
+__global__ __launch_bounds__(64 * NW) void gemm_fixup_kernel(GemmArgs<T> p, int ntiles,
+                                                             int nfull, int nsplit) {
     using acc_t = typename MF<T>::acc_t;
+    constexpr int NTH = 64 * NW, WCN = NW / 2, YB = 16 / NW;
     const int ntail = ntiles - nfull;
     const int u = nfull + blockIdx.x;
-    const int g = blockIdx.y, x = g >> 2, y = g & 3;
+    const int g = blockIdx.y, x = g / YB, y = g % YB;
     const long bz = blockIdx.z;
     const int nt = p.n / GT;
     int ti, tj;
     tile_of<SYM>(u, nt, ti, tj);
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int wr = wid >> 1, wc = wid & 1, fr = lane >> 4, fc = lane & 15;
+    const int wr = wid / WCN, wc = wid % WCN, fr = lane >> 4, fc = lane & 15;
     acc_t acc = acc_t{0, 0, 0, 0};
     const acc_t *wp = reinterpret_cast<const acc_t *>(
                           p.ws + ((long)bz * ntail * nsplit + (long)blockIdx.x * nsplit) *
-                                     (GT * GT)) + g * 256 + tid;
+                                     (GT * GT)) + g * NTH + tid;
     for (int s = 0; s < nsplit; ++s) acc += wp[(long)s * (GT * GT / 4)];
-    epilogue_block<T, SYM>(p, bz, ti, tj, wr, wc, fr, fc, x, y, acc);
+    epilogue_block<T, SYM>(p, bz, ti, tj, wr * 64 + x * 16, wc * 16 * YB + y * 16, fr, fc, acc);
 }
 
 inline int device_cus() {
@@ -557,6 +561,9 @@ template <typename T> long split_ws_elems(int n, bool sym, int dual, long batch)
     return std::max(1L, (long)(ntiles - s.nfull) * s.nsplit * batch * GT * GT);
 }
 
+// waves per workgroup of the product kernel by precision
+template <typename T> constexpr int TN_WAVES = std::is_same<T, double>::value ? 8 : 4;
+
 template <typename T>
 void gemm(const GemmArgs<T> &a, bool sym, hipStream_t st) {
     const int K = a.k ? a.k : a.n;
@@ -584,23 +591,34 @@ void gemm(const GemmArgs<T> &a, bool sym, hipStream_t st) {
                                    s.nfull, s.nsplit, per);
         }
     }
+    constexpr int NW = TN_WAVES<T>;
     if (!a.split3) {
         if (sym)
-            hipLaunchKernelGGL((gemm_tn_kernel<T, true>), grid, dim3(256), 0, st, a, ntiles,
-                               s.nfull, s.nsplit, per);
+            hipLaunchKernelGGL((gemm_tn_kernel<T, true, NW>), grid, dim3(64 * NW), 0, st, a,
+                               ntiles, s.nfull, s.nsplit, per);
         else
-            hipLaunchKernelGGL((gemm_tn_kernel<T, false>), grid, dim3(256), 0, st, a, ntiles,
-                               s.nfull, s.nsplit, per);
+            hipLaunchKernelGGL((gemm_tn_kernel<T, false, NW>), grid, dim3(64 * NW), 0, st, a,
+                               ntiles, s.nfull, s.nsplit, per);
     }
     XL_LAUNCH_CHECK();
     if (s.nfull < ntiles) {
-        dim3 g2(ntiles - s.nfull, 16, a.batch);
-        if (sym)
-            hipLaunchKernelGGL((gemm_fixup_kernel<T, true>), g2, dim3(256), 0, st, a, ntiles,
+        // the split kernel keeps the 4-wave accumulator layout
+        const bool w8 = !a.split3 && NW == 8;
+        dim3 g2(ntiles - s.nfull, w8 ? 8 : 16, a.batch);     // accumulator blocks per thread
+        if (w8) {
+            if (sym)
+                hipLaunchKernelGGL((gemm_fixup_kernel<T, true, 8>), g2, dim3(512), 0, st, a,
+                                   ntiles, s.nfull, s.nsplit);
+            else
+                hipLaunchKernelGGL((gemm_fixup_kernel<T, false, 8>), g2, dim3(512), 0, st, a,
+                                   ntiles, s.nfull, s.nsplit);
+        } else if (sym) {
+            hipLaunchKernelGGL((gemm_fixup_kernel<T, true, 4>), g2, dim3(256), 0, st, a, ntiles,
                                s.nfull, s.nsplit);
-        else
-            hipLaunchKernelGGL((gemm_fixup_kernel<T, false>), g2, dim3(256), 0, st, a, ntiles,
-                               s.nfull, s.nsplit);
+        } else {
+            hipLaunchKernelGGL((gemm_fixup_kernel<T, false, 4>), g2, dim3(256), 0, st, a,
+                               ntiles, s.nfull, s.nsplit);
+        }
         XL_LAUNCH_CHECK();
     }
 }
