@@ -561,8 +561,9 @@ template <typename T> long split_ws_elems(int n, bool sym, int dual, long batch)
     return std::max(1L, (long)(ntiles - s.nfull) * s.nsplit * batch * GT * GT);
 }
 
-// waves per workgroup of the product kernel by precision
-template <typename T> constexpr int TN_WAVES = std::is_same<T, double>::value ? 8 : 4;
+// waves per workgroup of the FP64 / FP32 product kernel: 8 (four per SIMD)
+// measured faster than 4 for both precisions at N = 4096
+template <typename T> constexpr int TN_WAVES = 8;
 
 template <typename T>
 void gemm(const GemmArgs<T> &a, bool sym, hipStream_t st) {
