@@ -58,8 +58,8 @@ ENERGY_EVERY = 10   # free-energy report cadence (every 10th step, in the timed 
 # (profiles/gemm_counters_n4096.md).  Valid only for the product-kernel
 # source they were measured with.
 GEMM_SRC = os.path.join(ROOT, "paper_1705_10845_amd", "csrc", "gemm.hpp")
-TRAFFIC = {"sha256": "2bf9144020aa25ccde84c74eab9b98416a603ba7db413998e589c5851a8679c6",
-           "f64": 1.335e9, "bf3": 1.088e9}
+TRAFFIC = {"sha256": "67ed2176bfc87d7b73dfddbcbb1a649e62d177890b921c7c0015c0b6d8c7907b",
+           "f64": 2.019e9, "bf3": 2.075e9}
 
 
 def traffic(key):
@@ -123,19 +123,20 @@ def cpu_baseline(n_atoms=128):
 def serving(n_requests=256, slots=16, budget_gib=96):
     """The serving workload: Poisson stream (200/s) of independent systems,
     16-512 atoms x 4 orbitals, Te U[0.02, 0.1], rank 2-6, 100 steps each,
-    admitted by HBM footprint; MIXED path."""
+    admitted by HBM footprint; the headline (MIXED_BF16X3) path."""
     from synth import serving_stream
     from paper_1705_10845_amd.serve import Server
-    from paper_1705_10845_amd import MIXED
+    from paper_1705_10845_amd import MIXED_BF16X3
     stream = serving_stream(n_requests)
-    srv = Server(hbm_budget=budget_gib << 30, max_slots=slots, precision=MIXED, steps=100,
-                 verbose=True)
+    srv = Server(hbm_budget=budget_gib << 30, max_slots=slots, precision=MIXED_BF16X3,
+                 steps=100, verbose=True)
     stats, summ = srv.run(stream)
     if summ["errors"]:
         print("[bench] serving errors:", [s.error for s in stats if s.error][:3], file=sys.stderr)
     summ["slots"] = slots
     summ["workload"] = (f"{n_requests} systems, 16-512 atoms x 4 orbitals (log-uniform), "
-                        "Poisson 200/s, Te U[0.02,0.1], rank U{2..6}, 100 steps each, MIXED")
+                        "Poisson 200/s, Te U[0.02,0.1], rank U{2..6}, 100 steps each, "
+                        "MIXED_BF16X3")
     return summ
 
 

@@ -486,19 +486,21 @@ __global__ __launch_bounds__(256, 2) void gemm_bf3_kernel(GemmArgs<float> p, int
 // back, from each partial, the one accumulator vector its counterpart in
 // the product kernel wrote for block g (4 KB contiguous per workgroup and
 // partial), so the reduction runs on 16 workgroups per tile.
+// 256 threads per workgroup whatever NW: for NW = 8 each (tile, block)
+// pair is covered by two workgroups, one per half of the product's threads.
 template <typename T, bool SYM, int NW = 4>
-__global__ __launch_bounds__(64 * NW) void gemm_fixup_kernel(GemmArgs<T> p, int ntiles,
-                                                             int nfull, int nsplit) {
+__global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs<T> p, int ntiles,
+                                                         int nfull, int nsplit) {
     using acc_t = typename MF<T>::acc_t;
-    constexpr int NTH = 64 * NW, WCN = NW / 2, YB = 16 / NW;
+    constexpr int NTH = 64 * NW, WCN = NW / 2, YB = 16 / NW, NH = NTH / 256;
     const int ntail = ntiles - nfull;
     const int u = nfull + blockIdx.x;
-    const int g = blockIdx.y, x = g / YB, y = g % YB;
+    const int g = blockIdx.y / NH, x = g / YB, y = g % YB;
     const long bz = blockIdx.z;
     const int nt = p.n / GT;
     int ti, tj;
     tile_of<SYM>(u, nt, ti, tj);
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = (blockIdx.y % NH) * 256 + threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wr = wid / WCN, wc = wid % WCN, fr = lane >> 4, fc = lane & 15;
     acc_t acc = acc_t{0, 0, 0, 0};
     const acc_t *wp = reinterpret_cast<const acc_t *>(
@@ -605,13 +607,14 @@ void gemm(const GemmArgs<T> &a, bool sym, hipStream_t st) {
     if (s.nfull < ntiles) {
         // the split kernel keeps the 4-wave accumulator layout
         const bool w8 = !a.split3 && NW == 8;
-        dim3 g2(ntiles - s.nfull, w8 ? 8 : 16, a.batch);     // accumulator blocks per thread
+        // (accumulator blocks per thread) x (256-thread groups of the product)
+        dim3 g2(ntiles - s.nfull, 16, a.batch);
         if (w8) {
             if (sym)
-                hipLaunchKernelGGL((gemm_fixup_kernel<T, true, 8>), g2, dim3(512), 0, st, a,
+                hipLaunchKernelGGL((gemm_fixup_kernel<T, true, 8>), g2, dim3(256), 0, st, a,
                                    ntiles, s.nfull, s.nsplit);
             else
-                hipLaunchKernelGGL((gemm_fixup_kernel<T, false, 8>), g2, dim3(512), 0, st, a,
+                hipLaunchKernelGGL((gemm_fixup_kernel<T, false, 8>), g2, dim3(256), 0, st, a,
                                    ntiles, s.nfull, s.nsplit);
         } else if (sym) {
             hipLaunchKernelGGL((gemm_fixup_kernel<T, true, 4>), g2, dim3(256), 0, st, a, ntiles,

@@ -21,27 +21,28 @@ from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
-from .binding import MIXED, FP32, FP64, XLBOMD
+from .binding import MIXED, MIXED_BF16X3, FP32, FP64, XLBOMD
 
-_ESZ = {FP64: (8, 8), FP32: (4, 4), MIXED: (8, 4)}
+_ESZ = {FP64: (8, 8), FP32: (4, 4), MIXED: (8, 4), MIXED_BF16X3: (8, 4)}
 
 
 def footprint_bytes(system, precision=MIXED, levels=10) -> int:
-    """Upper estimate of the device memory one system holds.
+    """Upper estimate of the device memory one system holds (no energy
+    evaluation, which the server does not request).
 
-    Expansion matrices: Z_0..Z_L, Y_0..Y_{L-1}, seed, seed^2, Z_L^2, D and
-    four work matrices; responses: three matrices per direction, plus the
-    response-precision copies of the expansion operands when the two
-    precisions differ; FP64 energy workspace of seven matrices.
+    Expansion matrices: Z_0..Z_L, Y_0..Y_{L-1}, A_0..A_{L-1}, the seed
+    powers Y, Y^2, Y^3 and four work matrices; responses: three matrices per
+    direction (four on the split path), plus the response-precision copies
+    of the expansion operands (Z, Y, Y..Y^4) when the two precisions differ.
     """
     n = system.n_atoms * system.n_orb
     npad = -(-n // 128) * 128
     ef, er = _ESZ[precision]
     m = max(1, system.rank)
-    mats_f = 2 * levels + 1 + 9
-    mats_r = 3 * m + ((2 * levels + 3) if ef != er else 0)
+    mats_f = 3 * levels + 8
+    mats_r = (4 if precision == MIXED_BF16X3 else 3) * m + ((2 * levels + 5) if ef != er else 0)
     vecs = 64 * system.n_atoms * 8 + 16 * npad * 8
-    return npad * npad * (mats_f * ef + mats_r * er + 7 * 8) + vecs
+    return npad * npad * (mats_f * ef + mats_r * er) + vecs
 
 
 @dataclass
