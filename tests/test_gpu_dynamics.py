@@ -173,3 +173,42 @@ def test_full_kernel_trajectory(P):
     w = _traj(P, s, 30, P.FP64)
     print("full kernel 30 steps:", {k: f"{v:.2e}" for k, v in w.items()})
     assert w["dq"] < 1e-8 and w["dF"] < 1e-5 and w["dn"] < 1e-8
+
+
+def test_checkpoint_resume(P):
+    """get_state / set_state: a run resumed from a checkpoint in a fresh
+    handle continues the original trajectory (to the solver tolerances)."""
+    s = lattice_system(40, "c2", seed=21)
+    g = P.XLBOMD(s, precision=P.MIXED_BF16X3, scf_tol=1e-10)
+    g.step(4, report=False)
+    ck = g.get_state()
+    g.step(4, report=False)
+    n_a, q_a = g.charges()
+    F_a, _ = g.forces(energy=False)
+    g.close()
+    h = P.XLBOMD(s, precision=P.MIXED_BF16X3, scf_tol=1e-10)
+    h.set_state(pos=ck["pos"], vel=ck["vel"], n_hist=ck["n_hist"], kr=ck["kr"])
+    h.step(4, report=False)
+    n_b, q_b = h.charges()
+    F_b, _ = h.forces(energy=False)
+    h.close()
+    dn, dq, dF = np.abs(n_a - n_b).max(), np.abs(q_a - q_b).max(), np.abs(F_a - F_b).max()
+    print(f"resume after 4 + 4 steps: dn {dn:.1e} dq {dq:.1e} dF {dF:.1e}")
+    # n differs by the mu-solve tolerance (the resumed run has no mu history
+    # to predict from); the charges carry it amplified by |J|
+    assert dn < 1e-8 and dq < 1e-8 + 100.0 * dn and dF < 1e-6
+
+
+def test_divergence_is_reported(P):
+    """K0 = -I on the stiff s+3p model puts modes of K0 (J - I) near -70, far
+    outside the electronic integrator's stability range: the run blows up
+    and the library reports it as an error (diverged or no convergence)."""
+    s = lattice_system(40, "c2", seed=1, k0_gamma=1.0, rank=1)
+    with pytest.raises(P.XlbomdError) as e:
+        g = P.XLBOMD(s, precision=P.FP64, scf_tol=1e-10, scf_max_iter=60)
+        try:
+            g.step(200, report=False)
+        finally:
+            g.close()
+    print("error code", e.value.code, str(e.value))
+    assert e.value.code in (-3, -4)
