@@ -27,7 +27,8 @@ sys.path.insert(0, ROOT)
 # so its algorithmic peak is a third of the bf16 rate
 PEAK = {"f32": 157.3, "f64": 78.6, "bf3": 2500.0 / 3}
 KERNEL = {"f64": "gemm_tn_kernel<double>", "f32": "gemm_tn_kernel<float>",
-          "bf3": "gemm_bf3_kernel"}
+          "bf3": "split bf16x3 products (gemm_bw_kernel on pre-split operands, "
+                 "gemm_bf3_kernel on FP32 operands)"}
 
 
 def _sync():
@@ -57,15 +58,21 @@ ENERGY_EVERY = 10   # free-energy report cadence (every 10th step, in the timed 
 # script scaled by the same counters' readings for a 1 GiB device copy
 # (profiles/gemm_counters_n4096.md).  Valid only for the product-kernel
 # source they were measured with.
-GEMM_SRC = os.path.join(ROOT, "paper_1705_10845_amd", "csrc", "gemm.hpp")
-TRAFFIC = {"sha256": "67ed2176bfc87d7b73dfddbcbb1a649e62d177890b921c7c0015c0b6d8c7907b",
-           "f64": 2.019e9, "bf3": 2.075e9}
+GEMM_SRC = [os.path.join(ROOT, "paper_1705_10845_amd", "csrc", f)
+            for f in ("gemm.hpp", "gemm_split.hpp")]
+TRAFFIC = {"sha256": None}
+
+
+def gemm_src_hash():
+    h = hashlib.sha256()
+    for p in GEMM_SRC:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def traffic(key):
-    with open(GEMM_SRC, "rb") as f:
-        h = hashlib.sha256(f.read()).hexdigest()
-    return TRAFFIC.get(key) if h == TRAFFIC["sha256"] else None
+    return TRAFFIC.get(key) if gemm_src_hash() == TRAFFIC["sha256"] else None
 
 
 def time_path(system, precision, steps, warmup, label):
@@ -214,9 +221,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": "c2: 1024 atoms x 4 orbitals (N=4096) jittered cubic "
                                "lattice, Te=0.05, rank-4 sequential Krylov kernel every "
-                               "step, K_max=5; mixed path: FP64 MFMA density-matrix "
-                               "expansion, split bf16x3 MFMA kernel responses (FP32 "
-                               "accumulation), FP64 mu/Krylov/Verlet/energy sums",
+                               "step, K_max=5; mixed path: density-matrix expansion "
+                               "with FP64 MFMA seed, A_k, residuals, Z_L^2 and D, level "
+                               "inverses in split bf16x3 refined against FP64 "
+                               "residuals; split bf16x3 MFMA kernel responses (FP32 "
+                               "accumulation); FP64 mu/Krylov/Verlet/energy sums",
                    "n_orbitals": 4096, "kernel_rank": 4, "energy_every": ENERGY_EVERY,
                    "foe_levels": mixed["report"]["foe_levels"]},
         "roofline": roof(mixed["prof"], args.steps),

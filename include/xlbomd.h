@@ -62,12 +62,19 @@ typedef enum {
     XLBOMD_MIXED = 2,        /* density-matrix expansion in FP64 MFMA (it
                                 fixes charges, forces, energy); the
                                 kernel's response products in FP32 MFMA   */
-    XLBOMD_MIXED_BF16X3 = 3  /* as XLBOMD_MIXED, but the response products
-                                are split-precision bf16x3: each FP32
+    XLBOMD_MIXED_BF16X3 = 3  /* split-precision bf16x3 products: each FP32
                                 operand is split into bf16 hi + lo parts
                                 and hi*hi + hi*lo + lo*hi is accumulated
                                 in FP32 on the bf16 matrix cores (relative
-                                error ~2^-16 per operand); storage FP32   */
+                                error ~2^-16 per operand).  All response
+                                products are split; in the expansion the
+                                seed, A_k = I + 4 Z_k^2, Z_L^2 and D are
+                                FP64, the inverse of A_k is split and
+                                Z_{k+1} is refined against an FP64
+                                residual of A_k Z_{k+1} = 2 Z_k (once per
+                                level in a step: charges within ~1e-9 of
+                                the FP64 path; twice inside an SCF whose
+                                tolerance is below 1e-8)                   */
 } xlbomd_precision;
 
 /* System descriptor.  Model (orthogonal SCC tight binding):

@@ -96,9 +96,10 @@ template <typename T> struct GemmArgs {
     const T *X = nullptr, *X2 = nullptr;
     const double *kscale = nullptr;
     bool kscale_both = false;   // also scale row k of B_1 (else B_0 only)
-    T *C = nullptr, *C2 = nullptr;
+    T *C = nullptr, *C2 = nullptr;   // C may be null when a copy below is set
     float *Cf = nullptr;    // optional FP32 copy of C (FP64 products only)
     uint16_t *Cs = nullptr; // optional split bf16 copy of C (planes Cs_pl apart)
+    uint16_t *Cs2 = nullptr;// optional split bf16 copy of C2 (planes Cs_pl apart)
     long Cs_pl = 0;
     T alpha = 1, beta = 0, beta2 = 0, gamma = 0, p0 = 0, p1 = 0;
     long sA0 = 0, sB0 = 0, sA1 = 0, sB1 = 0, sX = 0, sX2 = 0, sC = 0, sC2 = 0, sK = 0;
@@ -140,7 +141,7 @@ __device__ __forceinline__ void epilogue_block(const GemmArgs<T> &p, long bz, in
     const int ld = p.ld;
     const int i0 = ti * GT, j0 = tj * GT;
     // lane (fr, fc) of block (x, y) holds rows M::out_row(fr, r), column fc
-    T *C = p.C + bz * p.sC;
+    T *C = p.C ? p.C + bz * p.sC : nullptr;
     T *C2 = p.C2 ? p.C2 + bz * p.sC2 : nullptr;
     const T *X = p.X ? p.X + bz * p.sX : nullptr;
     const T *X2 = p.X2 ? p.X2 + bz * p.sX2 : nullptr;
@@ -156,19 +157,26 @@ __device__ __forceinline__ void epilogue_block(const GemmArgs<T> &p, long bz, in
         if (X2) val += p.beta2 * X2[o];
         if (row == col) val += p.gamma;
         T val2 = 0;
-        if (C2) val2 = p.p1 * val + (row == col ? p.p0 : (T)0);
+        if (C2 || p.Cs2) val2 = p.p1 * val + (row == col ? p.p0 : (T)0);
         if (!SYM) {
-            C[o] = val;
+            if (C) C[o] = val;
             if (C2) C2[o] = val2;
             if (Cf) Cf[o] = (float)val;
             if (Cs) put_split(Cs, p.Cs_pl, o, (float)val);
+            if (p.Cs2) put_split(p.Cs2, p.Cs_pl, o, (float)val2);
         } else if (ti < tj || row <= col) {
             const long ot = (long)col * ld + row;
-            C[o] = val;
-            C[ot] = val;
+            if (C) {
+                C[o] = val;
+                C[ot] = val;
+            }
             if (C2) {
                 C2[o] = val2;
                 C2[ot] = val2;
+            }
+            if (p.Cs2) {
+                put_split(p.Cs2, p.Cs_pl, o, (float)val2);
+                put_split(p.Cs2, p.Cs_pl, ot, (float)val2);
             }
             if (Cf) {
                 Cf[o] = (float)val;
@@ -522,7 +530,8 @@ inline int device_cus() {
     return cus;
 }
 
-// Work schedule of one launch (two workgroups per CU for both precisions).
+// Work schedule of one launch (per_cu workgroups per CU: two for the
+// 128 x 128 kernels, one for the 256 x 128 split kernel).
 // More tiles than workgroup slots: whole tiles fill complete rounds and only
 // the tiles of the last, partial round are split along k over the
 // otherwise idle slots.  Fewer tiles than slots: every tile is split into
@@ -532,8 +541,8 @@ inline int device_cus() {
 struct Sched {
     int nfull, nsplit;
 };
-template <typename T> Sched schedule(int ntiles, int nkt, long batch) {
-    const long slots = (long)device_cus() * 2;
+template <typename T> Sched schedule(int ntiles, int nkt, long batch, int per_cu = 2) {
+    const long slots = (long)device_cus() * per_cu;
     if (batch > 1) return {ntiles, 1};
     if (ntiles > slots) {
         const long rounds = ntiles / slots;

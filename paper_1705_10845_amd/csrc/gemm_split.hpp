@@ -5,11 +5,13 @@
 // hi (so a split matrix occupies the bytes of one FP32 matrix).  x = hi + lo
 // with hi = bf16(x), lo = bf16(x - hi) of the FP32 value.
 //
-// Product: C[i][j] = alpha sum_s sum_k A_s[i][k] B_s[j][k] + beta X[i][j],
-// i.e. both operands are read as rows with k contiguous ("NT").  Every
-// operand of the response recursion is symmetric, or is stored transposed
-// by the product that makes it, so this is the matrix product the recursion
-// needs.  C and X are split matrices too.
+// Product: C[i][j] = alpha sum_s sum_k A_s[i][k] B_s[j][k] + beta X[i][j]
+// + gamma delta_ij, i.e. both operands are read as rows with k contiguous
+// ("NT").  Every operand of the response recursion is symmetric, or is
+// stored transposed by the product that makes it, so this is the matrix
+// product the recursion needs.  C and X are split matrices too; X may
+// instead be an FP64 matrix (Xd) and the result may go (also) to an FP64
+// matrix Cd, with the epilogue sum taken in FP64.
 //
 // Against gemm_bf3_kernel (FP32 operands split while staging) the k-tiles
 // here are copied into LDS as 16-byte chunks with no conversion work, the
@@ -28,8 +30,10 @@ struct SplitArgs {
     long pl = 0;                                  // plane offset (elements)
     const uint16_t *A0 = nullptr, *B0 = nullptr, *A1 = nullptr, *B1 = nullptr;
     const uint16_t *X = nullptr;
+    const double *Xd = nullptr;                   // FP64 X (instead of X)
     uint16_t *C = nullptr;
-    float alpha = 1.f, beta = 0.f;
+    double *Cd = nullptr;                         // FP64 result (C may be null)
+    float alpha = 1.f, beta = 0.f, gamma = 0.f;
     long sA0 = 0, sB0 = 0, sA1 = 0, sB1 = 0, sX = 0, sC = 0;   // batch strides (elements)
     float *ws = nullptr;                          // split-k partial tiles (FP32)
     long ws_elems = 0;
@@ -41,29 +45,45 @@ __device__ __forceinline__ int swz(int r) {
     return ((r >> 2) & 1) | ((((r >> 1) ^ (r >> 3)) & 1) << 1);
 }
 
-// Write the 16 x 16 accumulator block whose first row / column within the
-// 128 x 128 tile are (r0, c0), from lane (fr, fc).
+// Write the 16 x 16 accumulator block whose first row / column are
+// (i0 + r0, j0 + c0), from lane (fr, fc).  With SYM only elements on or
+// above the diagonal are written, each with its mirror (the tiles of a
+// symmetric product cover every such element exactly once).
+template <bool SYM>
+__device__ __forceinline__ void epilogue_split_at(const SplitArgs &p, long bz, int i0, int j0,
+                                                  int r0, int c0, int fr, int fc,
+                                                  const f32x4 &acc) {
+    const int ld = p.ld;
+    uint16_t *C = p.C ? p.C + bz * p.sC : nullptr;
+    double *Cd = p.Cd ? p.Cd + bz * p.sC : nullptr;
+    const uint16_t *X = p.X ? p.X + bz * p.sX : nullptr;
+    const double *Xd = p.Xd ? p.Xd + bz * p.sX : nullptr;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = i0 + r0 + 4 * fr + r;
+        const int col = j0 + c0 + fc;
+        const long o = (long)row * ld + col;
+        if (SYM && row > col) continue;
+        double val = (double)(p.alpha * acc[r]);
+        if (X) val += (double)(p.beta * get_split(X, p.pl, o));
+        if (Xd) val += (double)p.beta * Xd[o];
+        if (row == col) val += (double)p.gamma;
+        const long ot = (long)col * ld + row;
+        if (C) {
+            put_split(C, p.pl, o, (float)val);
+            if (SYM && row != col) put_split(C, p.pl, ot, (float)val);
+        }
+        if (Cd) {
+            Cd[o] = val;
+            if (SYM && row != col) Cd[ot] = val;
+        }
+    }
+}
 template <bool SYM>
 __device__ __forceinline__ void epilogue_split_block(const SplitArgs &p, long bz, int ti,
                                                      int tj, int r0, int c0, int fr, int fc,
                                                      const f32x4 &acc) {
-    const int ld = p.ld;
-    uint16_t *C = p.C + bz * p.sC;
-    const uint16_t *X = p.X ? p.X + bz * p.sX : nullptr;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int row = ti * GT + r0 + 4 * fr + r;
-        const int col = tj * GT + c0 + fc;
-        const long o = (long)row * ld + col;
-        float val = p.alpha * acc[r];
-        if (X) val += p.beta * get_split(X, p.pl, o);
-        if (!SYM) {
-            put_split(C, p.pl, o, val);
-        } else if (ti < tj || row <= col) {
-            put_split(C, p.pl, o, val);
-            put_split(C, p.pl, (long)col * ld + row, val);
-        }
-    }
+    epilogue_split_at<SYM>(p, bz, ti * GT, tj * GT, r0, c0, fr, fc, acc);
 }
 
 // 512 threads = 8 waves in 2 (rows) x 4 (columns), 64 x 32 per wave
@@ -220,13 +240,246 @@ __global__ __launch_bounds__(BS_T) void gemm_bs_fixup_kernel(SplitArgs p, int nt
     epilogue_split_block<SYM>(p, bz, ti, tj, wr * 64 + x * 16, wc * 32 + y * 16, fr, fc, acc);
 }
 
+// ---------------------------------------------------------------------------
+// Wide variant: 256 x 128 workgroup tile, 16 waves (4 x 4 of 64 x 32), one
+// workgroup per CU (96 KB of LDS).  The k-tile bytes per flop drop by a
+// quarter against two 128 x 128 tiles, which is what bounds the split path
+// (n % 256 == 0).  Tiles of a symmetric product: in 256-row block bi, the
+// 128-column blocks bj >= 2 bi.
+// ---------------------------------------------------------------------------
+constexpr int BW_T = 1024;
+constexpr int BW_M = 256;
+constexpr int BW_TILE = BW_M * GT;     // elements of one tile
+
+inline int wide_tiles(int n, bool sym) {
+    const int nbi = n / BW_M, nbj = n / GT;
+    if (!sym) return nbi * nbj;
+    int t = 0;
+    for (int bi = 0; bi < nbi; ++bi) t += nbj - 2 * bi;
+    return t;
+}
+// Tile order: groups of BW_GM 256-row blocks, column by column inside a
+// group, so that the workgroups an XCD runs at once (a contiguous range of
+// units) share few row and column panels in its L2.
+constexpr int BW_GM = 4;
+template <bool SYM>
+__device__ __forceinline__ void tilew_of(int u, int nbj, int &bi, int &bj) {
+    const int nbi = nbj / 2;
+    int bi0 = 0, start = 0, gm = 0;
+    for (;;) {
+        gm = min(BW_GM, nbi - bi0);
+        int cnt = gm * nbj;
+        if (SYM) cnt -= gm * (2 * bi0 + gm - 1);     // rows keep bj >= 2 bi
+        if (u < start + cnt) break;
+        start += cnt;
+        bi0 += BW_GM;
+    }
+    int v = u - start;
+    if (!SYM) {
+        bi = bi0 + v % gm;
+        bj = v / gm;
+        return;
+    }
+    for (int c = 2 * bi0;; ++c) {
+        const int h = min(gm, c / 2 - bi0 + 1);
+        if (v < h) {
+            bi = bi0 + v;
+            bj = c;
+            return;
+        }
+        v -= h;
+    }
+}
+
+template <bool SYM>
+__global__ __launch_bounds__(BW_T, 1) void gemm_bw_kernel(SplitArgs p, int ntiles, int nfull,
+                                                       int nsplit, int per_xcd) {
+    using acc_t = f32x4;
+    __shared__ __attribute__((aligned(16))) u32x4 As[2][2][BW_M][4];
+    __shared__ __attribute__((aligned(16))) u32x4 Bs[2][2][GT][4];
+
+    const int b = blockIdx.x;
+    const int ntail = ntiles - nfull;
+    const int nfull_pad = ((nfull + NXCD - 1) / NXCD) * NXCD;
+    int unit;
+    if (b < nfull_pad) {
+        unit = (b % NXCD) * (nfull_pad / NXCD) + b / NXCD;
+        if (unit >= nfull) return;
+    } else {
+        const int bb = b - nfull_pad;
+        unit = nfull + (bb % NXCD) * per_xcd + bb / NXCD;
+        if (unit >= nfull + ntail * nsplit) return;
+    }
+    const bool part = unit >= nfull;
+    const int w = unit - nfull;
+    const int u = part ? nfull + w / nsplit : unit;
+    const int split = part ? w % nsplit : 0;
+    const int ns = part ? nsplit : 1;
+    int bi, bj;
+    tilew_of<SYM>(u, p.n / GT, bi, bj);
+    const long bz = blockIdx.z;
+    const uint16_t *A0 = p.A0 + bz * p.sA0, *B0 = p.B0 + bz * p.sB0;
+    const uint16_t *A1 = p.A1 ? p.A1 + bz * p.sA1 : nullptr;
+    const uint16_t *B1 = p.B1 ? p.B1 + bz * p.sB1 : nullptr;
+    const int ld = p.ld;
+    const long pl = p.pl;
+    const int i0 = bi * BW_M, j0 = bj * GT;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wr = wid >> 2, wc = wid & 3;
+
+    acc_t acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = acc_t{0, 0, 0, 0};
+
+    const int nk1 = p.n / B3K;
+    const int nktot = A1 ? 2 * nk1 : nk1;
+    const int kt0 = (int)((long)nktot * split / ns);
+    const int kt1 = (int)((long)nktot * (split + 1) / ns);
+
+    // A: 2 planes x 256 rows x 4 chunks (2 per thread); B: 2 x 128 x 4 (1)
+    u32x4 ra[2], rb;
+    auto gload = [&](int kt) {
+        const bool second = kt >= nk1;
+        const uint16_t *Ap = second ? A1 : A0;
+        const uint16_t *Bp = second ? B1 : B0;
+        const int kb = (second ? kt - nk1 : kt) * B3K;
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int idx = tid + BW_T * v;
+            const int pln = idx >> 10, row = (idx >> 2) & (BW_M - 1), ch = idx & 3;
+            ra[v] = *reinterpret_cast<const u32x4 *>(Ap + pln * pl + kb + 8 * ch +
+                                                     (long)(i0 + row) * ld);
+        }
+        const int pln = tid >> 9, row = (tid >> 2) & (GT - 1), ch = tid & 3;
+        rb = *reinterpret_cast<const u32x4 *>(Bp + pln * pl + kb + 8 * ch + (long)(j0 + row) * ld);
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int idx = tid + BW_T * v;
+            const int pln = idx >> 10, row = (idx >> 2) & (BW_M - 1), ch = idx & 3;
+            As[buf][pln][row][ch ^ swz(row)] = ra[v];
+        }
+        const int pln = tid >> 9, row = (tid >> 2) & (GT - 1), ch = tid & 3;
+        Bs[buf][pln][row][ch ^ swz(row)] = rb;
+    };
+
+    gload(kt0);
+    sstore(0);
+    __syncthreads();
+    const int fr = lane >> 4, fc = lane & 15;
+    for (int kt = kt0; kt < kt1; ++kt) {
+        const int buf = (kt - kt0) & 1;
+        if (kt + 1 < kt1) gload(kt + 1);
+        bf16x8 ah[4], al[4], bh[2], bl[2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = wr * 64 + q * 16 + fc, c = fr ^ swz(r);
+            ah[q] = __builtin_bit_cast(bf16x8, As[buf][0][r][c]);
+            al[q] = __builtin_bit_cast(bf16x8, As[buf][1][r][c]);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int r = wc * 32 + q * 16 + fc, c = fr ^ swz(r);
+            bh[q] = __builtin_bit_cast(bf16x8, Bs[buf][0][r][c]);
+            bl[q] = __builtin_bit_cast(bf16x8, Bs[buf][1][r][c]);
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], bh[y], acc[x][y], 0, 0, 0);
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bl[y], acc[x][y], 0, 0, 0);
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
+            }
+        if (kt + 1 < kt1) sstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    if (part) {
+        // block g = 2x + y of thread tid at [(g * 1024 + tid) * 4]
+        acc_t *wp = reinterpret_cast<acc_t *>(p.ws + ((long)bz * ntail * nsplit + w) * BW_TILE) + tid;
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) wp[(x * 2 + y) * BW_T] = acc[x][y];
+        return;
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+            epilogue_split_at<SYM>(p, bz, i0, j0, wr * 64 + x * 16, wc * 32 + y * 16, fr, fc,
+                                   acc[x][y]);
+}
+
+// One 256-thread workgroup per (tail tile, block g, quarter of the product's
+// threads): sums the vectors its counterparts wrote in every partial.
+template <bool SYM>
+__global__ __launch_bounds__(256) void gemm_bw_fixup_kernel(SplitArgs p, int ntiles, int nfull,
+                                                            int nsplit) {
+    const int ntail = ntiles - nfull;
+    const int u = nfull + blockIdx.x;
+    const int g = blockIdx.y >> 2, x = g >> 1, y = g & 1;
+    const long bz = blockIdx.z;
+    int bi, bj;
+    tilew_of<SYM>(u, p.n / GT, bi, bj);
+    const int tid = (blockIdx.y & 3) * 256 + threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wr = wid >> 2, wc = wid & 3, fr = lane >> 4, fc = lane & 15;
+    f32x4 acc = f32x4{0, 0, 0, 0};
+    const f32x4 *wp = reinterpret_cast<const f32x4 *>(
+                          p.ws + ((long)bz * ntail * nsplit + (long)blockIdx.x * nsplit) *
+                                     BW_TILE) + g * BW_T + tid;
+    for (int s = 0; s < nsplit; ++s) acc += wp[(long)s * (BW_TILE / 4)];
+    epilogue_split_at<SYM>(p, bz, bi * BW_M, bj * GT, wr * 64 + x * 16, wc * 32 + y * 16, fr, fc,
+                           acc);
+}
+
 inline long split_bs_ws_elems(int n, bool sym, int dual, long batch) {
-    return split_ws_elems<float>(n, sym, dual, batch);
+    long e = split_ws_elems<float>(n, sym, dual, batch);
+    if (n % BW_M == 0) {
+        const int nt = wide_tiles(n, sym);
+        const Sched s = schedule<float>(nt, (n / B3K) * (dual ? 2 : 1), batch, 1);
+        e = std::max(e, (long)(nt - s.nfull) * s.nsplit * batch * BW_TILE);
+    }
+    return e;
 }
 
 inline void gemm_split(const SplitArgs &a, bool sym, hipStream_t st) {
     if (a.n % GT != 0 || a.ld % 8 != 0 || a.pl % 8 != 0)
         throw InvalidArg("gemm_split: n must be a multiple of 128");
+    if (!a.C && !a.Cd) throw InvalidArg("gemm_split: no output");
+    if (a.n % BW_M == 0) {          // 256 x 128 tiles, one workgroup per CU
+        const int ntiles = wide_tiles(a.n, sym);
+        const int nkt = (a.n / B3K) * (a.A1 ? 2 : 1);
+        Sched s = a.ws ? schedule<float>(ntiles, nkt, a.batch, 1) : Sched{ntiles, 1};
+        if (s.nsplit > 1 && (long)(ntiles - s.nfull) * s.nsplit * a.batch * BW_TILE > a.ws_elems)
+            s = Sched{ntiles, 1};
+        const int nfull_pad = ((s.nfull + NXCD - 1) / NXCD) * NXCD;
+        const int tail_units = (ntiles - s.nfull) * s.nsplit;
+        const int per = (tail_units + NXCD - 1) / NXCD;
+        dim3 grid(nfull_pad + per * NXCD, 1, a.batch);
+        if (sym)
+            hipLaunchKernelGGL((gemm_bw_kernel<true>), grid, dim3(BW_T), 0, st, a, ntiles,
+                               s.nfull, s.nsplit, per);
+        else
+            hipLaunchKernelGGL((gemm_bw_kernel<false>), grid, dim3(BW_T), 0, st, a, ntiles,
+                               s.nfull, s.nsplit, per);
+        XL_LAUNCH_CHECK();
+        if (s.nfull < ntiles) {
+            dim3 g2(ntiles - s.nfull, 32, a.batch);   // 8 blocks x 4 thread quarters
+            if (sym)
+                hipLaunchKernelGGL((gemm_bw_fixup_kernel<true>), g2, dim3(256), 0, st, a, ntiles,
+                                   s.nfull, s.nsplit);
+            else
+                hipLaunchKernelGGL((gemm_bw_fixup_kernel<false>), g2, dim3(256), 0, st, a,
+                                   ntiles, s.nfull, s.nsplit);
+            XL_LAUNCH_CHECK();
+        }
+        return;
+    }
     const int nt = a.n / GT;
     const int ntiles = sym ? nt * (nt + 1) / 2 : nt * nt;
     const int nkt = (a.n / B3K) * (a.A1 ? 2 : 1);

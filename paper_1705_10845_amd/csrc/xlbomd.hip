@@ -14,10 +14,14 @@
 // D = I - 2 Z_L.  A_k has its spectrum in [1, 1 + t_k,max^2] within [1, 2],
 // so Y_k follows from a fixed Chebyshev-optimal linear guess plus a few
 // Newton-Schulz steps Y <- Y (2I - A Y), the number of steps chosen per level
-// from the known spectral bound.  The seed t0 = y - y^3/3, y = X/2^(L+1),
-// is tanh(y) to O(y^5), which lets L be about half of what t0 = y needs for
-// the same truncation error.  All products are dense symmetric GEMMs on
-// MFMA (FP64 or FP32).  The chemical potential follows from a Newton step
+// from the known spectral bound.  The seed t0 = y - y^3/3 + 2 y^5/15,
+// y = X/2^(L+1), is tanh(y) to O(y^7), which lets L be well under half of
+// what t0 = y needs for the same truncation error.  All products are dense
+// symmetric GEMMs on MFMA (FP64 or FP32).  On the split path (MIXED_BF16X3)
+// the inverse of each level runs as split bf16x3 products and Z_{k+1} is
+// then corrected with the FP64 residual 2 Z_k - A_k Z_{k+1}: only A_k, the
+// residual, the seed, Z_L^2 and D stay FP64 products.  The chemical
+// potential follows from a Newton step
 // on Tr D in FP64 (rerun of the expansion if beta |dmu| is above a
 // threshold) and a first-order correction dD/dmu = (beta/2)(I - 4 Z_L^2).
 //
@@ -132,6 +136,14 @@ int choose_levels(double xmax, double tol) {
 struct SysBase {
     virtual ~SysBase() = default;
     xlbomd_desc d{};
+    // RMS residual tolerance of the SCF loop in progress (0: none); the split
+    // path's expansion refines twice per level below 1e-8 (once otherwise)
+    double scf_need = 0.0;
+    struct ScfNeed {
+        double &ref;
+        ScfNeed(double &r, double v) : ref(r) { ref = v; }
+        ~ScfNeed() { ref = 0.0; }
+    };
     int nat = 0, no = 0, N = 0, Np = 0;
     double beta = 0.0, zc = 0.0;
     hipStream_t st = nullptr;
@@ -587,6 +599,7 @@ struct SysBase {
         const double tol = d.scf_tol > 0 ? d.scf_tol : 1e-10;
         const int maxit = d.scf_max_iter > 0 ? d.scf_max_iter : 200;
         bool have = false;
+        ScfNeed need(scf_need, tol);
         for (scf_iters = 0;; ++scf_iters) {
             solve(ncur, mu, have);
             have = true;
@@ -633,6 +646,7 @@ struct SysBase {
         if (gamma > 0.0) d.k0_gamma = gamma;
         bool have = false, ok = false;
         int it = 0;
+        ScfNeed need(scf_need, tol);
         try {
             for (;; ++it) {
                 solve(ncur, mu, have);
@@ -733,6 +747,9 @@ template <typename TF, typename TR> struct Sys : SysBase {
         long &wn = sizeof(U) == 8 ? ws_dn : ws_fn;
         if (!w) {
             wn = std::max(split_ws_elems<U>(Np, true, 1, 1), split_ws_elems<U>(Np, false, 1, 1));
+            if (sizeof(U) == 4)     // the split products' 256 x 128 tiles
+                wn = std::max({wn, split_bs_ws_elems(Np, true, 1, 1),
+                               split_bs_ws_elems(Np, false, 1, 1)});
             w = dalloc<U>(wn);
             mem.ptrs.push_back(w);
         }
@@ -800,8 +817,11 @@ template <typename TF, typename TR> struct Sys : SysBase {
             copy_out(a, Zr[0]);
             run_gemm(a, true);
         }
-        // Newton-Schulz target per level: far below the truncation bound
-        const double nstol = (sizeof(TF) == 8) ? 1e-12 : 1e-8;
+        // Newton-Schulz target per level: far below the truncation bound; on
+        // the split path the split products' own accuracy (the level is then
+        // brought to FP64 accuracy by a residual refinement of Z_{k+1})
+        const bool refine = FUSE_COPY && resp_split;
+        const double nstol = refine ? 3e-5 : (sizeof(TF) == 8) ? 1e-12 : 1e-8;
         double t = t0max;
         for (int k = 0; k < L; ++k) {
             // spectrum of A_k within [1, 1 + b]; Chebyshev-optimal first
@@ -821,6 +841,15 @@ template <typename TF, typename TR> struct Sys : SysBase {
             const bool quad = (1 + 2 * ns2) < 2 * ns1;
             const int ns = quad ? ns2 : ns1;
             ns_total += ns;
+            if (refine) {
+                const double lin[2] = {8.0 * c / den, -8.0 / den};
+                const double qd[3] = {-4.0 * al * al * al / D3, -12.0 * al * al * be / D3,
+                                      -(12.0 * al * be * be - 3.0 * al) / D3};
+                level_split(k, quad, ns, lin, qd,
+                            (scf_need > 0.0 && scf_need < 1e-8) ? 2 : 1);
+                t = 2.0 * t / (1.0 + t * t);
+                continue;
+            }
             auto a = base<TF>();
             TF *Am = Ak[k];
             a.A0 = Z[k]; a.B0 = Z[k]; a.alpha = (TF)4.0; a.gamma = (TF)1.0; a.C = Am;
@@ -880,6 +909,68 @@ template <typename TF, typename TR> struct Sys : SysBase {
         if constexpr (FUSE_COPY) {
             convert(Ys, Ysr, 1.0);
             Lr = L;                     // response operands are current
+        }
+    }
+
+    // One level on the split path.  A_k = I + 4 Z_k^2 in FP64 (kept for the
+    // entropy) with a split copy; Y_k ~ A_k^-1 from the Chebyshev guess and
+    // ns Newton-Schulz steps, all split bf16x3 products (error ~1e-5); then
+    // Z~ = 2 Y_k Z_k (FP64 result), the FP64 residual R = 2 Z_k - A_k Z~ and
+    // Z_{k+1} = Z~ + Y_k R, whose error is that of Z~ times that of Y_k.  R
+    // is a full product: Z~ commutes with A_k only to the split products'
+    // accuracy, so R is not symmetric.  It is formed transposed,
+    // R^T = 2 Z_k - Z~ A_k, which is the row layout the split product reads.
+    TR *Asp = nullptr, *Esp = nullptr, *Ysp = nullptr, *Rsp = nullptr;
+    SplitArgs sbase() const {
+        SplitArgs a;
+        a.n = Np;
+        a.ld = Np;
+        a.pl = (long)mat();
+        return a;
+    }
+    void level_split(int k, bool quad, int ns, const double *lin, const double *qd, int nref) {
+        if constexpr (FUSE_COPY) {
+            if (!Asp) { Asp = amat<TR>(); Esp = amat<TR>(); Ysp = amat<TR>(); Rsp = amat<TR>(); }
+            TF *Am = Ak[k];
+            auto a = base<TF>();            // A_k, its split copy, the linear guess
+            a.A0 = Z[k]; a.B0 = Z[k]; a.alpha = 4.0; a.gamma = 1.0; a.C = Am;
+            a.Cs = s16(Asp); a.Cs_pl = (long)mat();
+            if (!quad) { a.Cs2 = s16(Yr[k]); a.p0 = lin[0]; a.p1 = lin[1]; }
+            run_gemm(a, true);
+            if (quad) {                     // Y = p0 I + p1 A + p2 A^2
+                SplitArgs q = sbase();
+                q.A0 = s16(Asp); q.B0 = s16(Asp); q.X = s16(Asp); q.C = s16(Yr[k]);
+                q.alpha = (float)qd[0]; q.beta = (float)qd[1]; q.gamma = (float)qd[2];
+                run_split<TR>(q, true);
+            }
+            for (int j = 0; j < ns; ++j) {
+                SplitArgs e = sbase();      // E = 2I - A Y
+                e.A0 = s16(Asp); e.B0 = s16(Yr[k]); e.alpha = -1.f; e.gamma = 2.f;
+                e.C = s16(Esp);
+                run_split<TR>(e, true);
+                SplitArgs y = sbase();      // Y <- Y E
+                y.A0 = s16(Yr[k]); y.B0 = s16(Esp); y.C = s16(Ysp);
+                run_split<TR>(y, true);
+                std::swap(Yr[k], Ysp);
+            }
+            SplitArgs z = sbase();          // Z~ = 2 Y Z_k, FP64 result
+            z.A0 = s16(Yr[k]); z.B0 = s16(Zr[k]); z.alpha = 2.f; z.Cd = Wk;
+            run_split<TR>(z, true);
+            for (int i = 0; i < nref; ++i) {
+                const bool last = i + 1 == nref;
+                auto r = base<TF>();        // R^T = 2 Z_k - Z~ A_k, split copy only
+                r.A0 = Wk; r.B0 = Am; r.alpha = -1.0; r.X = Z[k]; r.beta = 2.0;
+                r.Cs = s16(Rsp); r.Cs_pl = (long)mat();
+                run_gemm(r, false);
+                SplitArgs u = sbase();      // Z~ <- Z~ + Y R; the last one is
+                u.A0 = s16(Yr[k]);          // Z_{k+1} (FP64 and split)
+                u.B0 = s16(Rsp); u.Xd = Wk; u.beta = 1.f;
+                // in place is safe: each upper element is read and written by
+                // one thread, which also writes its mirror (never read)
+                u.Cd = last ? Z[k + 1] : Wk;
+                if (last) u.C = s16(Zr[k + 1]);
+                run_split<TR>(u, true);
+            }
         }
     }
 

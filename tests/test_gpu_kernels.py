@@ -98,7 +98,7 @@ def test_split_gemm_dual_kscale_batch(B):
     assert np.abs(out[P.MIXED_BF16X3].sum(axis=1)).max() < 1e-9
 
 
-@pytest.mark.parametrize("n", [128, 256, 384, 1024])
+@pytest.mark.parametrize("n", [128, 256, 384, 512, 1024, 2048])
 @pytest.mark.parametrize("sym", [False, True])
 def test_gemm_presplit(B, n, sym):
     """Split product on pre-split operands: C = A B^T from the bf16 hi/lo
