@@ -17,9 +17,8 @@
 // here are copied into LDS as 16-byte chunks with no conversion work, the
 // workgroup has 8 waves (four per SIMD at two workgroups per CU), and
 // the chunk order within each 64-byte LDS row is permuted by a function of
-// the row (`swz`) so that both the chunk stores (4 lanes per row) and the
-// 16-byte fragment reads (16 consecutive rows, one chunk) hit distinct
-// banks for 8- and 16-lane service groups alike.
+// the row (`swz`) so that neither the chunk stores (4 lanes per row) nor the
+// 16-byte fragment reads (16 consecutive rows, one chunk) conflict in banks.
 #pragma once
 #include "gemm.hpp"
 
@@ -39,11 +38,13 @@ struct SplitArgs {
     long ws_elems = 0;
 };
 
-// chunk permutation of LDS row r (values 0..3; a bijection on every 4 rows
-// of equal residue mod 4 and on the 4 rows of each parity in every 8)
-__device__ __forceinline__ int swz(int r) {
-    return ((r >> 2) & 1) | ((((r >> 1) ^ (r >> 3)) & 1) << 1);
-}
+// chunk permutation of LDS row r (values 0..3, rows in pairs): with it the
+// 16-byte fragment reads (16 consecutive rows, one chunk each) and the chunk
+// stores (4 lanes per row) of these kernels count no LDS bank conflicts
+// (SQ_LDS_BANK_CONFLICT = 0 at N = 4096; the permutations that also spread
+// every 4 rows of equal residue mod 4, or none at all, count ~36% of the
+// LDS-active cycles as conflicts)
+__device__ __forceinline__ int swz(int r) { return (r >> 1) & 3; }
 
 // Write the 16 x 16 accumulator block whose first row / column are
 // (i0 + r0, j0 + c0), from lane (fr, fc).  With SYM only elements on or
@@ -241,13 +242,17 @@ __global__ __launch_bounds__(BS_T) void gemm_bs_fixup_kernel(SplitArgs p, int nt
 }
 
 // ---------------------------------------------------------------------------
-// Wide variant: 256 x 128 workgroup tile, 16 waves (4 x 4 of 64 x 32), one
-// workgroup per CU (96 KB of LDS).  The k-tile bytes per flop drop by a
-// quarter against two 128 x 128 tiles, which is what bounds the split path
-// (n % 256 == 0).  Tiles of a symmetric product: in 256-row block bi, the
-// 128-column blocks bj >= 2 bi.
+// Wide variant: 256 x 128 workgroup tile, one workgroup of 8 waves per CU
+// (two per SIMD; 96 KB of LDS), used when n % 256 == 0.  Waves in 4 rows x
+// 2 columns of 64 x 64 (4 x 4 accumulator blocks, 48 MFMAs per 32-wide
+// k-tile).  The k loop is software-pipelined three deep: while a wave runs
+// the MFMAs of k-tile t from registers, it reads the fragments of t + 1
+// from LDS into a second register set, stores t + 2 (fetched from global
+// memory one iteration earlier) into the LDS buffer t has vacated and
+// issues the global loads of t + 3, with one barrier per k-tile.  Tiles of a
+// symmetric product: in 256-row block bi, the 128-column blocks bj >= 2 bi.
 // ---------------------------------------------------------------------------
-constexpr int BW_T = 1024;
+constexpr int BW_NTH = 512;
 constexpr int BW_M = 256;
 constexpr int BW_TILE = BW_M * GT;     // elements of one tile
 
@@ -291,10 +296,16 @@ __device__ __forceinline__ void tilew_of(int u, int nbj, int &bi, int &bj) {
     }
 }
 
+struct BwFrag {
+    bf16x8 ah[4], al[4], bh[4], bl[4];
+};
+
 template <bool SYM>
-__global__ __launch_bounds__(BW_T, 1) void gemm_bw_kernel(SplitArgs p, int ntiles, int nfull,
-                                                       int nsplit, int per_xcd) {
+__global__ __launch_bounds__(BW_NTH, 1) void gemm_bw_kernel(SplitArgs p, int ntiles, int nfull,
+                                                         int nsplit, int per_xcd) {
     using acc_t = f32x4;
+    constexpr int NTH = BW_NTH;
+    constexpr int NA = 2048 / NTH, NB = 1024 / NTH;   // 16-byte chunks per thread
     __shared__ __attribute__((aligned(16))) u32x4 As[2][2][BW_M][4];
     __shared__ __attribute__((aligned(16))) u32x4 Bs[2][2][GT][4];
 
@@ -325,115 +336,164 @@ __global__ __launch_bounds__(BW_T, 1) void gemm_bw_kernel(SplitArgs p, int ntile
     const long pl = p.pl;
     const int i0 = bi * BW_M, j0 = bj * GT;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int wr = wid >> 2, wc = wid & 3;
+    const int wr = wid >> 1, wc = wid & 1;
+    const int fr = lane >> 4, fc = lane & 15;
 
-    acc_t acc[4][2];
+    acc_t acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) acc[a][c] = acc_t{0, 0, 0, 0};
+        for (int c = 0; c < 4; ++c) acc[a][c] = acc_t{0, 0, 0, 0};
 
     const int nk1 = p.n / B3K;
     const int nktot = A1 ? 2 * nk1 : nk1;
     const int kt0 = (int)((long)nktot * split / ns);
     const int kt1 = (int)((long)nktot * (split + 1) / ns);
 
-    // A: 2 planes x 256 rows x 4 chunks (2 per thread); B: 2 x 128 x 4 (1)
-    u32x4 ra[2], rb;
+    // A: 2 planes x 256 rows x 4 chunks; B: 2 x 128 x 4 (chunk idx = tid + NTH v)
+    u32x4 ra[NA], rb[NB];
     auto gload = [&](int kt) {
         const bool second = kt >= nk1;
         const uint16_t *Ap = second ? A1 : A0;
         const uint16_t *Bp = second ? B1 : B0;
         const int kb = (second ? kt - nk1 : kt) * B3K;
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
-            const int idx = tid + BW_T * v;
+        for (int v = 0; v < NA; ++v) {
+            const int idx = tid + NTH * v;
             const int pln = idx >> 10, row = (idx >> 2) & (BW_M - 1), ch = idx & 3;
             ra[v] = *reinterpret_cast<const u32x4 *>(Ap + pln * pl + kb + 8 * ch +
                                                      (long)(i0 + row) * ld);
         }
-        const int pln = tid >> 9, row = (tid >> 2) & (GT - 1), ch = tid & 3;
-        rb = *reinterpret_cast<const u32x4 *>(Bp + pln * pl + kb + 8 * ch + (long)(j0 + row) * ld);
+#pragma unroll
+        for (int v = 0; v < NB; ++v) {
+            const int idx = tid + NTH * v;
+            const int pln = idx >> 9, row = (idx >> 2) & (GT - 1), ch = idx & 3;
+            rb[v] = *reinterpret_cast<const u32x4 *>(Bp + pln * pl + kb + 8 * ch +
+                                                     (long)(j0 + row) * ld);
+        }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
-            const int idx = tid + BW_T * v;
+        for (int v = 0; v < NA; ++v) {
+            const int idx = tid + NTH * v;
             const int pln = idx >> 10, row = (idx >> 2) & (BW_M - 1), ch = idx & 3;
             As[buf][pln][row][ch ^ swz(row)] = ra[v];
         }
-        const int pln = tid >> 9, row = (tid >> 2) & (GT - 1), ch = tid & 3;
-        Bs[buf][pln][row][ch ^ swz(row)] = rb;
+#pragma unroll
+        for (int v = 0; v < NB; ++v) {
+            const int idx = tid + NTH * v;
+            const int pln = idx >> 9, row = (idx >> 2) & (GT - 1), ch = idx & 3;
+            Bs[buf][pln][row][ch ^ swz(row)] = rb[v];
+        }
     };
-
-    gload(kt0);
-    sstore(0);
-    __syncthreads();
-    const int fr = lane >> 4, fc = lane & 15;
-    for (int kt = kt0; kt < kt1; ++kt) {
-        const int buf = (kt - kt0) & 1;
-        if (kt + 1 < kt1) gload(kt + 1);
-        bf16x8 ah[4], al[4], bh[2], bl[2];
+    auto fread = [&](int buf, BwFrag &f) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = wr * 64 + q * 16 + fc, c = fr ^ swz(r);
-            ah[q] = __builtin_bit_cast(bf16x8, As[buf][0][r][c]);
-            al[q] = __builtin_bit_cast(bf16x8, As[buf][1][r][c]);
+            f.ah[q] = __builtin_bit_cast(bf16x8, As[buf][0][r][c]);
+            f.al[q] = __builtin_bit_cast(bf16x8, As[buf][1][r][c]);
         }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int r = wc * 32 + q * 16 + fc, c = fr ^ swz(r);
-            bh[q] = __builtin_bit_cast(bf16x8, Bs[buf][0][r][c]);
-            bl[q] = __builtin_bit_cast(bf16x8, Bs[buf][1][r][c]);
+        for (int q = 0; q < 4; ++q) {
+            const int r = wc * 64 + q * 16 + fc, c = fr ^ swz(r);
+            f.bh[q] = __builtin_bit_cast(bf16x8, Bs[buf][0][r][c]);
+            f.bl[q] = __builtin_bit_cast(bf16x8, Bs[buf][1][r][c]);
         }
+    };
+    // one of the three split terms (lo.hi, hi.lo, hi.hi) over the 4 x 4
+    // blocks: the three products into one accumulator are 16 instructions
+    // apart
+    auto mfma = [&](const bf16x8 (&a)[4], const bf16x8 (&bb)[4]) {
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-            for (int y = 0; y < 2; ++y) {
-                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], bh[y], acc[x][y], 0, 0, 0);
-                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bl[y], acc[x][y], 0, 0, 0);
-                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
-            }
-        if (kt + 1 < kt1) sstore(buf ^ 1);
+            for (int y = 0; y < 4; ++y)
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], bb[y], acc[x][y], 0, 0, 0);
+    };
+    // k-tile t lives in LDS buffer (t - kt0) & 1.  One step: fragments of t
+    // in `cur`; t + 1 stored and visible; t + 2 in flight in ra / rb.  The
+    // step is branch-free so that one scheduling region holds it: near the
+    // end of the range the fragment read and LDS store handle stale data that
+    // is never used, and the global load repeats the last k-tile.  The LDS
+    // instructions are spread between the MFMAs (one read or store per two
+    // MFMAs): issued in a burst after the barrier they fill the LDS queue
+    // and hold up the MFMAs behind them.
+    auto step = [&](int kt, const BwFrag &cur, BwFrag &nxt) {
+        const int buf = (kt - kt0) & 1;
+        fread(buf ^ 1, nxt);
+        mfma(cur.al, cur.bh);
+        mfma(cur.ah, cur.bl);
+        sstore(buf);                        // every wave read t's fragments before the last barrier
+        gload(min(kt + 3, kt1 - 1));
+        mfma(cur.ah, cur.bh);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // MFMA
+        }
+#pragma unroll
+        for (int i = 0; i < NA + NB; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // LDS write
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // global read
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // MFMA
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 48 - 32 - 2 * (NA + NB), 0);
+        __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
+    };
+
+    BwFrag f0, f1;
+    gload(kt0);
+    sstore(0);
+    if (kt0 + 1 < kt1) gload(kt0 + 1);
+    __syncthreads();
+    fread(0, f0);
+    if (kt0 + 1 < kt1) sstore(1);
+    if (kt0 + 2 < kt1) gload(kt0 + 2);
+    __syncthreads();
+    for (int kt = kt0; kt < kt1; kt += 2) {
+        step(kt, f0, f1);
+        if (kt + 1 < kt1) step(kt + 1, f1, f0);
     }
 
     if (part) {
-        // block g = 2x + y of thread tid at [(g * 1024 + tid) * 4]
+        // block g = 4 x + y of thread tid at [(g * NTH + tid) * 4]
         acc_t *wp = reinterpret_cast<acc_t *>(p.ws + ((long)bz * ntail * nsplit + w) * BW_TILE) + tid;
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-            for (int y = 0; y < 2; ++y) wp[(x * 2 + y) * BW_T] = acc[x][y];
+            for (int y = 0; y < 4; ++y) wp[(x * 4 + y) * NTH] = acc[x][y];
         return;
     }
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
-            epilogue_split_at<SYM>(p, bz, i0, j0, wr * 64 + x * 16, wc * 32 + y * 16, fr, fc,
+        for (int y = 0; y < 4; ++y)
+            epilogue_split_at<SYM>(p, bz, i0, j0, wr * 64 + x * 16, wc * 64 + y * 16, fr, fc,
                                    acc[x][y]);
 }
 
-// One 256-thread workgroup per (tail tile, block g, quarter of the product's
+// One 256-thread workgroup per (tail tile, block g, half of the product's
 // threads): sums the vectors its counterparts wrote in every partial.
+// grid.y = 16 blocks x 2 halves.
 template <bool SYM>
 __global__ __launch_bounds__(256) void gemm_bw_fixup_kernel(SplitArgs p, int ntiles, int nfull,
                                                             int nsplit) {
+    constexpr int NTH = BW_NTH;
     const int ntail = ntiles - nfull;
     const int u = nfull + blockIdx.x;
-    const int g = blockIdx.y >> 2, x = g >> 1, y = g & 1;
+    const int g = blockIdx.y >> 1, x = g >> 2, y = g & 3;
     const long bz = blockIdx.z;
     int bi, bj;
     tilew_of<SYM>(u, p.n / GT, bi, bj);
-    const int tid = (blockIdx.y & 3) * 256 + threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int wr = wid >> 2, wc = wid & 3, fr = lane >> 4, fc = lane & 15;
+    const int tid = (blockIdx.y & 1) * 256 + threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wr = wid >> 1, wc = wid & 1, fr = lane >> 4, fc = lane & 15;
     f32x4 acc = f32x4{0, 0, 0, 0};
     const f32x4 *wp = reinterpret_cast<const f32x4 *>(
                           p.ws + ((long)bz * ntail * nsplit + (long)blockIdx.x * nsplit) *
-                                     BW_TILE) + g * BW_T + tid;
+                                     BW_TILE) + g * NTH + tid;
     for (int s = 0; s < nsplit; ++s) acc += wp[(long)s * (BW_TILE / 4)];
-    epilogue_split_at<SYM>(p, bz, bi * BW_M, bj * GT, wr * 64 + x * 16, wc * 32 + y * 16, fr, fc,
+    epilogue_split_at<SYM>(p, bz, bi * BW_M, bj * GT, wr * 64 + x * 16, wc * 64 + y * 16, fr, fc,
                            acc);
 }
 
@@ -462,17 +522,17 @@ inline void gemm_split(const SplitArgs &a, bool sym, hipStream_t st) {
         const int per = (tail_units + NXCD - 1) / NXCD;
         dim3 grid(nfull_pad + per * NXCD, 1, a.batch);
         if (sym)
-            hipLaunchKernelGGL((gemm_bw_kernel<true>), grid, dim3(BW_T), 0, st, a, ntiles,
-                               s.nfull, s.nsplit, per);
+            hipLaunchKernelGGL((gemm_bw_kernel<true>), grid, dim3(BW_NTH), 0, st, a,
+                               ntiles, s.nfull, s.nsplit, per);
         else
-            hipLaunchKernelGGL((gemm_bw_kernel<false>), grid, dim3(BW_T), 0, st, a, ntiles,
-                               s.nfull, s.nsplit, per);
+            hipLaunchKernelGGL((gemm_bw_kernel<false>), grid, dim3(BW_NTH), 0, st, a,
+                               ntiles, s.nfull, s.nsplit, per);
         XL_LAUNCH_CHECK();
         if (s.nfull < ntiles) {
-            dim3 g2(ntiles - s.nfull, 32, a.batch);   // 8 blocks x 4 thread quarters
+            dim3 g2(ntiles - s.nfull, 32, a.batch);   // 16 blocks x 2 halves
             if (sym)
-                hipLaunchKernelGGL((gemm_bw_fixup_kernel<true>), g2, dim3(256), 0, st, a, ntiles,
-                                   s.nfull, s.nsplit);
+                hipLaunchKernelGGL((gemm_bw_fixup_kernel<true>), g2, dim3(256), 0, st, a,
+                                   ntiles, s.nfull, s.nsplit);
             else
                 hipLaunchKernelGGL((gemm_bw_fixup_kernel<false>), g2, dim3(256), 0, st, a,
                                    ntiles, s.nfull, s.nsplit);
