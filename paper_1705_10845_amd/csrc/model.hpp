@@ -355,11 +355,14 @@ __global__ __launch_bounds__(256) void seed_resp_kernel(int n, int ld, const T *
     Zp[b * sG + o] = (T)val;
 }
 
-// Split-storage form of seed_resp_kernel: same inputs (FP32), Z'_0 written
-// as a split bf16 matrix (planes pl elements apart, batch stride 2 sG).
-__global__ __launch_bounds__(256) void seed_resp_split_kernel(int n, int ld, const float *G,
-                                                              const float *H2, const float *H13,
-                                                              const float *Y2, const float *Y4,
+// Split-storage form of seed_resp_kernel: G, H2, H13 and Y^4 are split
+// matrices (G, H2, H13 with batch stride 2 sG in bf16 elements), Y^2 FP32;
+// Z'_0 written as a split matrix (planes pl elements apart, batch stride
+// 2 sG).
+__global__ __launch_bounds__(256) void seed_resp_split_kernel(int n, int ld, const uint16_t *G,
+                                                              const uint16_t *H2,
+                                                              const uint16_t *H13,
+                                                              const float *Y2, const uint16_t *Y4,
                                                               const double *u, long su, long sG,
                                                               uint16_t *Zp, long pl) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -370,12 +373,27 @@ __global__ __launch_bounds__(256) void seed_resp_split_kernel(int n, int ld, con
     double val = 0.0;
     if (i < n && j < n) {
         const double ui = u[b * su + i], uj = u[b * su + j];
-        val = -(1.0 / 6.0) * ((double)G[b * sG + o] + (ui + uj) * (double)Y2[o]) +
-              (1.0 / 15.0) * ((double)H13[b * sG + o] + (double)H2[b * sG + o] +
-                              (ui + uj) * (double)Y4[o]);
+        const long ob = b * 2 * sG;
+        val = -(1.0 / 6.0) * ((double)get_split(G + ob, pl, o) + (ui + uj) * (double)Y2[o]) +
+              (1.0 / 15.0) * ((double)get_split(H13 + ob, pl, o) +
+                              (double)get_split(H2 + ob, pl, o) +
+                              (ui + uj) * (double)get_split(Y4, pl, o));
         if (i == j) val += 0.5 * ui;
     }
     put_split(Zp + b * 2 * sG, pl, o, (float)val);
+}
+
+// Rows of Y D for D = diag(u_b), as split matrices: dst_b[j][k] =
+// split(u_b[k] Y[j][k]) for the FP32 matrix Y (ld x ld, whole padded array;
+// u_b zero past the orbitals), batch stride sd bf16 elements.
+__global__ __launch_bounds__(256) void colscale_split_kernel(int ld, const float *Y,
+                                                             const double *u, long su,
+                                                             uint16_t *dst, long pl, long sd) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long b = blockIdx.y;
+    if (t >= (long)ld * ld) return;
+    const int k = (int)(t % ld);
+    put_split(dst + b * sd, pl, t, (float)(u[b * su + k] * (double)Y[t]));
 }
 
 // diag(Y T)_i = sum_l Y[i][l] T^T[i][l] for split Y and the stored transpose

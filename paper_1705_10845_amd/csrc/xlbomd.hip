@@ -720,10 +720,15 @@ template <typename TF, typename TR> struct Sys : SysBase {
         if (resp_split) {
             Xb = dalloc<TR>(mat() * nb);
             mem.ptrs.push_back(Xb);
+            for (auto &q : Sd) {
+                q = dalloc<TR>(mat() * nb);
+                mem.ptrs.push_back(q);
+            }
         }
         bcap = nb;
     }
     TR *Xb = nullptr;                 // fourth response buffer (split path)
+    TR *Sd[3] = {};                   // rows of Y D, Y^2 D, Y^3 D (split path)
     // split bf16 view of a TR matrix buffer (planes mat() elements apart)
     uint16_t *s16(TR *p) const { return reinterpret_cast<uint16_t *>(p); }
     // response operand copy written by an expansion product: split planes
@@ -783,7 +788,10 @@ template <typename TF, typename TR> struct Sys : SysBase {
         while ((int)Zr.size() < L + 1) Zr.push_back(amat<TR>());
         while ((int)Yr.size() < L) Yr.push_back(amat<TR>());
         if (!Ysr) { Ysr = amat<TR>(); Y2r = amat<TR>(); Y3r = amat<TR>(); }
+        if (resp_split && !Sy[0])
+            for (auto &q : Sy) q = amat<TR>();
     }
+    TR *Sy[3] = {};                   // split Y, Y^2, Y^3 (split path)
 
     void foe(double mu0) override {
         const double xmax = beta * std::max(std::fabs(elo - mu0), std::fabs(ehi - mu0)) * 1.02 + 1e-12;
@@ -804,11 +812,17 @@ template <typename TF, typename TR> struct Sys : SysBase {
         {   // Y2 = Y Y ; Y3 = Y Y2 ; Z0 = Y/2 - Y3/6 + Y3 Y2 / 15 (= tanh(Y)/2 to O(Y^7))
             auto a = base<TF>();
             a.A0 = Ys; a.B0 = Ys; a.C = Y2;
-            if constexpr (FUSE_COPY) a.Cf = Y2r;
+            if constexpr (FUSE_COPY) {
+                a.Cf = Y2r;
+                if (resp_split) { a.Cs = s16(Sy[1]); a.Cs_pl = (long)mat(); }
+            }
             run_gemm(a, true);
             a = base<TF>();
             a.A0 = Ys; a.B0 = Y2; a.C = Y3;
-            if constexpr (FUSE_COPY) a.Cf = Y3r;
+            if constexpr (FUSE_COPY) {
+                a.Cf = Y3r;
+                if (resp_split) { a.Cs = s16(Sy[2]); a.Cs_pl = (long)mat(); }
+            }
             run_gemm(a, true);
             a = base<TF>();
             a.A0 = Y3; a.B0 = Y2; a.alpha = (TF)(1.0 / 15.0);
@@ -908,6 +922,12 @@ template <typename TF, typename TR> struct Sys : SysBase {
         XL_LAUNCH_CHECK();
         if constexpr (FUSE_COPY) {
             convert(Ys, Ysr, 1.0);
+            if (resp_split) {
+                hipLaunchKernelGGL(convert_split_kernel, dim3(ceil_div((long)mat(), 256)),
+                                   dim3(256), 0, st, (long)mat(), (const double *)Ys, 1.0,
+                                   s16(Sy[0]), (long)mat());
+                XL_LAUNCH_CHECK();
+            }
             Lr = L;                     // response operands are current
         }
     }
@@ -1013,11 +1033,17 @@ template <typename TF, typename TR> struct Sys : SysBase {
             }
             Lr = L;
         }
-        if (Y4_for != expansion_id) {   // Y^4 for the seed response, in TR
-            if (!Y4r) Y4r = amat<TR>();
-            auto a = base<TR>();
-            a.A0 = Y2r; a.B0 = Y2r; a.C = Y4r; a.split3 = resp_split;
-            run_gemm(a, true);
+        if (Y4_for != expansion_id) {   // Y^4 for the seed response, in TR (split when
+            if (!Y4r) Y4r = amat<TR>(); // the responses are)
+            if (resp_split) {
+                SplitArgs a = sbase();
+                a.A0 = s16(Sy[1]); a.B0 = s16(Sy[1]); a.C = s16(Y4r);
+                run_split<TR>(a, true);
+            } else {
+                auto a = base<TR>();
+                a.A0 = Y2r; a.B0 = Y2r; a.C = Y4r;
+                run_gemm(a, true);
+            }
             Y4_for = expansion_id;
         }
     }
@@ -1045,23 +1071,32 @@ template <typename TF, typename TR> struct Sys : SysBase {
         hipLaunchKernelGGL(expand_orbital_kernel, dim3(ceil_div((long)N * nb, 256)), dim3(256), 0,
                            st, nat, no, nb, sc, hb, (long)Np, ub);
         XL_LAUNCH_CHECK();
-        {   // G = Y D Y, H2 = Y2 D Y2, H13 = Y D Y3 + Y3 D Y (FP32 storage), then Z'_0
-            auto a = base<TR>();
-            a.batch = nb; a.A0 = Ysr; a.B0 = Ysr; a.kscale = ub; a.sK = Np;
-            a.split3 = true;
-            a.C = Tb; a.sC = sm;
-            run_gemm(a, true);
-            a.A0 = Y2r; a.B0 = Y2r; a.C = Ap;
-            run_gemm(a, true);
-            a.A0 = Ysr; a.B0 = Y3r; a.A1 = Y3r; a.B1 = Ysr; a.kscale_both = true; a.C = Xb;
-            run_gemm(a, true);
+        const long s2 = 2 * sm;            // batch stride of split buffers
+        {   // rows of Y D, Y^2 D, Y^3 D (D = diag(u), split), then on pre-split
+            // operands G = Y D Y, H2 = Y2 D Y2, H13 = Y D Y3 + Y3 D Y, then Z'_0
+            const dim3 cg(ceil_div((long)mat(), 256), nb);
+            hipLaunchKernelGGL(colscale_split_kernel, cg, dim3(256), 0, st, Np,
+                               (const float *)Ysr, ub, (long)Np, s16(Sd[0]), sm, s2);
+            hipLaunchKernelGGL(colscale_split_kernel, cg, dim3(256), 0, st, Np,
+                               (const float *)Y2r, ub, (long)Np, s16(Sd[1]), sm, s2);
+            hipLaunchKernelGGL(colscale_split_kernel, cg, dim3(256), 0, st, Np,
+                               (const float *)Y3r, ub, (long)Np, s16(Sd[2]), sm, s2);
+            XL_LAUNCH_CHECK();
+            SplitArgs a = sbase();
+            a.batch = nb; a.A0 = s16(Sy[0]); a.B0 = s16(Sd[0]); a.sB0 = s2;
+            a.C = s16(Tb); a.sC = s2;
+            run_split<TR>(a, true);
+            a.A0 = s16(Sy[1]); a.B0 = s16(Sd[1]); a.C = s16(Ap);
+            run_split<TR>(a, true);
+            a.A0 = s16(Sy[0]); a.B0 = s16(Sd[2]); a.A1 = s16(Sy[2]); a.B1 = s16(Sd[0]); a.sB1 = s2;
+            a.C = s16(Xb);
+            run_split<TR>(a, true);
             hipLaunchKernelGGL(seed_resp_split_kernel, dim3(ceil_div(Np, 256), Np, nb), dim3(256),
-                               0, st, N, Np, (const float *)Tb, (const float *)Ap,
-                               (const float *)Xb, (const float *)Y2r, (const float *)Y4r, ub,
-                               (long)Np, sm, s16(Zp), sm);
+                               0, st, N, Np, (const uint16_t *)s16(Tb), (const uint16_t *)s16(Ap),
+                               (const uint16_t *)s16(Xb), (const float *)Y2r,
+                               (const uint16_t *)s16(Y4r), ub, (long)Np, sm, s16(Zp), sm);
             XL_LAUNCH_CHECK();
         }
-        const long s2 = 2 * sm;            // batch stride of split buffers
         for (int k = 0; k < L; ++k) {
             SplitArgs a;                    // A' = 4 (Z Z' + Z' Z)
             a.n = Np; a.ld = Np; a.pl = sm; a.batch = nb;
