@@ -309,9 +309,11 @@ __global__ __launch_bounds__(64 * NW, 2) void gemm_tn_kernel(GemmArgs<T> p, int 
     sstore(0);
     __syncthreads();
     const int fr = lane >> 4, fc = lane & 15;
+    // branch-free k step (one scheduling region): at the last k-tile the
+    // global load repeats it and the LDS store fills the idle buffer
     for (int kt = kt0; kt < kt1; ++kt) {
         const int buf = (kt - kt0) & 1;
-        if (kt + 1 < kt1) gload(kt + 1);
+        gload(min(kt + 1, kt1 - 1));
 #pragma unroll
         for (int s = 0; s < BK / 4; ++s) {
             T a[4], b[YB];
@@ -324,7 +326,19 @@ __global__ __launch_bounds__(64 * NW, 2) void gemm_tn_kernel(GemmArgs<T> p, int 
 #pragma unroll
                 for (int y = 0; y < YB; ++y) acc[x][y] = M::mma(a[x], b[y], acc[x][y]);
         }
-        if (kt + 1 < kt1) sstore(buf ^ 1);
+        sstore(buf ^ 1);
+        if constexpr (sizeof(T) == 8) {
+            // FP64: each sub-step's LDS reads ahead of its MFMAs, the global
+            // loads after the first, the LDS stores last
+#pragma unroll
+            for (int s = 0; s < BK / 4; ++s) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 4 + YB, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 4 * YB, 0);
+                if (s == 0) __builtin_amdgcn_sched_group_barrier(0x020, 2 * NV, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x200, 2 * NV, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
         __syncthreads();
     }
 
