@@ -6,12 +6,13 @@
 // with hi = bf16(x), lo = bf16(x - hi) of the FP32 value.
 //
 // Product: C[i][j] = alpha sum_s sum_k A_s[i][k] B_s[j][k] + beta X[i][j]
-// + gamma delta_ij, i.e. both operands are read as rows with k contiguous
-// ("NT").  Every operand of the response recursion is symmetric, or is
-// stored transposed by the product that makes it, so this is the matrix
-// product the recursion needs.  C and X are split matrices too; X may
-// instead be an FP64 matrix (Xd) and the result may go (also) to an FP64
-// matrix Cd, with the epilogue sum taken in FP64.
+// (+ beta2 X2[i][j]) + gamma delta_ij, i.e. both operands are read as rows
+// with k contiguous ("NT").  Every operand of the response recursion is
+// symmetric, or is stored transposed by the product that makes it, so this
+// is the matrix product the recursion needs.  C and X are split matrices
+// too; X may instead be an FP64 matrix (Xd), X2 is FP64, and the result may
+// go (also) to an FP64 matrix Cd.  The epilogue sum and its coefficients
+// are FP64.
 //
 // Against gemm_bf3_kernel (FP32 operands split while staging) the k-tiles
 // here are copied into LDS as 16-byte chunks with no conversion work, the
@@ -29,10 +30,10 @@ struct SplitArgs {
     long pl = 0;                                  // plane offset (elements)
     const uint16_t *A0 = nullptr, *B0 = nullptr, *A1 = nullptr, *B1 = nullptr;
     const uint16_t *X = nullptr;
-    const double *Xd = nullptr;                   // FP64 X (instead of X)
+    const double *Xd = nullptr, *Xd2 = nullptr;   // FP64 X (instead of X), second term
     uint16_t *C = nullptr;
     double *Cd = nullptr;                         // FP64 result (C may be null)
-    float alpha = 1.f, beta = 0.f, gamma = 0.f;
+    double alpha = 1.0, beta = 0.0, beta2 = 0.0, gamma = 0.0;
     long sA0 = 0, sB0 = 0, sA1 = 0, sB1 = 0, sX = 0, sC = 0;   // batch strides (elements)
     float *ws = nullptr;                          // split-k partial tiles (FP32)
     long ws_elems = 0;
@@ -59,16 +60,18 @@ __device__ __forceinline__ void epilogue_split_at(const SplitArgs &p, long bz, i
     double *Cd = p.Cd ? p.Cd + bz * p.sC : nullptr;
     const uint16_t *X = p.X ? p.X + bz * p.sX : nullptr;
     const double *Xd = p.Xd ? p.Xd + bz * p.sX : nullptr;
+    const double *Xd2 = p.Xd2 ? p.Xd2 + bz * p.sX : nullptr;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int row = i0 + r0 + 4 * fr + r;
         const int col = j0 + c0 + fc;
         const long o = (long)row * ld + col;
         if (SYM && row > col) continue;
-        double val = (double)(p.alpha * acc[r]);
-        if (X) val += (double)(p.beta * get_split(X, p.pl, o));
-        if (Xd) val += (double)p.beta * Xd[o];
-        if (row == col) val += (double)p.gamma;
+        double val = p.alpha * (double)acc[r];
+        if (X) val += p.beta * (double)get_split(X, p.pl, o);
+        if (Xd) val += p.beta * Xd[o];
+        if (Xd2) val += p.beta2 * Xd2[o];
+        if (row == col) val += p.gamma;
         const long ot = (long)col * ld + row;
         if (C) {
             put_split(C, p.pl, o, (float)val);

@@ -355,6 +355,51 @@ __global__ __launch_bounds__(256) void seed_resp_kernel(int n, int ld, const T *
     Zp[b * sG + o] = (T)val;
 }
 
+// ---- spectral bounds by Lanczos ----
+// w = A v for the leading n x n block of a dense row-major matrix (leading
+// dimension ld), one workgroup per row.
+template <typename T>
+__global__ __launch_bounds__(256) void matvec_kernel(int n, int ld, const T *A, const double *v,
+                                                     double *w) {
+    __shared__ double sh[16];
+    const int i = blockIdx.x;
+    const T *a = A + (long)i * ld;
+    double s = 0.0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) s += (double)a[j] * v[j];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) w[i] = s;
+}
+
+// Lanczos step j on length-n vectors (one workgroup), w = A v on entry:
+// alpha_j = w.v, w <- w - alpha_j v - beta_{j-1} v_prev, beta_j = |w|,
+// (v_prev, v) <- (v, w / beta_j).  ab[j] = alpha_j, ab[m + j] = beta_j; on a
+// breakdown (beta_j = 0) v is left zero and the host ignores the bounds.
+__global__ __launch_bounds__(1024) void lanczos_step_kernel(int n, int j, int m, double *v,
+                                                            double *vp, double *w, double *ab) {
+    __shared__ double sh[16];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) a += w[i] * v[i];
+    a = block_sum(a, sh);
+    const double bprev = j > 0 ? ab[m + j - 1] : 0.0;
+    double b2 = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double x = w[i] - a * v[i] - (j > 0 ? bprev * vp[i] : 0.0);
+        w[i] = x;
+        b2 += x * x;
+    }
+    b2 = block_sum(b2, sh);
+    const double b = sqrt(b2);
+    if (threadIdx.x == 0) {
+        ab[j] = a;
+        ab[m + j] = b;
+    }
+    const double inv = b > 0.0 ? 1.0 / b : 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        vp[i] = v[i];
+        v[i] = w[i] * inv;
+    }
+}
+
 // Split-storage form of seed_resp_kernel: G, H2, H13 and Y^4 are split
 // matrices (G, H2, H13 with batch stride 2 sG in bf16 elements), Y^2 FP32;
 // Z'_0 written as a split matrix (planes pl elements apart, batch stride

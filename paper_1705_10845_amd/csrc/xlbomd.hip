@@ -106,6 +106,37 @@ double foe_scalar(double x, int L) {
     return 0.5 * (1.0 - t);
 }
 
+// Extreme eigenvalues of the symmetric tridiagonal matrix with diagonal
+// a[0..m) and off-diagonal b[0..m-1), by Sturm-count bisection.
+void tridiag_extremes(const double *a, const double *b, int m, double &lo, double &hi) {
+    double gl = 1e300, gh = -1e300;
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+        gl = std::min(gl, a[i] - r);
+        gh = std::max(gh, a[i] + r);
+    }
+    auto below = [&](double x) {    // number of eigenvalues < x
+        int c = 0;
+        double q = 1.0;
+        for (int i = 0; i < m; ++i) {
+            q = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / q : 0.0);
+            if (q == 0.0) q = -1e-300;
+            if (q < 0.0) ++c;
+        }
+        return c;
+    };
+    auto kth = [&](int k) {         // k-th smallest eigenvalue (0-based)
+        double l = gl, h = gh;
+        for (int it = 0; it < 200 && h - l > 1e-13 * (std::fabs(l) + std::fabs(h) + 1e-300); ++it) {
+            const double x = 0.5 * (l + h);
+            if (below(x) > k) h = x; else l = x;
+        }
+        return 0.5 * (l + h);
+    };
+    lo = kth(0);
+    hi = kth(m - 1);
+}
+
 // Smallest L whose expansion keeps |y| <= 1 (where the quintic seed is
 // increasing and below 1) and stays within `tol` of the Fermi function on
 // [-xmax, xmax].
@@ -235,6 +266,7 @@ struct SysBase {
         A(hist, (size_t)K * nat); A(kr, nat); A(q, nat); A(r, nat); A(ncur, nat);
         A(vpot, nat); A(glo, N); A(ghi, N); A(g, N); A(epart, 4 * nat);
         A(scal, 64); A(cvec, 8);
+        A(lz_v, N); A(lz_vp, N); A(lz_w, N); A(lz_v0, N); A(lz_ab, 2 * LZ_M);
         mcap = std::max(1, std::min(d.kernel_rank, 16));
         A(V, (size_t)mcap * nat); A(W, (size_t)mcap * nat); A(Vprev, (size_t)mcap * nat);
         A(vtmp, nat); A(vin, (size_t)mcap * nat); A(qp, (size_t)mcap * nat); A(hb, (size_t)mcap * nat);
@@ -257,6 +289,19 @@ struct SysBase {
         up(hop, d.hop_block, no * no);
         up(U, d.hubbard_u, nat);
         XL_HIP(hipMemsetAsync(ub, 0, (size_t)mcap * Np * sizeof(double), st));
+        {   // fixed pseudo-random Lanczos start vector (xorshift64), unit norm
+            std::vector<double> v0(N);
+            unsigned long long x = 0x9e3779b97f4a7c15ull;
+            double nn = 0.0;
+            for (int i = 0; i < N; ++i) {
+                x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+                v0[i] = (double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+                nn += v0[i] * v0[i];
+            }
+            for (auto &e : v0) e /= std::sqrt(nn);
+            up(lz_v0, v0.data(), N);
+            sync();
+        }
         const DampRow &row = kDamp[d.kmax - 5];
         up(cvec, row.c, row.nc);
         sync();   // host arrays may be released after the call
@@ -274,6 +319,7 @@ struct SysBase {
 
     // ---- precision-dependent parts ----
     virtual void alloc_matrices(int Lcap) = 0;
+    virtual void lanczos() = 0;             // LZ_M steps on H into lz_ab (device)
     virtual void foe(double mu0) = 0;       // expansion at mu0 -> Z, Y, g, dmu
     virtual void finish_density() = 0;      // D_c and charges
     virtual void responses(int nb, const double *v, double *qout, double *wout) = 0;
@@ -288,6 +334,28 @@ struct SysBase {
         XL_LAUNCH_CHECK();
         hipLaunchKernelGGL(minmax_kernel, dim3(1), dim3(1024), 0, st, N, glo, ghi, scal + 8);
         XL_LAUNCH_CHECK();
+    }
+
+    // Spectral interval of H: Gershgorin, tightened by LZ_M Lanczos steps
+    // from a fixed random vector.  Each side becomes the extreme Ritz value
+    // widened by the last Lanczos coefficient beta_m (the norm of the
+    // residual vector; the extreme Ritz values converge from inside), and is
+    // kept only when tighter than Gershgorin.  On a breakdown or a
+    // non-finite coefficient Gershgorin stays.  (Gershgorin overestimates the
+    // half-width about twofold on dense 3-D lattices; the level count of the
+    // expansion follows it.)
+    static constexpr int LZ_M = 12;
+    double *lz_v = nullptr, *lz_vp = nullptr, *lz_w = nullptr, *lz_v0 = nullptr, *lz_ab = nullptr;
+    void spectral_tighten() {
+        const double *a = hscal + 16, *b = hscal + 16 + LZ_M;
+        for (int j = 0; j < LZ_M; ++j)
+            if (!std::isfinite(a[j]) || !std::isfinite(b[j]) || !(b[j] > 1e-12 * (std::fabs(ehi) + std::fabs(elo))))
+                return;
+        double tlo, thi;
+        tridiag_extremes(a, b, LZ_M, tlo, thi);
+        const double bm = b[LZ_M - 1];
+        elo = std::max(elo, tlo - bm);
+        ehi = std::min(ehi, thi + bm);
     }
 
     double initial_mu() {
@@ -318,10 +386,14 @@ struct SysBase {
                            0, st, md, 1, ncur, vpot);
         XL_LAUNCH_CHECK();
         gershgorin();
+        lanczos();
         XL_HIP(hipMemcpyAsync(hscal, scal + 8, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        XL_HIP(hipMemcpyAsync(hscal + 16, lz_ab, 2 * LZ_M * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
         sync();
         elo = hscal[0];
         ehi = hscal[1];
+        spectral_tighten();
         double mu0 = have_guess ? mu_guess : initial_mu();
         const double tau = (d.precision == XLBOMD_FP64) ? 1e-6 : 1e-3;
         reruns = 0;
@@ -699,6 +771,23 @@ template <typename TF, typename TR> struct Sys : SysBase {
     }
     int levels_cap() const override { return Lcap; }
 
+    void lanczos() override {
+        if (!Ys) alloc_matrices(std::max(Lcap, 1));
+        // H itself (scale 1, no shift) in the seed buffer; the expansion
+        // rebuilds its seed there
+        hipLaunchKernelGGL((build_seed_kernel<TF>), dim3(ceil_div(Np, 256), Np), dim3(256), 0, st,
+                           md, vpot, 0.0, 1.0, Ys);
+        XL_LAUNCH_CHECK();
+        XL_HIP(hipMemcpyAsync(lz_v, lz_v0, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+        for (int j = 0; j < LZ_M; ++j) {
+            hipLaunchKernelGGL((matvec_kernel<TF>), dim3(N), dim3(256), 0, st, N, Np,
+                               (const TF *)Ys, (const double *)lz_v, lz_w);
+            hipLaunchKernelGGL(lanczos_step_kernel, dim3(1), dim3(1024), 0, st, N, j, LZ_M, lz_v,
+                               lz_vp, lz_w, lz_ab);
+        }
+        XL_LAUNCH_CHECK();
+    }
+
     void alloc_matrices(int cap) override {
         if (cap <= Lcap) return;
         while ((int)Z.size() < cap + 1) Z.push_back(amat<TF>());
@@ -912,6 +1001,12 @@ template <typename TF, typename TR> struct Sys : SysBase {
         {   // Z_L^2 for the electron-count derivatives and the mu correction
             auto a = base<TF>();
             a.A0 = Z[L]; a.B0 = Z[L]; a.C = ZL2;
+            if constexpr (FUSE_COPY) {
+                if (resp_split) {
+                    if (!ZL2s) ZL2s = amat<TR>();
+                    a.Cs = s16(ZL2s); a.Cs_pl = (long)mat();
+                }
+            }
             run_gemm(a, true);
         }
         hipLaunchKernelGGL((zz2_rows_kernel<TF>), dim3(ceil_div((long)N * 64, 256)), dim3(256), 0,
@@ -994,9 +1089,28 @@ template <typename TF, typename TR> struct Sys : SysBase {
         }
     }
 
+    TR *ZL2s = nullptr;               // split copy of Z_L^2 (split path)
     void finish_density() override {
         // D(mu0 + d) = I - 2Z + d (beta/2)(I - 4Z^2) + d^2/2 beta^2 (Z - 4Z^3)
         const double bd = beta * dmu;
+        if constexpr (FUSE_COPY) {
+            if (resp_split) {
+                // only the Z Z^2 term is a product, with a coefficient of
+                // 2 (beta d)^2 <= 2e-6 (the mu threshold bounds beta |d|):
+                // split products change D by ~1e-11 at most; the other terms
+                // are FP64 in the epilogue
+                SplitArgs a = sbase();
+                a.A0 = s16(Zr[L]); a.B0 = s16(ZL2s); a.alpha = -2.0 * bd * bd;
+                a.Xd = Z[L]; a.beta = -2.0 + 0.5 * bd * bd;
+                a.Xd2 = ZL2; a.beta2 = -2.0 * bd;
+                a.gamma = 1.0 + 0.5 * bd; a.Cd = Dc;
+                run_split<TR>(a, true);
+                hipLaunchKernelGGL((charges_kernel<TF>), dim3(1), dim3(1024), 0, st, nat, no, Np,
+                                   Dc, zc, ncur, q, r, scal + 16);
+                XL_LAUNCH_CHECK();
+                return;
+            }
+        }
         auto a = base<TF>();
         a.A0 = Z[L]; a.B0 = ZL2; a.alpha = (TF)(-2.0 * bd * bd);
         a.X = Z[L]; a.beta = (TF)(-2.0 + 0.5 * bd * bd);
