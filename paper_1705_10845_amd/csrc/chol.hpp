@@ -1,7 +1,10 @@
-// FP64 log-determinant of a symmetric positive definite matrix by a blocked
-// right-looking Cholesky factorisation.  Used only for the electronic
+// FP64 log-determinants of a batch of symmetric positive definite matrices by
+// a blocked right-looking Cholesky factorisation (the batch index is the
+// last grid dimension of every launch).  Used only for the electronic
 // entropy, where every matrix factorised (I + T0, I + 4 Z_k^2) has its
-// spectrum in [1/2, 2], so no pivoting is needed.
+// spectrum in [1/2, 2], so no pivoting is needed; the L + 1 factorisations
+// of one evaluation are independent and run as one batch, which divides the
+// number of latency-bound panel launches by L + 1.
 //
 // Outer panels of NB = 128 columns.  Inside a panel, inner panels of CB = 32
 // columns, one kernel launch each: it applies the panel's earlier inner
@@ -37,8 +40,10 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 // Block 0 writes the factored diagonal block and adds 2 sum ln L_ii to *acc.
 constexpr int CHOL_PT = 64;
 __global__ __launch_bounds__(CHOL_PT) void chol_panel_kernel(int n, int ld, int p, int q,
-                                                             double *A, double *acc) {
+                                                             double *A, long sA, double *acc) {
     __shared__ double Lp[CB][NB - CB + 1];   // L[q + j][p + k], k < q - p
+    A += blockIdx.y * sA;                    // matrix of the batch
+    acc += blockIdx.y;
     __shared__ double Ld[CB][CB + 1];        // factored diagonal block
     const int w = q - p, lane = threadIdx.x;
     for (int t = lane; t < CB * w; t += CHOL_PT)
@@ -105,8 +110,11 @@ __global__ __launch_bounds__(CHOL_PT) void chol_panel_kernel(int n, int ld, int 
 // dimension m): the panel rows below the outer diagonal block, transposed
 // so the product kernel reads them as k-rows.
 __global__ __launch_bounds__(256) void chol_transpose_kernel(int m, int ld, int r0, int c0,
-                                                             const double *A, double *P) {
+                                                             const double *A, long sA, double *P,
+                                                             long sP) {
     __shared__ double t[32][33];
+    A += blockIdx.z * sA;
+    P += blockIdx.z * sP;
     const int i0 = blockIdx.x * 32, k0 = blockIdx.y * 32;
     const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;   // 32 x 8
     for (int r = ty; r < 32; r += 8)
@@ -116,32 +124,34 @@ __global__ __launch_bounds__(256) void chol_transpose_kernel(int m, int ld, int 
         if (i0 + tx < m) P[(long)(k0 + r) * m + i0 + tx] = t[tx][r];
 }
 
-// ln det of the n x n matrix A (destroyed; only its lower triangle is
-// read), n % NB == 0; P is an NB x n workspace, ws (ws_elems doubles) the
-// split-k workspace of the product kernel.  The result is written to *out
-// (device).
-inline void chol_logdet(int n, int ld, double *A, double *P, double *ws, long ws_elems,
-                        double *out, hipStream_t st) {
+// ln det of each of the nb n x n matrices A + b sA (destroyed; only the
+// lower triangles are read), n % NB == 0, into out[b] (device).  P is an
+// NB x n workspace per matrix (stride sP >= NB n), ws (ws_elems doubles)
+// the split-k workspace of the product kernel.
+inline void chol_logdet(int n, int ld, int nb, double *A, long sA, double *P, long sP, double *ws,
+                        long ws_elems, double *out, hipStream_t st) {
     if (n % NB) throw InvalidArg("chol_logdet: n must be a multiple of 128");
-    XL_HIP(hipMemsetAsync(out, 0, sizeof(double), st));
+    if (nb < 1 || sP < (long)NB * n) throw InvalidArg("chol_logdet: bad batch");
+    XL_HIP(hipMemsetAsync(out, 0, nb * sizeof(double), st));
     for (int p = 0; p < n; p += NB) {
         const int pe = p + NB;
         for (int q = p; q < pe; q += CB) {
             const int rest = n - q - CB;
-            hipLaunchKernelGGL(chol_panel_kernel, dim3(std::max(1, ceil_div(rest, CHOL_PT))),
-                               dim3(CHOL_PT), 0, st, n, ld, p, q, A, out);
+            hipLaunchKernelGGL(chol_panel_kernel, dim3(std::max(1, ceil_div(rest, CHOL_PT)), nb),
+                               dim3(CHOL_PT), 0, st, n, ld, p, q, A, sA, out);
             XL_LAUNCH_CHECK();
         }
         const int m = n - pe;
         if (m <= 0) break;
-        hipLaunchKernelGGL(chol_transpose_kernel, dim3(ceil_div(m, 32), NB / 32), dim3(256), 0,
-                           st, m, ld, pe, p, A, P);
+        hipLaunchKernelGGL(chol_transpose_kernel, dim3(ceil_div(m, 32), NB / 32, nb), dim3(256),
+                           0, st, m, ld, pe, p, A, sA, P, sP);
         XL_LAUNCH_CHECK();
         GemmArgs<double> g;                    // A22 <- A22 - L21 L21^T
         g.n = m; g.ld = ld; g.k = NB; g.lda = m;
         g.A0 = P; g.B0 = P;
         g.C = A + (long)pe * ld + pe; g.X = g.C;
         g.alpha = -1.0; g.beta = 1.0;
+        g.batch = nb; g.sA0 = sP; g.sB0 = sP; g.sC = sA; g.sX = sA;
         g.ws = ws; g.ws_elems = ws_elems;
         gemm(g, true, st);
     }

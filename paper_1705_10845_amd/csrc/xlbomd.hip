@@ -1322,18 +1322,31 @@ template <typename TF, typename TR> struct Sys : SysBase {
         return dst;
     }
 
-    double *cholP = nullptr;           // NB x Np panel workspace
-    double logdet(double *A) {         // ln det of the padded Np x Np array, A destroyed
-        if (!cholP) {
-            cholP = dalloc<double>((size_t)NB * Np);
+    // ln det of the first nb matrices of the batch buffer (destroyed), to
+    // hscal[48 ..)
+    double *cholP = nullptr, *cholA = nullptr, *cholOut = nullptr;
+    int chol_cap = 0;
+    double *chol_batch(int nb) {       // nb padded Np x Np FP64 matrices
+        if (nb > chol_cap) {
+            cholA = dalloc<double>(mat() * nb);
+            cholP = dalloc<double>((size_t)NB * Np * nb);
+            mem.ptrs.push_back(cholA);
             mem.ptrs.push_back(cholP);
+            if (!cholOut) {
+                cholOut = dalloc<double>(16);
+                mem.ptrs.push_back(cholOut);
+            }
+            chol_cap = nb;
         }
+        return cholA;
+    }
+    void logdets(int nb) {
         GemmArgs<double> w;
         attach_ws(w);
-        chol_logdet(Np, Np, A, cholP, w.ws, w.ws_elems, scal + 48, st);
-        XL_HIP(hipMemcpyAsync(hscal + 48, scal + 48, sizeof(double), hipMemcpyDeviceToHost, st));
+        chol_logdet(Np, Np, nb, cholA, (long)mat(), cholP, (long)NB * Np, w.ws, w.ws_elems,
+                    cholOut, st);
+        XL_HIP(hipMemcpyAsync(hscal + 48, cholOut, nb * sizeof(double), hipMemcpyDeviceToHost, st));
         sync();
-        return hscal[48];
     }
 
     double entropy_ts() override {
@@ -1341,28 +1354,32 @@ template <typename TF, typename TR> struct Sys : SysBase {
         a.n = Np; a.ld = Np;
         attach_ws(a);                    // split-k for the N x N products
         const double *T0 = as64(Z[0], 0, 2.0);          // T0 = 2 Z_0
-        double *C = w64(1);
+        // one batch: I + T0, then A_0 .. A_{L-1} (the factorisation
+        // overwrites its copies); L + 1 <= 16 outputs
+        if (L + 1 > 16) throw InvalidArg("entropy: more than 15 expansion levels");
+        double *C = chol_batch(L + 1);
         // I + T0 over the padded array: the padding is an identity block
         // (ln det 1 = 0), so the factorisation runs on whole 128-blocks
         hipLaunchKernelGGL(add_diag_copy_kernel, dim3(ceil_div((long)mat(), 256)), dim3(256), 0, st,
                            Np, Np, T0, 1.0, C);
         XL_LAUNCH_CHECK();
-        const double l0 = logdet(C);                     // ln det(I + T0)
-        const double ln2 = std::log(2.0);
-        double lnF = std::ldexp(-N * ln2 + l0, L);
         for (int k = 0; k < L; ++k) {
+            double *Ck = C + (size_t)(k + 1) * mat();
             if constexpr (std::is_same<TF, double>::value) {
-                // the expansion's own A_k (the factorisation overwrites its copy)
-                XL_HIP(hipMemcpyAsync(C, Ak[k], mat() * sizeof(double), hipMemcpyDeviceToDevice, st));
+                // the expansion's own A_k
+                XL_HIP(hipMemcpyAsync(Ck, Ak[k], mat() * sizeof(double), hipMemcpyDeviceToDevice, st));
             } else {
                 // FP32 expansion: A_k again in FP64 from Z_k
                 const double *Zk = as64(Z[k], 2, 1.0);
                 GemmArgs<double> b = a;
-                b.A0 = Zk; b.B0 = Zk; b.alpha = 4.0; b.gamma = 1.0; b.C = C;
+                b.A0 = Zk; b.B0 = Zk; b.alpha = 4.0; b.gamma = 1.0; b.C = Ck;
                 gemm(b, true, st);
             }
-            lnF += std::ldexp(N * ln2 - logdet(C), L - 1 - k);
         }
+        logdets(L + 1);
+        const double ln2 = std::log(2.0);
+        double lnF = std::ldexp(-N * ln2 + hscal[48], L);   // ln det(I + T0) first
+        for (int k = 0; k < L; ++k) lnF += std::ldexp(N * ln2 - hscal[49 + k], L - 1 - k);
         // X_eff = 2^(L+1) atanh(T0) = T0 q(W), W = T0^2, q(w) = sum_j c_j w^j
         // with c_j = 2^(L+1) / (2j + 1), truncated where the next term is
         // below 1e-14 in the trace; q by Paterson-Stockmeyer: baby steps
