@@ -429,16 +429,38 @@ __global__ __launch_bounds__(256) void seed_resp_split_kernel(int n, int ld, con
 }
 
 // Rows of Y D for D = diag(u_b), as split matrices: dst_b[j][k] =
-// split(u_b[k] Y[j][k]) for the FP32 matrix Y (ld x ld, whole padded array;
-// u_b zero past the orbitals), batch stride sd bf16 elements.
+// split(u_b[k] Y[j][k]) for the FP32 matrix Y (ld x ld, whole padded array,
+// ld % 8 == 0; u_b zero past the orbitals), batch stride sd bf16 elements.
+// Eight consecutive elements of one row per thread: two 16-byte loads of Y,
+// one 16-byte store per plane (grid: ld / 8 / 256 x ld rows x batch).
 __global__ __launch_bounds__(256) void colscale_split_kernel(int ld, const float *Y,
                                                              const double *u, long su,
                                                              uint16_t *dst, long pl, long sd) {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long b = blockIdx.y;
-    if (t >= (long)ld * ld) return;
-    const int k = (int)(t % ld);
-    put_split(dst + b * sd, pl, t, (float)(u[b * su + k] * (double)Y[t]));
+    const int c8 = blockIdx.x * blockDim.x + threadIdx.x;   // 8-column group
+    const int j = blockIdx.y;
+    const long b = blockIdx.z;
+    if (8 * c8 >= ld) return;
+    const long o = (long)j * ld + 8 * c8;
+    const f32x4 y0 = *reinterpret_cast<const f32x4 *>(Y + o);
+    const f32x4 y1 = *reinterpret_cast<const f32x4 *>(Y + o + 4);
+    const double *ub = u + b * su + 8 * c8;
+    float x[8];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        x[e] = (float)(ub[e] * (double)y0[e]);
+        x[e + 4] = (float)(ub[e + 4] * (double)y1[e]);
+    }
+    u32x4 hi, lo;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        unsigned h, l;
+        split_pair(x[2 * e], x[2 * e + 1], h, l);
+        hi[e] = h;
+        lo[e] = l;
+    }
+    uint16_t *d = dst + b * sd + o;
+    *reinterpret_cast<u32x4 *>(d) = hi;
+    *reinterpret_cast<u32x4 *>(d + pl) = lo;
 }
 
 // diag(Y T)_i = sum_l Y[i][l] T^T[i][l] for split Y and the stored transpose

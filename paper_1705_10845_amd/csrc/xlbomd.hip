@@ -1188,7 +1188,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
         const long s2 = 2 * sm;            // batch stride of split buffers
         {   // rows of Y D, Y^2 D, Y^3 D (D = diag(u), split), then on pre-split
             // operands G = Y D Y, H2 = Y2 D Y2, H13 = Y D Y3 + Y3 D Y, then Z'_0
-            const dim3 cg(ceil_div((long)mat(), 256), nb);
+            const dim3 cg(ceil_div(Np / 8, 256), Np, nb);
             hipLaunchKernelGGL(colscale_split_kernel, cg, dim3(256), 0, st, Np,
                                (const float *)Ysr, ub, (long)Np, s16(Sd[0]), sm, s2);
             hipLaunchKernelGGL(colscale_split_kernel, cg, dim3(256), 0, st, Np,
