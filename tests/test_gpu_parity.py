@@ -35,10 +35,20 @@ CASES = [
 def _system(name, spec):
     if spec is None:
         return make_system(name)
-    return lattice_system(spec["n"], spec["tmpl"], seed=spec["seed"])
+    extra = {k: v for k, v in spec.items() if k not in ("n", "tmpl", "seed")}
+    return lattice_system(spec["n"], spec["tmpl"], seed=spec["seed"], **extra)
 
 
-@pytest.mark.parametrize("name,spec", CASES)
+# 2 and 3 atoms: 8 and 12 orbitals, no more than the 12 Lanczos steps of
+# the spectral interval, whose recurrence then breaks down and leaves the
+# Gershgorin interval in place
+TINY = [
+    ("lat2", dict(n=2, tmpl="c2", seed=5, rank=1)),
+    ("lat3", dict(n=3, tmpl="c2", seed=6, rank=1)),
+]
+
+
+@pytest.mark.parametrize("name,spec", CASES + TINY)
 def test_solve_charges_fp64(gpu, name, spec):
     s = _system(name, spec)
     m = R.Model(s)
