@@ -355,6 +355,118 @@ __global__ __launch_bounds__(256) void seed_resp_kernel(int n, int ld, const T *
     Zp[b * sG + o] = (T)val;
 }
 
+// ---- sparse seed products ----
+// H (and the seed Y = sc (H - mu I)) is nonzero only on the orbital blocks
+// of atom pairs closer than the hopping cutoff, plus the diagonal blocks.
+constexpr int NB_MAX = 64;   // neighbour atoms per atom, itself included
+
+// Neighbour atoms of every atom (itself first, then every J != I with
+// r_IJ < rc), nb[I * NB_MAX + t]; cnt[I] = their number, or -1 when above
+// NB_MAX.  One wavefront per atom.
+__global__ __launch_bounds__(64) void neighbours_kernel(ModelDev m, int *nb, int *cnt) {
+    const int I = blockIdx.x, lane = threadIdx.x;
+    if (lane == 0) nb[I * NB_MAX] = I;
+    int c = 1;
+    for (int J0 = 0; J0 < m.nat; J0 += 64) {
+        const int J = J0 + lane;
+        bool in = false;
+        if (J < m.nat && J != I) {
+            double dx, dy, dz;
+            in = pair_dist(m.pos, I, J, dx, dy, dz) < m.rc;
+        }
+        const unsigned long long mask = __ballot(in);
+        const int off = __popcll(mask & ((1ull << lane) - 1ull));
+        if (in && c + off < NB_MAX) nb[I * NB_MAX + c + off] = J;
+        c += __popcll(mask);
+    }
+    if (lane == 0) cnt[I] = c <= NB_MAX ? c : -1;
+}
+
+// max over atoms of cnt (a -1 entry counts as NB_MAX + 1) -> *out (double)
+__global__ __launch_bounds__(1024) void max_count_kernel(int nat, const int *cnt, double *out) {
+    __shared__ double sh[16];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nat; i += blockDim.x)
+        v = fmax(v, cnt[i] < 0 ? (double)(NB_MAX + 1) : (double)cnt[i]);
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, sh[w]);
+        out[0] = r;
+    }
+}
+
+// C = alpha Y B + beta X + beta2 X2 over the whole padded ld x ld array
+// (rows of padding zero), for the seed Y with its neighbour-block sparsity
+// and dense B; optional FP32 (Cf) and split (Cs, planes pl apart) copies of
+// C.  One workgroup per (atom, 256 columns): its Y blocks are staged in LDS,
+// each thread accumulates the NO rows of one column in FP64.
+template <typename T> struct SpmmArgs {
+    int nat, ld;
+    const int *nb, *cnt;
+    const T *Y, *B, *X = nullptr, *X2 = nullptr;
+    T *C = nullptr;
+    float *Cf = nullptr;
+    uint16_t *Cs = nullptr;
+    long pl = 0;
+    double alpha = 1.0, beta = 0.0, beta2 = 0.0;
+};
+template <typename T, int NO>
+__global__ __launch_bounds__(256) void spmm_seed_kernel(SpmmArgs<T> p) {
+    __shared__ double yb[NB_MAX][NO * NO];
+    __shared__ int nbs[NB_MAX];
+    const int I = blockIdx.y;
+    const int ld = p.ld;
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = p.cnt[I];
+    for (int t = threadIdx.x; t < c * NO * NO; t += blockDim.x) {
+        const int e = t / (NO * NO), a = (t / NO) % NO, b = t % NO;
+        const int J = p.nb[I * NB_MAX + e];
+        if (a == 0 && b == 0) nbs[e] = J;
+        yb[e][a * NO + b] = (double)p.Y[(long)(I * NO + a) * ld + J * NO + b];
+    }
+    __syncthreads();
+    if (col >= ld) return;
+    double acc[NO];
+#pragma unroll
+    for (int a = 0; a < NO; ++a) acc[a] = 0.0;
+    for (int e = 0; e < c; ++e) {
+        const T *brow = p.B + (long)nbs[e] * NO * ld + col;
+        double bv[NO];
+#pragma unroll
+        for (int b = 0; b < NO; ++b) bv[b] = (double)brow[(long)b * ld];
+#pragma unroll
+        for (int a = 0; a < NO; ++a)
+#pragma unroll
+            for (int b = 0; b < NO; ++b) acc[a] += yb[e][a * NO + b] * bv[b];
+    }
+#pragma unroll
+    for (int a = 0; a < NO; ++a) {
+        const long o = (long)(I * NO + a) * ld + col;
+        double v = p.alpha * acc[a];
+        if (p.X) v += p.beta * (double)p.X[o];
+        if (p.X2) v += p.beta2 * (double)p.X2[o];
+        if (p.C) p.C[o] = (T)v;
+        if (p.Cf) p.Cf[o] = (float)v;
+        if (p.Cs) put_split(p.Cs, p.pl, o, (float)v);
+    }
+}
+
+// rows r0 .. ld of C (and its copies) set to zero (the padding of the seed
+// products)
+template <typename T>
+__global__ __launch_bounds__(256) void zero_rows_kernel(int r0, int ld, T *C, float *Cf,
+                                                        uint16_t *Cs, long pl) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long o = (long)r0 * ld + t;
+    if (t >= (long)(ld - r0) * ld) return;
+    if (C) C[o] = (T)0;
+    if (Cf) Cf[o] = 0.f;
+    if (Cs) put_split(Cs, pl, o, 0.f);
+}
+
 // ---- spectral bounds by Lanczos ----
 // w = A v for the leading n x n block of a dense row-major matrix (leading
 // dimension ld), one workgroup per row.

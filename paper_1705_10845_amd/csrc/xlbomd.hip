@@ -267,6 +267,7 @@ struct SysBase {
         A(vpot, nat); A(glo, N); A(ghi, N); A(g, N); A(epart, 4 * nat);
         A(scal, 64); A(cvec, 8);
         A(lz_v, N); A(lz_vp, N); A(lz_w, N); A(lz_v0, N); A(lz_ab, 2 * LZ_M);
+        A(nbl, (size_t)nat * NB_MAX); A(nbc, nat);
         mcap = std::max(1, std::min(d.kernel_rank, 16));
         A(V, (size_t)mcap * nat); A(W, (size_t)mcap * nat); A(Vprev, (size_t)mcap * nat);
         A(vtmp, nat); A(vin, (size_t)mcap * nat); A(qp, (size_t)mcap * nat); A(hb, (size_t)mcap * nat);
@@ -345,6 +346,12 @@ struct SysBase {
     // half-width about twofold on dense 3-D lattices; the level count of the
     // expansion follows it.)
     static constexpr int LZ_M = 12;
+    // neighbour lists of the current positions (sparse seed products): the
+    // seed's powers of Y are sparse-dense products when every atom has at
+    // most NB_MAX neighbours and at most a quarter of all atoms
+    int *nbl = nullptr, *nbc = nullptr;
+    int nb_max = 0;
+    bool sparse_seed() const { return nb_max > 0 && nb_max <= NB_MAX && 4 * nb_max <= nat; }
     double *lz_v = nullptr, *lz_vp = nullptr, *lz_w = nullptr, *lz_v0 = nullptr, *lz_ab = nullptr;
     void spectral_tighten() {
         const double *a = hscal + 16, *b = hscal + 16 + LZ_M;
@@ -387,12 +394,17 @@ struct SysBase {
         XL_LAUNCH_CHECK();
         gershgorin();
         lanczos();
-        XL_HIP(hipMemcpyAsync(hscal, scal + 8, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        hipLaunchKernelGGL(neighbours_kernel, dim3(nat), dim3(64), 0, st, md, nbl, nbc);
+        hipLaunchKernelGGL(max_count_kernel, dim3(1), dim3(1024), 0, st, nat, (const int *)nbc,
+                           scal + 10);
+        XL_LAUNCH_CHECK();
+        XL_HIP(hipMemcpyAsync(hscal, scal + 8, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
         XL_HIP(hipMemcpyAsync(hscal + 16, lz_ab, 2 * LZ_M * sizeof(double),
                               hipMemcpyDeviceToHost, st));
         sync();
         elo = hscal[0];
         ehi = hscal[1];
+        nb_max = (int)hscal[2];
         spectral_tighten();
         double mu0 = have_guess ? mu_guess : initial_mu();
         const double tau = (d.precision == XLBOMD_FP64) ? 1e-6 : 1e-3;
@@ -898,7 +910,48 @@ template <typename TF, typename TR> struct Sys : SysBase {
         XL_LAUNCH_CHECK();
         const double ymax = std::ldexp(xmax, -(L + 1)), ym2 = ymax * ymax;
         t0max = ymax * (1.0 - ym2 / 3.0 + 2.0 * ym2 * ym2 / 15.0);
-        {   // Y2 = Y Y ; Y3 = Y Y2 ; Z0 = Y/2 - Y3/6 + Y3 Y2 / 15 (= tanh(Y)/2 to O(Y^7))
+        if (sparse_seed()) {
+            // Y2 = Y Y, Y3 = Y Y2, Y4 = Y Y3 (kept for the seed response),
+            // Z0 = Y/2 - Y3/6 + Y Y4 / 15, each a sparse-dense product
+            SpmmArgs<TF> a{};
+            a.Y = Ys; a.B = Ys; a.C = Y2;
+            if constexpr (FUSE_COPY) {
+                a.Cf = Y2r;
+                if (resp_split) { a.Cs = s16(Sy[1]); a.pl = (long)mat(); }
+            }
+            spmm(a);
+            a = SpmmArgs<TF>{};
+            a.Y = Ys; a.B = Y2; a.C = Y3;
+            if constexpr (FUSE_COPY) {
+                a.Cf = Y3r;
+                if (resp_split) { a.Cs = s16(Sy[2]); a.pl = (long)mat(); }
+            }
+            spmm(a);
+            if (!Y4r) Y4r = amat<TR>();
+            TF *Y4t;
+            if constexpr (SAME) Y4t = (TF *)Y4r;
+            else {
+                if (!Y4f) Y4f = amat<TF>();
+                Y4t = Y4f;
+            }
+            a = SpmmArgs<TF>{};
+            a.Y = Ys; a.B = Y3; a.C = Y4t;
+            if constexpr (FUSE_COPY) {
+                if (resp_split) { a.Cs = s16(Y4r); a.pl = (long)mat(); }
+                else a.Cf = (float *)Y4r;
+            }
+            spmm(a);
+            Y4_for = expansion_id;
+            a = SpmmArgs<TF>{};
+            a.Y = Ys; a.B = Y4t; a.alpha = 1.0 / 15.0;
+            a.X = Y3; a.beta = -1.0 / 6.0; a.X2 = Ys; a.beta2 = 0.5;
+            a.C = Z[0];
+            if constexpr (FUSE_COPY) {
+                if (resp_split) { a.Cs = s16(Zr[0]); a.pl = (long)mat(); }
+                else a.Cf = (float *)Zr[0];
+            }
+            spmm(a);
+        } else {   // Y2 = Y Y ; Y3 = Y Y2 ; Z0 = Y/2 - Y3/6 + Y3 Y2 / 15 (= tanh(Y)/2 to O(Y^7))
             auto a = base<TF>();
             a.A0 = Ys; a.B0 = Ys; a.C = Y2;
             if constexpr (FUSE_COPY) {
@@ -1090,6 +1143,24 @@ template <typename TF, typename TR> struct Sys : SysBase {
     }
 
     TR *ZL2s = nullptr;               // split copy of Z_L^2 (split path)
+    TF *Y4f = nullptr;                // FP64 Y^4 of the sparse seed (when TF != TR)
+    void spmm(SpmmArgs<TF> a) {
+        a.nat = nat; a.ld = Np; a.nb = nbl; a.cnt = nbc;
+        const dim3 g(ceil_div(Np, 256), nat);
+        switch (no) {
+#define XL_SPMM(K) case K: hipLaunchKernelGGL((spmm_seed_kernel<TF, K>), g, dim3(256), 0, st, a); break;
+            XL_SPMM(1) XL_SPMM(2) XL_SPMM(3) XL_SPMM(4) XL_SPMM(5) XL_SPMM(6) XL_SPMM(7) XL_SPMM(8)
+#undef XL_SPMM
+            default: throw InvalidArg("spmm: orbitals per atom must be 1..8");
+        }
+        XL_LAUNCH_CHECK();
+        if (Np > N) {
+            hipLaunchKernelGGL((zero_rows_kernel<TF>), dim3(ceil_div((long)(Np - N) * Np, 256)),
+                               dim3(256), 0, st, N, Np, a.C, a.Cf, a.Cs, a.pl);
+            XL_LAUNCH_CHECK();
+        }
+    }
+
     void finish_density() override {
         // D(mu0 + d) = I - 2Z + d (beta/2)(I - 4Z^2) + d^2/2 beta^2 (Z - 4Z^3)
         const double bd = beta * dmu;

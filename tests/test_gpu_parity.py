@@ -48,9 +48,21 @@ TINY = [
 ]
 
 
-@pytest.mark.parametrize("name,spec", CASES + TINY)
+# 160 atoms (N = 640): every atom has at most a quarter of all atoms within
+# the hopping cutoff, so the seed's powers of Y are sparse-dense products
+SPARSE = [("lat160", dict(n=160, tmpl="c2", seed=7))]
+
+
+def _max_neighbours(s):
+    d = np.sqrt(((s.pos[:, None, :] - s.pos[None, :, :]) ** 2).sum(-1))
+    return int((d < s.hop_cutoff).sum(1).max())
+
+
+@pytest.mark.parametrize("name,spec", CASES + TINY + SPARSE)
 def test_solve_charges_fp64(gpu, name, spec):
     s = _system(name, spec)
+    if (name, spec) in SPARSE:
+        assert 4 * _max_neighbours(s) <= s.n_atoms
     m = R.Model(s)
     g = gpu.XLBOMD(s, precision=gpu.FP64, scf_tol=1e-9)
     for seed in (1, 2):
@@ -213,3 +225,28 @@ def test_mixed_path(gpu, name, spec):
     assert dq < 1e-8
     assert err < 1e-4
     g.close()
+
+
+@pytest.mark.parametrize("prec_name", ["MIXED", "MIXED_BF16X3"])
+def test_sparse_seed_reduced_precision_paths(gpu, prec_name):
+    """The sparse-dense seed also writes the response operands (FP32 copies
+    for MIXED, split copies and the split Y^4 for MIXED_BF16X3): charges and
+    a response on the 160-atom lattice against the oracle."""
+    name, spec = SPARSE[0]
+    s = _system(name, spec)
+    assert 4 * _max_neighbours(s) <= s.n_atoms
+    m = R.Model(s)
+    g = gpu.XLBOMD(s, precision=getattr(gpu, prec_name), scf_tol=1e-9)
+    n = _rand_n(s.n_atoms, 5)
+    q, rep = g.solve(n)
+    el = R.electronic(m, s.pos, n)
+    dq = np.abs(q - el.q).max()
+    V = np.random.default_rng(6).standard_normal((1, s.n_atoms))
+    V /= np.linalg.norm(V)
+    dv = g.response(V)[0]
+    ref = R.response(m, el, V[0])
+    err = np.abs(dv - ref).max() / np.abs(ref).max()
+    print(f"{name} {prec_name}: max|dq| {dq:.2e}, response rel err {err:.2e}, L={rep['foe_levels']}")
+    g.close()
+    assert dq < 1e-8
+    assert err < (1e-4 if prec_name == "MIXED" else 1e-3)
