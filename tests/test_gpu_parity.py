@@ -32,6 +32,22 @@ CASES = [
 ]
 
 
+# oracle solves of the sparse case take ~14 s each (N = 640): its tests
+# share one n and one cached solve
+_EL_CACHE = {}
+
+
+def _seed(name, seed):
+    return 1 if name == SPARSE[0][0] else seed
+
+
+def _electronic(name, m, s, n, seed):
+    key = (name, seed)
+    if key not in _EL_CACHE:
+        _EL_CACHE[key] = R.electronic(m, s.pos, n)
+    return _EL_CACHE[key]
+
+
 def _system(name, spec):
     if spec is None:
         return make_system(name)
@@ -77,14 +93,15 @@ def test_solve_charges_fp64(gpu, name, spec):
     g.close()
 
 
-@pytest.mark.parametrize("name,spec", CASES[:2])
+@pytest.mark.parametrize("name,spec", CASES[:2] + SPARSE)
 def test_response_fp64(gpu, name, spec):
     s = _system(name, spec)
     m = R.Model(s)
     g = gpu.XLBOMD(s, precision=gpu.FP64, scf_tol=1e-9)
-    n = _rand_n(s.n_atoms, 7)
+    seed = _seed(name, 7)
+    n = _rand_n(s.n_atoms, seed)
     g.solve(n)
-    el = R.electronic(m, s.pos, n)
+    el = _electronic(name, m, s, n, seed)
     rng = np.random.default_rng(5)
     V = rng.standard_normal((1, s.n_atoms))
     V /= np.linalg.norm(V)
@@ -182,14 +199,15 @@ def test_trajectory_c1_fp64(gpu):
     g.close()
 
 
-@pytest.mark.parametrize("name,spec", CASES)
+@pytest.mark.parametrize("name,spec", CASES + SPARSE)
 def test_solve_charges_fp32(gpu, name, spec):
     s = _system(name, spec)
     m = R.Model(s)
     g = gpu.XLBOMD(s, precision=gpu.FP32, scf_tol=1e-6)
-    n = _rand_n(s.n_atoms, 1)
+    seed = _seed(name, 1)
+    n = _rand_n(s.n_atoms, seed)
     q, rep = g.solve(n)
-    el = R.electronic(m, s.pos, n)
+    el = _electronic(name, m, s, n, seed)
     dq = np.abs(q - el.q).max()
     print(f"{name} FP32: max|dq| {dq:.2e} L={rep['foe_levels']}")
     assert dq < 1e-5
@@ -212,9 +230,10 @@ def test_mixed_path(gpu, name, spec):
     s = _system(name, spec)
     m = R.Model(s)
     g = gpu.XLBOMD(s, precision=gpu.MIXED, scf_tol=1e-9)
-    n = _rand_n(s.n_atoms, 3)
+    seed = _seed(name, 3)
+    n = _rand_n(s.n_atoms, seed)
     q, rep = g.solve(n)
-    el = R.electronic(m, s.pos, n)
+    el = _electronic(name, m, s, n, seed)
     dq = np.abs(q - el.q).max()
     V = np.random.default_rng(2).standard_normal((1, s.n_atoms))
     V /= np.linalg.norm(V)
@@ -237,9 +256,10 @@ def test_sparse_seed_reduced_precision_paths(gpu, prec_name):
     assert 4 * _max_neighbours(s) <= s.n_atoms
     m = R.Model(s)
     g = gpu.XLBOMD(s, precision=getattr(gpu, prec_name), scf_tol=1e-9)
-    n = _rand_n(s.n_atoms, 5)
+    seed = _seed(name, 5)
+    n = _rand_n(s.n_atoms, seed)
     q, rep = g.solve(n)
-    el = R.electronic(m, s.pos, n)
+    el = _electronic(name, m, s, n, seed)
     dq = np.abs(q - el.q).max()
     V = np.random.default_rng(6).standard_normal((1, s.n_atoms))
     V /= np.linalg.norm(V)
@@ -250,3 +270,24 @@ def test_sparse_seed_reduced_precision_paths(gpu, prec_name):
     g.close()
     assert dq < 1e-8
     assert err < (1e-4 if prec_name == "MIXED" else 1e-3)
+
+
+def test_sparse_seed_forces_energy_fp64(gpu):
+    """Forces and free energy (its entropy starts from the Z_0 the sparse
+    seed makes) at a solved n on the 160-atom lattice, against the oracle."""
+    name, spec = SPARSE[0]
+    s = _system(name, spec)
+    m = R.Model(s)
+    g = gpu.XLBOMD(s, precision=gpu.FP64, scf_tol=1e-9)
+    seed = _seed(name, 1)
+    n = _rand_n(s.n_atoms, seed)
+    g.solve(n)
+    F, e = g.forces()
+    el = _electronic(name, m, s, n, seed)
+    Fo = R.forces(m, s.pos, el)
+    eo = R.free_energy(m, s.pos, el)
+    dF = np.abs(F - Fo).max()
+    dO = abs(e["omega"] - eo["omega"]) / abs(eo["omega"])
+    print(f"{name}: dF {dF:.2e} rel dOmega {dO:.2e} dTS {abs(e['te_s'] - eo['te_s']):.2e}")
+    g.close()
+    assert dF < 1e-5 and dO < 1e-8
