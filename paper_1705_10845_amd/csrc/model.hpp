@@ -412,20 +412,27 @@ template <typename T> struct SpmmArgs {
     uint16_t *Cs = nullptr;
     long pl = 0;
     double alpha = 1.0, beta = 0.0, beta2 = 0.0;
+    // optional column scale of Y (Y D, D = diag(u_b) for batch b = blockIdx.z)
+    // and batch strides of the outputs C (elements) and Cs (bf16 elements)
+    const double *u = nullptr;
+    long su = 0, sC = 0, sCs = 0;
 };
 template <typename T, int NO>
 __global__ __launch_bounds__(256) void spmm_seed_kernel(SpmmArgs<T> p) {
     __shared__ double yb[NB_MAX][NO * NO];
     __shared__ int nbs[NB_MAX];
     const int I = blockIdx.y;
+    const long bz = blockIdx.z;
     const int ld = p.ld;
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = p.cnt[I];
+    const double *u = p.u ? p.u + bz * p.su : nullptr;
     for (int t = threadIdx.x; t < c * NO * NO; t += blockDim.x) {
         const int e = t / (NO * NO), a = (t / NO) % NO, b = t % NO;
         const int J = p.nb[I * NB_MAX + e];
         if (a == 0 && b == 0) nbs[e] = J;
-        yb[e][a * NO + b] = (double)p.Y[(long)(I * NO + a) * ld + J * NO + b];
+        yb[e][a * NO + b] = (double)p.Y[(long)(I * NO + a) * ld + J * NO + b] *
+                            (u ? u[J * NO + b] : 1.0);
     }
     __syncthreads();
     if (col >= ld) return;
@@ -448,10 +455,30 @@ __global__ __launch_bounds__(256) void spmm_seed_kernel(SpmmArgs<T> p) {
         double v = p.alpha * acc[a];
         if (p.X) v += p.beta * (double)p.X[o];
         if (p.X2) v += p.beta2 * (double)p.X2[o];
-        if (p.C) p.C[o] = (T)v;
+        if (p.C) p.C[bz * p.sC + o] = (T)v;
         if (p.Cf) p.Cf[o] = (float)v;
-        if (p.Cs) put_split(p.Cs, p.pl, o, (float)v);
+        if (p.Cs) put_split(p.Cs + bz * p.sCs, p.pl, o, (float)v);
     }
+}
+
+// H = P + P^T (ld x ld, whole padded array) for the FP64 matrices P_b
+// (batch stride sP), written as split matrices (planes pl apart, batch
+// stride sH bf16 elements): 32 x 32 tiles through LDS, 256 threads.
+__global__ __launch_bounds__(256) void sym_split_kernel(int ld, const double *P, long sP,
+                                                        uint16_t *H, long pl, long sH) {
+    __shared__ double t1[32][33], t2[32][33];
+    const long bz = blockIdx.z;
+    P += bz * sP;
+    H += bz * sH;
+    const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        t1[r][tx] = P[(long)(i0 + r) * ld + j0 + tx];          // P[i][j]
+        t2[r][tx] = P[(long)(j0 + r) * ld + i0 + tx];          // P[j][i] (row j0 + r)
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8)
+        put_split(H, pl, (long)(i0 + r) * ld + j0 + tx, (float)(t1[r][tx] + t2[tx][r]));
 }
 
 // rows r0 .. ld of C (and its copies) set to zero (the padding of the seed

@@ -830,6 +830,8 @@ template <typename TF, typename TR> struct Sys : SysBase {
     }
     TR *Xb = nullptr;                 // fourth response buffer (split path)
     TR *Sd[3] = {};                   // rows of Y D, Y^2 D, Y^3 D (split path)
+    double *Pb = nullptr;             // Y D Y^3 per direction (sparse seed)
+    int pb_cap = 0;
     // split bf16 view of a TR matrix buffer (planes mat() elements apart)
     uint16_t *s16(TR *p) const { return reinterpret_cast<uint16_t *>(p); }
     // response operand copy written by an expansion product: split planes
@@ -1144,9 +1146,10 @@ template <typename TF, typename TR> struct Sys : SysBase {
 
     TR *ZL2s = nullptr;               // split copy of Z_L^2 (split path)
     TF *Y4f = nullptr;                // FP64 Y^4 of the sparse seed (when TF != TR)
-    void spmm(SpmmArgs<TF> a) {
+    void spmm(SpmmArgs<TF> a, int nb = 1) {
         a.nat = nat; a.ld = Np; a.nb = nbl; a.cnt = nbc;
-        const dim3 g(ceil_div(Np, 256), nat);
+        if (nb > 1 && Np > N) throw InvalidArg("spmm: batched products need an unpadded matrix");
+        const dim3 g(ceil_div(Np, 256), nat, nb);
         switch (no) {
 #define XL_SPMM(K) case K: hipLaunchKernelGGL((spmm_seed_kernel<TF, K>), g, dim3(256), 0, st, a); break;
             XL_SPMM(1) XL_SPMM(2) XL_SPMM(3) XL_SPMM(4) XL_SPMM(5) XL_SPMM(6) XL_SPMM(7) XL_SPMM(8)
@@ -1257,7 +1260,38 @@ template <typename TF, typename TR> struct Sys : SysBase {
                            st, nat, no, nb, sc, hb, (long)Np, ub);
         XL_LAUNCH_CHECK();
         const long s2 = 2 * sm;            // batch stride of split buffers
-        {   // rows of Y D, Y^2 D, Y^3 D (D = diag(u), split), then on pre-split
+        if (sparse_seed() && Np == N) {
+            // G = (Y D) Y and P = (Y D) Y^3 as sparse-dense products (the
+            // column scale on the staged Y blocks), H13 = Y D Y^3 + Y^3 D Y
+            // = P + P^T, and H2 = Y2 D Y2 on pre-split operands
+            const dim3 cg(ceil_div(Np / 8, 256), Np, nb);
+            hipLaunchKernelGGL(colscale_split_kernel, cg, dim3(256), 0, st, Np,
+                               (const float *)Y2r, ub, (long)Np, s16(Sd[1]), sm, s2);
+            XL_LAUNCH_CHECK();
+            if (!Pb || pb_cap < nb) {
+                Pb = dalloc<double>(mat() * nb);
+                mem.ptrs.push_back(Pb);
+                pb_cap = nb;
+            }
+            SpmmArgs<TF> a{};
+            a.Y = Ys; a.B = Ys; a.u = ub; a.su = Np; a.Cs = s16(Tb); a.pl = sm; a.sCs = s2;
+            spmm(a, nb);
+            a = SpmmArgs<TF>{};
+            a.Y = Ys; a.B = Y3; a.u = ub; a.su = Np; a.C = (TF *)Pb; a.sC = sm;
+            spmm(a, nb);
+            hipLaunchKernelGGL(sym_split_kernel, dim3(Np / 32, Np / 32, nb), dim3(256), 0, st, Np,
+                               (const double *)Pb, sm, s16(Xb), sm, s2);
+            XL_LAUNCH_CHECK();
+            SplitArgs h = sbase();
+            h.batch = nb; h.A0 = s16(Sy[1]); h.B0 = s16(Sd[1]); h.sB0 = s2;
+            h.C = s16(Ap); h.sC = s2;
+            run_split<TR>(h, true);
+            hipLaunchKernelGGL(seed_resp_split_kernel, dim3(ceil_div(Np, 256), Np, nb), dim3(256),
+                               0, st, N, Np, (const uint16_t *)s16(Tb), (const uint16_t *)s16(Ap),
+                               (const uint16_t *)s16(Xb), (const float *)Y2r,
+                               (const uint16_t *)s16(Y4r), ub, (long)Np, sm, s16(Zp), sm);
+            XL_LAUNCH_CHECK();
+        } else {   // rows of Y D, Y^2 D, Y^3 D (D = diag(u), split), then on pre-split
             // operands G = Y D Y, H2 = Y2 D Y2, H13 = Y D Y3 + Y3 D Y, then Z'_0
             const dim3 cg(ceil_div(Np / 8, 256), Np, nb);
             hipLaunchKernelGGL(colscale_split_kernel, cg, dim3(256), 0, st, Np,

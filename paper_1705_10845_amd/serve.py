@@ -32,8 +32,9 @@ def footprint_bytes(system, precision=MIXED, levels=10) -> int:
 
     Expansion matrices: Z_0..Z_L, Y_0..Y_{L-1}, A_0..A_{L-1}, the seed
     powers Y, Y^2, Y^3 and four work matrices; responses: three matrices per
-    direction (seven on the split path: four work matrices and the split
-    rows of Y D, Y^2 D, Y^3 D), plus the response-precision copies of the
+    direction (nine on the split path: four work matrices, the split rows
+    of Y D, Y^2 D, Y^3 D and the FP64 Y D Y^3), plus the response-precision
+    copies of the
     expansion operands (Z, Y, Y..Y^4) when the two precisions differ, and
     on the split path the split Y, Y^2, Y^3, Z_L^2 and four level work
     matrices.
@@ -44,7 +45,7 @@ def footprint_bytes(system, precision=MIXED, levels=10) -> int:
     m = max(1, system.rank)
     mats_f = 3 * levels + 8
     if precision == MIXED_BF16X3:
-        mats_r = 7 * m + 2 * levels + 13
+        mats_r = 9 * m + 2 * levels + 13
     else:
         mats_r = 3 * m + ((2 * levels + 5) if ef != er else 0)
     vecs = 64 * system.n_atoms * 8 + 16 * npad * 8
