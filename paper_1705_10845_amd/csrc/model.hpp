@@ -495,18 +495,26 @@ __global__ __launch_bounds__(256) void zero_rows_kernel(int r0, int ld, T *C, fl
 }
 
 // ---- spectral bounds by Lanczos ----
-// w = A v for the leading n x n block of a dense row-major matrix (leading
-// dimension ld), one workgroup per row.
+// w = A v for the neighbour-block sparsity of H (A dense-stored, ld; no
+// orbitals per atom, <= 8): one wavefront per atom; an atom whose list
+// overflowed (cnt < 0) reads its full rows.
 template <typename T>
-__global__ __launch_bounds__(256) void matvec_kernel(int n, int ld, const T *A, const double *v,
-                                                     double *w) {
-    __shared__ double sh[16];
-    const int i = blockIdx.x;
-    const T *a = A + (long)i * ld;
-    double s = 0.0;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) s += (double)a[j] * v[j];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) w[i] = s;
+__global__ __launch_bounds__(64) void sp_matvec_kernel(int n, int no, int ld, const int *nb,
+                                                       const int *cnt, const T *A,
+                                                       const double *v, double *w) {
+    const int I = blockIdx.x, lane = threadIdx.x;
+    const int c = cnt[I];
+    const int m = c < 0 ? n : c * no;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int t = lane; t < m; t += 64) {
+        const int j = c < 0 ? t : nb[I * NB_MAX + t / no] * no + t % no;
+        const double vj = v[j];
+        for (int a = 0; a < no; ++a) acc[a] += (double)A[(long)(I * no + a) * ld + j] * vj;
+    }
+    for (int a = 0; a < no; ++a) {
+        const double s = wave_sum(acc[a]);
+        if (lane == 0) w[I * no + a] = s;
+    }
 }
 
 // Lanczos step j on length-n vectors (one workgroup), w = A v on entry:

@@ -338,7 +338,7 @@ struct SysBase {
     }
 
     // Spectral interval of H: Gershgorin, tightened by LZ_M Lanczos steps
-    // from a fixed random vector.  Each side becomes the extreme Ritz value
+    // (neighbour-block matvecs) from a fixed random vector.  Each side becomes the extreme Ritz value
     // widened by the last Lanczos coefficient beta_m (the norm of the
     // residual vector; the extreme Ritz values converge from inside), and is
     // kept only when tighter than Gershgorin.  On a breakdown or a
@@ -393,11 +393,11 @@ struct SysBase {
                            0, st, md, 1, ncur, vpot);
         XL_LAUNCH_CHECK();
         gershgorin();
-        lanczos();
         hipLaunchKernelGGL(neighbours_kernel, dim3(nat), dim3(64), 0, st, md, nbl, nbc);
         hipLaunchKernelGGL(max_count_kernel, dim3(1), dim3(1024), 0, st, nat, (const int *)nbc,
                            scal + 10);
         XL_LAUNCH_CHECK();
+        lanczos();
         XL_HIP(hipMemcpyAsync(hscal, scal + 8, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
         XL_HIP(hipMemcpyAsync(hscal + 16, lz_ab, 2 * LZ_M * sizeof(double),
                               hipMemcpyDeviceToHost, st));
@@ -792,8 +792,9 @@ template <typename TF, typename TR> struct Sys : SysBase {
         XL_LAUNCH_CHECK();
         XL_HIP(hipMemcpyAsync(lz_v, lz_v0, N * sizeof(double), hipMemcpyDeviceToDevice, st));
         for (int j = 0; j < LZ_M; ++j) {
-            hipLaunchKernelGGL((matvec_kernel<TF>), dim3(N), dim3(256), 0, st, N, Np,
-                               (const TF *)Ys, (const double *)lz_v, lz_w);
+            hipLaunchKernelGGL((sp_matvec_kernel<TF>), dim3(nat), dim3(64), 0, st, N, no, Np,
+                               (const int *)nbl, (const int *)nbc, (const TF *)Ys,
+                               (const double *)lz_v, lz_w);
             hipLaunchKernelGGL(lanczos_step_kernel, dim3(1), dim3(1024), 0, st, N, j, LZ_M, lz_v,
                                lz_vp, lz_w, lz_ab);
         }
