@@ -41,7 +41,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <atomic>
 #include <string>
 #include <thread>
@@ -137,25 +139,50 @@ void tridiag_extremes(const double *a, const double *b, int m, double &lo, doubl
     hi = kth(m - 1);
 }
 
+// Largest deviation of the L-level expansion from the Fermi function on
+// [-xmax, xmax] (a uniform grid plus a dense one near the Fermi level).
+double level_error(double xmax, int L) {
+    double err = 0.0;
+    const int G = 2000;
+    for (int g = 0; g <= G; ++g) {
+        const double x = -xmax + 2.0 * xmax * g / G;
+        err = std::max(err, std::fabs(foe_scalar(x, L) - fermi(x)));
+    }
+    for (int g = 0; g <= 400; ++g) {
+        const double x = -12.0 + 24.0 * g / 400.0;
+        if (std::fabs(x) <= xmax) err = std::max(err, std::fabs(foe_scalar(x, L) - fermi(x)));
+    }
+    return err;
+}
+
+// Largest xmax (at most 2^(L+1), i.e. |y| <= 1) for which L levels stay
+// within tol.  The deviation over [-xmax, xmax] does not decrease with xmax,
+// so the reach is found once per (L, tol) by bisection and kept.
+double level_reach(int L, double tol) {
+    static std::mutex mu;
+    static std::map<std::pair<int, double>, double> known;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(L, tol);
+    const auto it = known.find(key);
+    if (it != known.end()) return it->second;
+    double lo = 0.0, hi = std::ldexp(1.0, L + 1);
+    if (level_error(hi, L) > tol) {
+        for (int i = 0; i < 60 && hi - lo > 1e-12 * hi; ++i) {
+            const double m = 0.5 * (lo + hi);
+            if (level_error(m, L) <= tol) lo = m; else hi = m;
+        }
+        hi = lo;
+    }
+    known.emplace(key, hi);
+    return hi;
+}
+
 // Smallest L whose expansion keeps |y| <= 1 (where the quintic seed is
 // increasing and below 1) and stays within `tol` of the Fermi function on
 // [-xmax, xmax].
 int choose_levels(double xmax, double tol) {
-    for (int L = 1; L <= 40; ++L) {
-        if (std::ldexp(xmax, -(L + 1)) > 1.0) continue;
-        double err = 0.0;
-        const int G = 2000;
-        for (int g = 0; g <= G; ++g) {
-            const double x = -xmax + 2.0 * xmax * g / G;
-            err = std::max(err, std::fabs(foe_scalar(x, L) - fermi(x)));
-        }
-        for (int g = 0; g <= 400; ++g) {   // dense near the Fermi level
-            const double x = -12.0 + 24.0 * g / 400.0;
-            if (std::fabs(x) <= xmax)
-                err = std::max(err, std::fabs(foe_scalar(x, L) - fermi(x)));
-        }
-        if (err <= tol) return L;
-    }
+    for (int L = 1; L <= 40; ++L)
+        if (xmax <= level_reach(L, tol)) return L;
     return 40;
 }
 
@@ -406,6 +433,7 @@ struct SysBase {
         ehi = hscal[1];
         nb_max = (int)hscal[2];
         spectral_tighten();
+        if (!std::isfinite(elo) || !std::isfinite(ehi)) throw Diverged("non-finite spectral bounds");
         double mu0 = have_guess ? mu_guess : initial_mu();
         const double tau = (d.precision == XLBOMD_FP64) ? 1e-6 : 1e-3;
         reruns = 0;
