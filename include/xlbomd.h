@@ -12,7 +12,7 @@
  *   - H[n] = H0(R) + diag(Gamma n) (Section IV.A, SCC tight binding), the
  *     Fermi-Dirac density matrix D = 2 f(H) at fixed electron number
  *     (Section IV.B, Eq. 36), net charges q and the residual r = q - n;
- *   - Hellmann-Feynman forces at fixed n (Eq. 40, first line);
+ *   - Hellmann-Feynman forces at fixed n (the fixed-n derivative in Eq. 40);
  *   - the rank-m kernel from Sherman-Morrison updates of K0 = -gamma I
  *     (Eqs. 48-51) along Krylov directions whose responses dq/dv come from
  *     density-matrix perturbation theory (Section V.B);

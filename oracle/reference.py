@@ -13,15 +13,16 @@ principles molecular dynamics"):
                       D = 2 f(H), net Mulliken charges q (Section VI).
   free energy         Eqs. 35, 37, 38 specialised to SCC tight binding:
                       Omega = Tr[H0 D] + 1/2 (2q - n)^T Gamma n + E_rep - Te S.
-  forces              Eq. 40 first line (partial derivative at fixed n).
+  forces              Eq. 40, the partial derivative at fixed n.
   response            Section V.B: canonical first-order response of q to a
                       potential perturbation along v (directional derivative
                       of q[n + lambda v]).
   kernel              Eqs. 48-51: K0 = (J0 - I)^-1, J0 = c I, followed by the
                       Sherman-Morrison sequence of rank-1 updates over
                       orthonormal directions, the first along K0 r.
-  integration         Eq. 22 (velocity Verlet for the nuclei; the second line
-                      is read with the velocity, not the acceleration) and
+  integration         Eq. 22 (velocity Verlet for the nuclei; the position
+                      update is read with the velocity, not the
+                      acceleration) and
                       Eq. 23 with the K_max = 5, 6, 7 rows of Table I.
   initial state       Eq. 20 with the ground state from the kernel SCF of
                       Eq. 52.

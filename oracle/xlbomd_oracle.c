@@ -18,7 +18,7 @@
  *   - the canonical (fixed electron number) first-order response of the
  *     charges to a potential perturbation, in closed form through divided
  *     differences of the occupations (Section V.B);
- *   - Hellmann-Feynman forces at fixed n (Eq. 40, first line).
+ *   - Hellmann-Feynman forces at fixed n (the fixed-n derivative in Eq. 40).
  *
  * Every function returns 0 on success, a negative value on bad input.
  */
@@ -123,7 +123,7 @@ double orc_erep(int nat, const double *pos, double A, double decay,
     return e;
 }
 
-/* Hellmann-Feynman forces at fixed n and fixed D (Eq. 40, first line):
+/* Hellmann-Feynman forces at fixed n and fixed D (the fixed-n derivative in Eq. 40):
  *   band:    -2 sum_{J!=I} sum_ab B_ab d/dR_I[h(r)s(r)] D[Ia,Jb]
  *   Coulomb: -1/2 sum_{J!=I} [(2q_I-n_I) n_J + (2q_J-n_J) n_I] dGamma_IJ/dR_I
  * Repulsion is added separately by orc_erep.  F is overwritten. */

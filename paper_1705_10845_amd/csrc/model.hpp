@@ -401,8 +401,12 @@ __global__ __launch_bounds__(1024) void max_count_kernel(int nat, const int *cnt
 // C = alpha Y B + beta X + beta2 X2 over the whole padded ld x ld array
 // (rows of padding zero), for the seed Y with its neighbour-block sparsity
 // and dense B; optional FP32 (Cf) and split (Cs, planes pl apart) copies of
-// C.  One workgroup per (atom, 256 columns): its Y blocks are staged in LDS,
-// each thread accumulates the NO rows of one column in FP64.
+// C.  One workgroup per (atom, 256 columns), each thread accumulating the NO
+// rows of one column in FP64.  The Y blocks are the same for the whole
+// workgroup and are read with scalar loads; the optional column scale of Y
+// is applied to the NO loaded values of B instead.  Vector registers then
+// hold only B values and accumulators, and the neighbour loop, unrolled
+// four times, keeps 4 NO loads of B per wave in flight.
 template <typename T> struct SpmmArgs {
     int nat, ld;
     const int *nb, *cnt;
@@ -417,38 +421,43 @@ template <typename T> struct SpmmArgs {
     const double *u = nullptr;
     long su = 0, sC = 0, sCs = 0;
 };
+template <typename T, int NO, bool SCALE>
+__device__ __forceinline__ void spmm_rows(const T *__restrict__ Yr, const T *__restrict__ B,
+                                          const int *__restrict__ nl, const double *__restrict__ u,
+                                          int c, int ld, int col, double *acc) {
+#pragma unroll
+    for (int a = 0; a < NO; ++a) acc[a] = 0.0;
+#pragma unroll 4
+    for (int e = 0; e < c; ++e) {
+        const int J = nl[e];
+        const T *brow = B + (long)J * NO * ld + col;
+        double bv[NO];
+#pragma unroll
+        for (int b = 0; b < NO; ++b) bv[b] = (double)brow[(long)b * ld];
+        if (SCALE) {
+#pragma unroll
+            for (int b = 0; b < NO; ++b) bv[b] *= u[J * NO + b];
+        }
+#pragma unroll
+        for (int a = 0; a < NO; ++a)
+#pragma unroll
+            for (int b = 0; b < NO; ++b) acc[a] += (double)Yr[(long)a * ld + J * NO + b] * bv[b];
+    }
+}
 template <typename T, int NO>
 __global__ __launch_bounds__(256) void spmm_seed_kernel(SpmmArgs<T> p) {
-    __shared__ double yb[NB_MAX][NO * NO];
-    __shared__ int nbs[NB_MAX];
     const int I = blockIdx.y;
     const long bz = blockIdx.z;
     const int ld = p.ld;
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= ld) return;
     const int c = p.cnt[I];
     const double *u = p.u ? p.u + bz * p.su : nullptr;
-    for (int t = threadIdx.x; t < c * NO * NO; t += blockDim.x) {
-        const int e = t / (NO * NO), a = (t / NO) % NO, b = t % NO;
-        const int J = p.nb[I * NB_MAX + e];
-        if (a == 0 && b == 0) nbs[e] = J;
-        yb[e][a * NO + b] = (double)p.Y[(long)(I * NO + a) * ld + J * NO + b] *
-                            (u ? u[J * NO + b] : 1.0);
-    }
-    __syncthreads();
-    if (col >= ld) return;
+    const T *Yr = p.Y + (long)I * NO * ld;     // the atom's NO rows of Y
+    const int *nl = p.nb + I * NB_MAX;
     double acc[NO];
-#pragma unroll
-    for (int a = 0; a < NO; ++a) acc[a] = 0.0;
-    for (int e = 0; e < c; ++e) {
-        const T *brow = p.B + (long)nbs[e] * NO * ld + col;
-        double bv[NO];
-#pragma unroll
-        for (int b = 0; b < NO; ++b) bv[b] = (double)brow[(long)b * ld];
-#pragma unroll
-        for (int a = 0; a < NO; ++a)
-#pragma unroll
-            for (int b = 0; b < NO; ++b) acc[a] += yb[e][a * NO + b] * bv[b];
-    }
+    if (u) spmm_rows<T, NO, true>(Yr, p.B, nl, u, c, ld, col, acc);
+    else spmm_rows<T, NO, false>(Yr, p.B, nl, u, c, ld, col, acc);
 #pragma unroll
     for (int a = 0; a < NO; ++a) {
         const long o = (long)(I * NO + a) * ld + col;
