@@ -188,14 +188,18 @@ def charges(model, D):
     return np.diag(D).reshape(model.nat, model.no).sum(axis=1) - model.zcore
 
 
-def electronic(model, pos, n, H0=None, G=None):
-    """One-shot solve of the linearised functional at fixed n."""
+def electronic(model, pos, n, H0=None, G=None, eig=None):
+    """One-shot solve of the linearised functional at fixed n.
+
+    `eig` (default: `jacobi`) returns (eigenvalues, eigenvectors as rows);
+    a library eigensolver may stand in for Jacobi on matrices too large for
+    it, the rest of the solve being unchanged."""
     if H0 is None:
         H0 = model.h0(pos)
     if G is None:
         G = model.gamma(pos)
     H = H0 + np.diag(model.orbital_potential(G, n))
-    ev, Vt = jacobi(H)
+    ev, Vt = (eig or jacobi)(H)
     mu, f = fermi_mu(ev, model.beta, model.s.n_electrons)
     D = density(Vt, f)
     q = charges(model, D)
