@@ -21,9 +21,10 @@
 // the inverse of each level runs as split bf16x3 products and Z_{k+1} is
 // then corrected with the FP64 residual 2 Z_k - A_k Z_{k+1}: only A_k, the
 // residual, the seed, Z_L^2 and D stay FP64 products.  The chemical
-// potential follows from a Newton step
-// on Tr D in FP64 (rerun of the expansion if beta |dmu| is above a
-// threshold) and a first-order correction dD/dmu = (beta/2)(I - 4 Z_L^2).
+// potential follows in FP64 from the root of the quadratic model of Tr D
+// in mu (rerun of the expansion if beta |dmu| is above a threshold), and D
+// is corrected to second order with dD/dmu = (beta/2)(I - 4 Z_L^2) and
+// d2D/dmu2 = beta^2 (Z_L - 4 Z_L^3).
 //
 // Response (Section V.B).  Differentiating the same recursion along a
 // perturbation H1 = diag(Gamma v) gives, with Z'_0 from the seed,
@@ -1291,7 +1292,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
         const long s2 = 2 * sm;            // batch stride of split buffers
         if (sparse_seed() && Np == N) {
             // G = (Y D) Y and P = (Y D) Y^3 as sparse-dense products (the
-            // column scale on the staged Y blocks), H13 = Y D Y^3 + Y^3 D Y
+            // column scale applied to the rows of B), H13 = Y D Y^3 + Y^3 D Y
             // = P + P^T, and H2 = Y2 D Y2 on pre-split operands
             const dim3 cg(ceil_div(Np / 8, 256), Np, nb);
             hipLaunchKernelGGL(colscale_split_kernel, cg, dim3(256), 0, st, Np,
