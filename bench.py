@@ -164,9 +164,9 @@ def main():
     ap.add_argument("--serving-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the hot path is single-GPU "
-              "(see the sharding paragraph of the design notes); use --gpus 1",
-              file=sys.stderr)
+        print("bench.py runs on exactly one GPU: every system is stepped on one "
+              "device (independent systems shard by system, without "
+              "communication); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     from synth import make_system
