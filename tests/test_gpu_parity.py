@@ -291,3 +291,42 @@ def test_sparse_seed_forces_energy_fp64(gpu):
     print(f"{name}: dF {dF:.2e} rel dOmega {dO:.2e} dTS {abs(e['te_s'] - eo['te_s']):.2e}")
     g.close()
     assert dF < 1e-5 and dO < 1e-8
+
+
+def _leading_orbitals(base, no):
+    """The model restricted to the first `no` orbitals of every atom: onsite
+    energies, their jitter and the leading block of the hopping matrix, at
+    half filling."""
+    jit = base.onsite_jitter.reshape(base.n_atoms, base.n_orb)[:, :no]
+    return base.replace(n_orb=no, onsite=base.onsite[:no].copy(),
+                        onsite_jitter=np.ascontiguousarray(jit).reshape(-1),
+                        hop_block=np.ascontiguousarray(base.hop_block[:no, :no]),
+                        n_electrons=float(base.n_atoms * no))
+
+
+@pytest.mark.parametrize("no", [2, 3])
+def test_sparse_seed_other_orbital_counts(gpu, no):
+    """The sparse-dense seed kernel is compiled per orbital count (1 to 8);
+    the other tests run 1 and 4.  Two and three orbitals per atom on the
+    160-atom lattice: FP64 and MIXED_BF16X3 charges and one response against
+    the oracle."""
+    name, spec = SPARSE[0]
+    s = _leading_orbitals(_system(name, spec), no)
+    assert 4 * _max_neighbours(s) <= s.n_atoms
+    m = R.Model(s)
+    n = _rand_n(s.n_atoms, 3)
+    el = R.electronic(m, s.pos, n)
+    V = np.random.default_rng(8).standard_normal((1, s.n_atoms))
+    V /= np.linalg.norm(V)
+    ref = R.response(m, el, V[0])
+    for prec, tol_r in ((gpu.FP64, 1e-6), (gpu.MIXED_BF16X3, 1e-3)):
+        g = gpu.XLBOMD(s, precision=prec, scf_tol=1e-9)
+        q, rep = g.solve(n)
+        dv = g.response(V)[0]
+        g.close()
+        dq = np.abs(q - el.q).max()
+        err = np.abs(dv - ref).max() / np.abs(ref).max()
+        print(f"{no} orbitals, precision {prec}: max|dq| {dq:.2e}, response rel err "
+              f"{err:.2e}, L={rep['foe_levels']}")
+        assert dq < 1e-8
+        assert err < tol_r
