@@ -22,8 +22,8 @@ principles molecular dynamics"):
                       orthonormal directions, the first along K0 r.
   integration         Eq. 22 (velocity Verlet for the nuclei; the position
                       update is read with the velocity, not the
-                      acceleration) and
-                      Eq. 23 with the K_max = 5, 6, 7 rows of Table I.
+                      acceleration) and Eq. 23 with the K_max = 5, 6, 7
+                      rows of Table I.
   initial state       Eq. 20 with the ground state from the kernel SCF of
                       Eq. 52.
 """
