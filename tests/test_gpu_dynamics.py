@@ -282,3 +282,47 @@ def test_energy_conservation_split_path_c1(P):
     assert s3 < 1.5 * s64 + 1e-6
     # same initial ground state: the conserved level is the same
     assert abs(E3.mean() - E64.mean()) < s64 + 1e-6
+
+
+def _dt_rung(P, dt, t_end=8.0, nat=24):
+    """Mean distance of the GPU trajectory's n to the ground state at the same
+    geometry, and of its shadow free energy to the Born-Oppenheimer one,
+    sampled every 2 time units (ground states from the oracle's SCF at the
+    GPU's positions)."""
+    # the exact kernel (J - I)^-1, rebuilt every step (the full-rank
+    # Sherman-Morrison sequence equals it)
+    s = lattice_system(nat, "c1", seed=21, dt=dt, k0_gamma=0.1, rank=16,
+                       krylov_mode=2, kernel_every=1)
+    s = s.replace(mass=np.full(nat, 10.0))
+    m = R.Model(s)
+    g = P.XLBOMD(s, precision=P.FP64, scf_tol=1e-12)
+    every = int(round(2.0 / dt))
+    res, dom = [], []
+    for _ in range(int(round(t_end / dt)) // every):
+        g.step(every, report=False)
+        pos = g.get_state()["pos"]
+        n, _ = g.charges()
+        _, e = g.forces()
+        el_bo, _ = R.scf(m, pos, 0.1, nat, tol=1e-12, n0=n)
+        res.append(np.sqrt(np.mean((n - el_bo.n) ** 2)))
+        dom.append(abs(e["omega"] - R.free_energy(m, pos, el_bo)["omega"]))
+    g.close()
+    return np.mean(res), np.mean(dom)
+
+
+def test_dt_ladder_scaling(P):
+    """Section VI.C on the GPU path: halving dt divides the distance of n to
+    the ground state by ~4 (dt^2) and the shadow free energy's distance to
+    the Born-Oppenheimer free energy by ~16 (dt^4)."""
+    rungs = {dt: _dt_rung(P, dt) for dt in (0.4, 0.2, 0.1)}
+    for dt, (r, e) in rungs.items():
+        print(f"dt {dt}: rms(n - n_BO) {r:.3e}, |Omega - Omega_BO| {e:.3e}")
+    (r1, e1), (r2, e2) = rungs[0.4], rungs[0.2]
+    print(f"ratios 0.4/0.2: {r1 / r2:.2f} {e1 / e2:.2f}; 0.2/0.1: "
+          f"{r2 / rungs[0.1][0]:.2f} {e2 / rungs[0.1][1]:.2f}")
+    assert 3.0 < r1 / r2 < 5.5
+    assert 10.0 < e1 / e2 < 25.0
+    # closer to the asymptotic 4 and 16 one rung further down
+    (r3, e3) = rungs[0.1]
+    assert 3.5 < r2 / r3 < 4.5
+    assert 13.0 < e2 / e3 < 19.0
