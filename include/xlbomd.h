@@ -211,9 +211,12 @@ int xlbomd_kernel_apply(xlbomd_system *h, int32_t rank, const double *r,
  * Outputs (each nullable except n_eval): n_out (n_atoms) the last n;
  * rms_hist (max_iter + 1 entries) the RMS residual of every evaluated n;
  * *n_eval the number of evaluations.  XLBOMD_E_NOCONV if tol was not
- * reached (the outputs are still written).  The MD history and K r are not
- * touched; the handle's electronic state (charges, density) is left at the
- * last evaluated n. */
+ * reached within max_iter kernel updates (the outputs are still written).
+ * XLBOMD_E_DIVERGED if an iterate could not be evaluated (no chemical
+ * potential, non-finite spectral bounds) or its RMS residual is above 1e3;
+ * *n_eval and rms_hist then cover the evaluations before it, n_out is not
+ * written.  The MD history and K r are not touched; the handle's
+ * electronic state (charges, density) is left at the last evaluated n. */
 int xlbomd_scf(xlbomd_system *h, const double *n0, int32_t rank, double gamma, double tol,
                int32_t max_iter, double *n_out, double *rms_hist, int32_t *n_eval);
 

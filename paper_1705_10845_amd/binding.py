@@ -268,16 +268,22 @@ class XLBOMD:
 
     def scf(self, n0=None, rank=1, gamma=0.0, tol=1e-10, max_iter=100):
         """Kernel SCF (Eq. 52) at the current positions.  Returns
-        (n, rms history, converged)."""
+        (n, rms history, converged); a diverged iteration raises XlbomdError
+        (code -4) carrying the history so far as `rms_hist`."""
         n0 = None if n0 is None else _c(n0, (self.nat,))
         n = np.zeros(self.nat)
         hist = np.zeros(max_iter + 1)
         ne = ctypes.c_int32(0)
         rc = lib().xlbomd_scf(self._h, _ptr(n0), rank, gamma, tol, max_iter, _ptr(n),
                               _ptr(hist), ctypes.byref(ne))
+        done = hist[:ne.value].copy()
         if rc not in (0, -3):
-            _check(rc)
-        return n, hist[:ne.value].copy(), rc == 0
+            try:
+                _check(rc)
+            except XlbomdError as e:
+                e.rms_hist = done     # the evaluations before the failure
+                raise
+        return n, done, rc == 0
 
     def kernel_apply(self, rank, r):
         r = _c(r, (self.nat,))

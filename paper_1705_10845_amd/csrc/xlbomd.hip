@@ -760,13 +760,24 @@ struct SysBase {
         bool have = false, ok = false;
         int it = 0;
         ScfNeed need(scf_need, tol);
+        *n_eval = 0;
         try {
             for (;; ++it) {
-                solve(ncur, mu, have);
+                // an iterate the electronic solve cannot handle (no chemical
+                // potential, non-finite bounds) or a residual above 1e3 (as in
+                // the MD step; charges are bounded by the orbital count) means
+                // the iteration diverged; the evaluations so far stay reported
+                try {
+                    solve(ncur, mu, have);
+                } catch (const NoConv &e) {
+                    throw Diverged(std::string("scf diverged: ") + e.what());
+                }
                 have = true;
                 if (rms_hist) rms_hist[it] = rms;
+                *n_eval = it + 1;
+                if (!(rms <= 1e3)) throw Diverged("scf diverged: residual above 1e3");
                 if (rms <= tol) { ok = true; break; }
-                if (it >= max_iter || !std::isfinite(rms)) break;
+                if (it >= max_iter) break;
                 rank_prev = 0;
                 build_kernel(rank, 0, false, false);
                 apply_kernel(r, vtmp);
@@ -779,7 +790,6 @@ struct SysBase {
             throw;
         }
         d.k0_gamma = g_saved;
-        *n_eval = it + 1;
         sync();
         return ok;
     }
@@ -1870,9 +1880,8 @@ int xlbomd_scf(xlbomd_system *h, const double *n0, int32_t rank, double gamma, d
             XL_HIP(hipMemcpyAsync(s.ncur, n0, s.nat * sizeof(double), hipMemcpyHostToDevice, s.st));
         else
             XL_HIP(hipMemsetAsync(s.ncur, 0, s.nat * sizeof(double), s.st));
-        int ne = 0;
-        ok = s.scf_run(rank, gamma, tol, max_iter, rms_hist, &ne);
-        *n_eval = ne;
+        *n_eval = 0;
+        ok = s.scf_run(rank, gamma, tol, max_iter, rms_hist, n_eval);
         if (n_out)
             XL_HIP(hipMemcpyAsync(n_out, s.ncur, s.nat * sizeof(double), hipMemcpyDeviceToHost, s.st));
         s.sync();

@@ -69,3 +69,19 @@ def test_scf_reports_nonconvergence(P):
     n, hist, ok = g.scf(rank=0, gamma=0.1, tol=1e-14, max_iter=3)
     g.close()
     assert not ok and len(hist) == 4
+
+
+def test_scf_reports_divergence(P):
+    """An iterate far outside the charge range (n0 = +-1e6 per atom): its
+    residual is ~1e6, so the SCF stops at that evaluation with
+    XLBOMD_E_DIVERGED (not the max_iter code) and the history so far."""
+    s = make_system("c1")
+    g = P.XLBOMD(s, precision=P.FP64, scf_tol=1e-10)
+    n0 = 1e6 * np.where(np.arange(s.n_atoms) % 2 == 0, 1.0, -1.0)
+    with pytest.raises(P.XlbomdError) as e:
+        g.scf(n0=n0, rank=1, tol=1e-10, max_iter=20)
+    g.close()
+    h = e.value.rms_hist
+    print("error", e.value.code, str(e.value), "history", h)
+    assert e.value.code == -4
+    assert len(h) <= 1 and all(x > 1e3 for x in h)
