@@ -99,7 +99,7 @@ typedef struct {
     double te;                    /* electronic temperature, > 0            */
     double dt;                    /* time step, > 0                         */
     int32_t kmax;                 /* 5, 6 or 7: Table I row                 */
-    int32_t kernel_rank;          /* m >= 0 (0 = K0 only), m <= n_atoms     */
+    int32_t kernel_rank;          /* m in 0..min(n_atoms, 16) (0 = K0 only) */
     int32_t kernel_every;         /* rebuild the kernel every k steps (>=1) */
     int32_t krylov_mode;          /* 0 sequential Krylov, 1 block, 2 full
                                      kernel (J - I)^-1 from n_atoms responses
@@ -145,8 +145,10 @@ int xlbomd_init_system(const xlbomd_desc *desc, xlbomd_system **out);
 /* Advance n_steps XL-BOMD steps (Eqs. 22-23).  The free energy is
  * evaluated on steps whose index is a multiple of desc.energy_every.  If
  * last != NULL the report of the final step is written (its energy fields
- * are valid when has_energy is 1; xlbomd_forces evaluates them on demand).  Returns XLBOMD_E_DIVERGED if a non-finite value or a residual
- * above 1e3 appears; the state is then the last good step. */
+ * are valid when has_energy is 1; xlbomd_forces evaluates them on demand).
+ * Returns XLBOMD_E_DIVERGED if a non-finite value or a residual above 1e3
+ * appears.  The handle then holds the state of the failed step; to go on,
+ * restore a checkpoint taken with xlbomd_get_state via xlbomd_set_state. */
 int xlbomd_step(xlbomd_system *h, int32_t n_steps, xlbomd_report *last);
 
 /* Advance n_steps steps of `count` independent systems concurrently: each
