@@ -242,8 +242,9 @@ int xlbomd_selftest_gemm(int32_t n, int32_t precision, int32_t sym, const double
                          const double *B, double *C);
 
 /* Benchmark hook for the same kernel: average milliseconds per launch over
- * `reps` back-to-back launches on zero-filled n x n device operands
- * (dual != 0: two products concatenated along k, as in the response). */
+ * `reps` back-to-back launches on n x n device operands filled with
+ * pseudo-random values in [-1, 1) (dual != 0: two products concatenated
+ * along k, as in the response). */
 int xlbomd_selftest_gemm_time(int32_t n, int32_t precision, int32_t sym, int32_t dual,
                               int32_t reps, double *ms_per_launch);
 

@@ -1009,4 +1009,20 @@ __global__ __launch_bounds__(256) void lincomb_kernel(long ld, LinComb lc, doubl
     out[t] = v;
 }
 
+// x[i] in [-1, 1) from an integer hash of i (the lowbias32 mixer) and a
+// seed: benchmark operands whose bits vary as real data do (zeros would
+// understate the matrix cores' power draw)
+template <typename T>
+__global__ __launch_bounds__(256) void fill_hash_kernel(long n, unsigned seed, T *x) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned h = (unsigned)i ^ (unsigned)(i >> 32) ^ seed;
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    h *= 0x846ca68bu;
+    h ^= h >> 16;
+    x[i] = (T)((double)h * (2.0 / 4294967296.0) - 1.0);
+}
+
 }  // namespace xl

@@ -1970,8 +1970,13 @@ int xlbomd_selftest_gemm_time(int32_t n, int32_t precision, int32_t sym, int32_t
             using T = decltype(tag);
             T *a = dalloc<T>(nn), *b = dalloc<T>(nn), *c = dalloc<T>(nn);
             fr.ptrs = {a, b, c};
-            XL_HIP(hipMemset(a, 0, nn * sizeof(T)));
-            XL_HIP(hipMemset(b, 0, nn * sizeof(T)));
+            const unsigned nblk = (unsigned)((nn + 255) / 256);
+            hipLaunchKernelGGL((fill_hash_kernel<T>), dim3(nblk), dim3(256), 0, nullptr,
+                               (long)nn, 0x1705u, a);
+            XL_LAUNCH_CHECK();
+            hipLaunchKernelGGL((fill_hash_kernel<T>), dim3(nblk), dim3(256), 0, nullptr,
+                               (long)nn, 0x10845u, b);
+            XL_LAUNCH_CHECK();
             GemmArgs<T> ga;
             ga.n = n; ga.ld = n; ga.A0 = a; ga.B0 = b; ga.C = c;
             if (dual) { ga.A1 = b; ga.B1 = a; }
