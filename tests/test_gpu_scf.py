@@ -23,6 +23,9 @@ CASES = [
     ("c1", None, 3, 0.1),
     ("lat40", dict(n=40, tmpl="c2", seed=6), 1, 0.1),
     ("lat40", dict(n=40, tmpl="c2", seed=6), 4, 0.1),
+    # small gap (T_e = 0.02): one rank-1 update per iteration, 30 evaluations
+    # (at gamma = 0.1 the same iteration locks into a 2-cycle)
+    ("lat48", dict(n=48, tmpl="c3", seed=4, init_rank=8), 1, 0.01),
 ]
 
 
@@ -32,7 +35,8 @@ def test_scf_history_matches_oracle(P, name, spec, rank, gamma):
                                                               seed=spec["seed"])
     m = R.Model(s)
     el, ref = R.scf(m, s.pos, gamma, rank, tol=1e-10, max_iter=300)
-    g = P.XLBOMD(s.replace(rank=max(rank, 1)), precision=P.FP64, scf_tol=1e-10)
+    init_rank = (spec or {}).get("init_rank", max(rank, 1))
+    g = P.XLBOMD(s.replace(rank=init_rank), precision=P.FP64, scf_tol=1e-10)
     n, hist, ok = g.scf(rank=rank, gamma=gamma, tol=1e-10, max_iter=300)
     g.close()
     ref = np.array(ref)
