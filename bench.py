@@ -222,11 +222,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": "c2: 1024 atoms x 4 orbitals (N=4096) jittered cubic "
                                "lattice, Te=0.05, rank-4 sequential Krylov kernel every "
-                               "step, K_max=5; mixed path: density-matrix expansion "
-                               "with FP64 MFMA seed, A_k, residuals, Z_L^2 and D, level "
-                               "inverses in split bf16x3 refined against FP64 "
-                               "residuals; split bf16x3 MFMA kernel responses (FP32 "
-                               "accumulation); FP64 mu/Krylov/Verlet/energy sums",
+                               "step, K_max=5, free energy every 10th step; mixed "
+                               "path: density-matrix expansion with an FP64 "
+                               "sparse-dense seed, FP64 MFMA A_k, residuals, Z_L^2 "
+                               "and D, level inverses in split bf16x3 refined against "
+                               "FP64 residuals; split bf16x3 MFMA kernel responses "
+                               "(FP32 accumulation); FP64 mu/Krylov/Verlet/energy sums",
                    "n_orbitals": 4096, "kernel_rank": 4, "energy_every": ENERGY_EVERY,
                    "foe_levels": mixed["report"]["foe_levels"]},
         "roofline": roof(mixed["prof"], args.steps),
