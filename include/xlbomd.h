@@ -77,6 +77,21 @@ typedef enum {
                                 tolerance is below 1e-8)                   */
 } xlbomd_precision;
 
+/* Optional source of the device memory a system holds (PyTorch's caching
+ * allocator, a pool, a fixed arena).  alloc returns `bytes` of device memory
+ * on the current device, 256-byte aligned, or NULL (the call then fails
+ * with XLBOMD_E_NOMEM); free returns a pointer alloc gave.  The library
+ * calls alloc during xlbomd_init_system and, for buffers first needed
+ * later (responses of a larger batch, the energy workspace), inside other
+ * calls on the same handle, on the calling thread.  Every pointer goes back
+ * through free in xlbomd_destroy, after the handle's stream has drained.
+ * The struct is copied at init; ctx must stay valid until xlbomd_destroy. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} xlbomd_allocator;
+
 /* System descriptor.  Model (orthogonal SCC tight binding):
  *   H0[Ia,Ia] = onsite[a] + onsite_jitter[Ia]
  *   H0[Ia,Jb] = hop_block[a*n_orb+b] exp(-r/hop_decay) s(r), I != J, r < hop_cutoff
@@ -119,6 +134,8 @@ typedef struct {
                                      inside xlbomd_step)                    */
     void *stream;                 /* hipStream_t to run on; NULL = library's
                                      own stream                             */
+    const xlbomd_allocator *allocator; /* device memory source; NULL =
+                                     hipMalloc / hipFree                    */
 } xlbomd_desc;
 
 typedef struct {

@@ -19,6 +19,50 @@ FP64, FP32, MIXED, MIXED_BF16X3 = 0, 1, 2, 3
 _dp = ctypes.POINTER(ctypes.c_double)
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    """xlbomd_allocator: the device-memory source of a system."""
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+class TorchAllocator:
+    """Device memory for a system from PyTorch's caching allocator.
+
+    Every buffer the library asks for is a uint8 tensor on `device` (sizes
+    rounded up to 256 bytes; the caching allocator's blocks are 512-byte
+    aligned), held here until the library gives it back at xlbomd_destroy.
+    """
+
+    def __init__(self, device=None):
+        import torch
+        self._torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.live = {}
+
+        def _alloc(nbytes, ctx):
+            try:
+                t = self._torch.empty(((int(nbytes) + 255) // 256) * 256,
+                                      dtype=self._torch.uint8, device=self.device)
+            except Exception:
+                return None
+            self.live[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def _free(ptr, ctx):
+            self.live.pop(ptr, None)
+
+        self._fns = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+        self.struct = Allocator(self._fns[0], self._fns[1], None)
+
+    @property
+    def bytes_held(self):
+        return sum(t.numel() for t in self.live.values())
+
+
 class Desc(ctypes.Structure):
     _fields_ = [
         ("n_atoms", ctypes.c_int32), ("n_orb", ctypes.c_int32),
@@ -34,6 +78,7 @@ class Desc(ctypes.Structure):
         ("k0_gamma", ctypes.c_double), ("precision", ctypes.c_int32),
         ("scf_tol", ctypes.c_double), ("scf_max_iter", ctypes.c_int32),
         ("energy_every", ctypes.c_int32), ("stream", ctypes.c_void_p),
+        ("allocator", ctypes.POINTER(Allocator)),
     ]
 
 
@@ -64,6 +109,16 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} missing: run "
                               "python -m paper_1705_10845_amd.build")
+        # PyTorch carries a HIP runtime of its own.  Initialised first, it is
+        # the one the library binds to, so torch streams and torch memory
+        # (TorchAllocator) are valid in library calls; loaded the other way
+        # round, torch would find no GPU.
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp = ctypes.c_void_p
         L.xlbomd_init_system.argtypes = [ctypes.POINTER(Desc),
@@ -170,7 +225,10 @@ class XLBOMD:
     """One system living on the GPU (a library handle)."""
 
     def __init__(self, system, precision=FP64, scf_tol=None, scf_max_iter=300,
-                 energy_every=0, stream=None, **override):
+                 energy_every=0, stream=None, allocator=None, **override):
+        """allocator: None (hipMalloc), "torch" (a TorchAllocator on the
+        current device) or an object with a ctypes `struct` (Allocator);
+        it is kept alive with the handle."""
         s = system.replace(**override) if override else system
         self.nat, self.no = int(s.n_atoms), int(s.n_orb)
         self.kmax = int(s.kmax)
@@ -193,6 +251,11 @@ class XLBOMD:
             1e-6 if precision == FP32 else 1e-10)
         d.scf_max_iter, d.energy_every = scf_max_iter, energy_every
         d.stream = stream
+        if allocator == "torch":
+            allocator = TorchAllocator()
+        self.allocator = allocator
+        if allocator is not None:
+            d.allocator = ctypes.pointer(allocator.struct)
         self._h = ctypes.c_void_p()
         _check(lib().xlbomd_init_system(ctypes.byref(d), ctypes.byref(self._h)))
 

@@ -84,10 +84,16 @@ template <typename T> T *dalloc(size_t n) {
     return (T *)p;
 }
 
+// Device buffers of one system, returned at destruction to the allocator
+// that gave them (the caller's xlbomd_allocator, else hipFree).
 struct DevFree {
     std::vector<void *> ptrs;
+    xlbomd_allocator al{};
     ~DevFree() {
-        for (void *p : ptrs) (void)hipFree(p);
+        for (void *p : ptrs) {
+            if (al.free) al.free(p, al.ctx);
+            else (void)hipFree(p);
+        }
     }
 };
 
@@ -208,6 +214,22 @@ struct SysBase {
     hipStream_t st = nullptr;
     bool own_stream = false;
     DevFree mem;
+    // n elements of device memory owned by the system: from the caller's
+    // allocator when the descriptor gives one, else hipMalloc
+    template <typename T> T *dev(size_t n) {
+        if (!mem.al.alloc) {
+            T *p = dalloc<T>(n);
+            mem.ptrs.push_back(p);
+            return p;
+        }
+        const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+        void *p = mem.al.alloc(bytes, mem.al.ctx);
+        if (!p) throw NoMem("allocator returned no memory for " + std::to_string(bytes) + " bytes");
+        if (reinterpret_cast<uintptr_t>(p) % 256)
+            throw InvalidArg("allocator memory must be 256-byte aligned");
+        mem.ptrs.push_back(p);
+        return (T *)p;
+    }
     ModelDev md{};
 
     // device arrays (FP64)
@@ -271,6 +293,8 @@ struct SysBase {
 
     void upload_model(const xlbomd_desc *ds) {
         d = *ds;
+        if (d.allocator) mem.al = *d.allocator;   // kept by value
+        d.allocator = nullptr;
         nat = d.n_atoms;
         no = d.n_orb;
         N = nat * no;
@@ -285,8 +309,7 @@ struct SysBase {
         }
         auto A = [&](auto *&p, size_t n) {
             using E = std::remove_pointer_t<std::remove_reference_t<decltype(p)>>;
-            p = dalloc<E>(n);
-            mem.ptrs.push_back(p);
+            p = dev<E>(n);
         };
         A(pos, 3 * nat); A(vel, 3 * nat); A(mass, nat); A(force, 3 * nat);
         A(onsite, no); A(jit, N); A(hop, no * no); A(U, nat);
@@ -590,13 +613,11 @@ struct SysBase {
     bool full_built = false;
     void build_full_kernel() {
         if (!gj) {
-            gj = dalloc<double>((size_t)2 * nat * nat);
-            gjf = dalloc<double>(nat);
-            dirs = dalloc<double>((size_t)mcap * nat);
-            qdir = dalloc<double>((size_t)mcap * nat);
-            gjflag = dalloc<int>(1);
-            mem.ptrs.push_back(gj); mem.ptrs.push_back(gjf); mem.ptrs.push_back(dirs);
-            mem.ptrs.push_back(qdir); mem.ptrs.push_back(gjflag);
+            gj = dev<double>((size_t)2 * nat * nat);
+            gjf = dev<double>(nat);
+            dirs = dev<double>((size_t)mcap * nat);
+            qdir = dev<double>((size_t)mcap * nat);
+            gjflag = dev<int>(1);
         }
         for (int i0 = 0; i0 < nat; i0 += mcap) {
             const int nb = std::min(mcap, nat - i0);
@@ -816,9 +837,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
 
     size_t mat() const { return (size_t)Np * Np; }
     template <typename U> U *amat() {
-        U *p = dalloc<U>(mat());
-        mem.ptrs.push_back(p);
-        return p;
+        return this->template dev<U>(mat());
     }
     int levels_cap() const override { return Lcap; }
 
@@ -848,23 +867,18 @@ template <typename TF, typename TR> struct Sys : SysBase {
         if (!Ys) {
             Ys = amat<TF>(); Y2 = amat<TF>(); Y3 = amat<TF>(); E = amat<TF>();
             Wk = amat<TF>(); Dc = amat<TF>(); ZL2 = amat<TF>();
-            m3 = dalloc<double>(Np);
-            mem.ptrs.push_back(m3);
+            m3 = this->template dev<double>(Np);
         }
         Lcap = cap;
     }
     void alloc_resp(int nb) {
         if (nb <= bcap) return;
-        TR *zp = dalloc<TR>(mat() * nb), *ap = dalloc<TR>(mat() * nb), *tb = dalloc<TR>(mat() * nb);
-        mem.ptrs.push_back(zp); mem.ptrs.push_back(ap); mem.ptrs.push_back(tb);
+        TR *zp = this->template dev<TR>(mat() * nb), *ap = this->template dev<TR>(mat() * nb),
+           *tb = this->template dev<TR>(mat() * nb);
         Zp = zp; Ap = ap; Tb = tb;
         if (resp_split) {
-            Xb = dalloc<TR>(mat() * nb);
-            mem.ptrs.push_back(Xb);
-            for (auto &q : Sd) {
-                q = dalloc<TR>(mat() * nb);
-                mem.ptrs.push_back(q);
-            }
+            Xb = this->template dev<TR>(mat() * nb);
+            for (auto &q : Sd) q = this->template dev<TR>(mat() * nb);
         }
         bcap = nb;
     }
@@ -898,8 +912,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
             if (sizeof(U) == 4)     // the split products' 256 x 128 tiles
                 wn = std::max({wn, split_bs_ws_elems(Np, true, 1, 1),
                                split_bs_ws_elems(Np, false, 1, 1)});
-            w = dalloc<U>(wn);
-            mem.ptrs.push_back(w);
+            w = this->template dev<U>(wn);
         }
         a.ws = (U *)w;
         a.ws_elems = wn;
@@ -1309,8 +1322,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
                                (const float *)Y2r, ub, (long)Np, s16(Sd[1]), sm, s2);
             XL_LAUNCH_CHECK();
             if (!Pb || pb_cap < nb) {
-                Pb = dalloc<double>(mat() * nb);
-                mem.ptrs.push_back(Pb);
+                Pb = this->template dev<double>(mat() * nb);
                 pb_cap = nb;
             }
             SpmmArgs<TF> a{};
@@ -1453,8 +1465,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
     // correction adds dmu <X_eff, (1/2)(I - 4 Z_L^2)>.
     double *w64(int i) {
         if (!e64[i]) {
-            e64[i] = dalloc<double>(mat());
-            mem.ptrs.push_back(e64[i]);
+            e64[i] = this->template dev<double>(mat());
         }
         return e64[i];
     }
@@ -1473,13 +1484,10 @@ template <typename TF, typename TR> struct Sys : SysBase {
     int chol_cap = 0;
     double *chol_batch(int nb) {       // nb padded Np x Np FP64 matrices
         if (nb > chol_cap) {
-            cholA = dalloc<double>(mat() * nb);
-            cholP = dalloc<double>((size_t)NB * Np * nb);
-            mem.ptrs.push_back(cholA);
-            mem.ptrs.push_back(cholP);
+            cholA = this->template dev<double>(mat() * nb);
+            cholP = this->template dev<double>((size_t)NB * Np * nb);
             if (!cholOut) {
-                cholOut = dalloc<double>(16);
-                mem.ptrs.push_back(cholOut);
+                cholOut = this->template dev<double>(16);
             }
             chol_cap = nb;
         }
@@ -1635,6 +1643,8 @@ void validate(const xlbomd_desc *d) {
     if (!d) throw InvalidArg("null descriptor");
     if (d->n_atoms <= 0 || d->n_orb <= 0 || d->n_orb > 8)
         throw InvalidArg("n_atoms must be > 0 and n_orb in 1..8");
+    if (d->allocator && (!d->allocator->alloc || !d->allocator->free))
+        throw InvalidArg("allocator needs both alloc and free");
     if (!d->pos || !d->mass || !d->onsite || !d->hop_block || !d->hubbard_u)
         throw InvalidArg("pos, mass, onsite, hop_block and hubbard_u are required");
     const double n2 = 2.0 * d->n_atoms * d->n_orb;

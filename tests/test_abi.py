@@ -32,9 +32,32 @@ def test_library_exports_every_declared_symbol():
     assert L.xlbomd_version().startswith(b"xlbomd")
 
 
-def test_struct_layout_matches_header():
+def test_struct_layout_matches_header(tmp_path):
+    """Every field offset and the size of the descriptor, the report and the
+    allocator struct, from a C program compiled against the header, equal
+    the ctypes layouts the binding passes."""
     import ctypes
-    # 2 int32 + 6 pointers + 3 doubles + pointer + 6 doubles + 4 int32 +
-    # double + int32 (+pad) + double + 2 int32 + pointer
-    assert ctypes.sizeof(binding.Desc) == 8 + 48 + 24 + 8 + 48 + 16 + 8 + 8 + 8 + 8 + 8
-    assert ctypes.sizeof(binding.Report) == 10 * 8 + 7 * 4 + 4 + 8
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = (("xlbomd_desc", binding.Desc), ("xlbomd_report", binding.Report),
+               ("xlbomd_allocator", binding.Allocator))
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "xlbomd.h"',
+             "int main(void) {"]
+    for cname, py in structs:
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'    printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out.splitlines()}
+    for cname, py in structs:
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -1,0 +1,64 @@
+"""Device memory from a caller-supplied allocator (xlbomd_allocator), here
+PyTorch's caching allocator, against the library's own hipMalloc."""
+import numpy as np
+import pytest
+
+from synth import make_system
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1705_10845_amd as P
+    P.lib()
+    return P
+
+
+def test_torch_allocator_matches_hipmalloc(P):
+    """Ten steps of the 64-atom cluster with memory from torch: the same
+    trajectory as with hipMalloc, the buffers held as torch tensors while the
+    handle lives (including the energy workspace allocated on demand), and
+    every one given back at close."""
+    import torch
+    s = make_system("c1")
+    runs = {}
+    for alloc in (None, "torch"):
+        g = P.XLBOMD(s, precision=P.FP64, scf_tol=1e-10, energy_every=5, allocator=alloc)
+        rep = g.step(10)
+        n, q = g.charges()
+        F, e = g.forces()
+        a = g.allocator
+        held = a.bytes_held if a is not None else 0
+        torch_mem = torch.cuda.memory_allocated()
+        g.close()
+        runs[alloc] = dict(n=n, q=q, F=F, E=rep["e_total"], held=held, a=a, tm=torch_mem)
+    r0, r1 = runs[None], runs["torch"]
+    print(f"torch allocator held {r1['held'] / 1e6:.1f} MB in {len(r1['a'].live)} live tensors "
+          f"after close; dq {np.abs(r0['q'] - r1['q']).max():.1e}")
+    assert r1["held"] > 0 and r1["tm"] >= r1["held"]
+    assert len(r1["a"].live) == 0
+    assert np.abs(r0["n"] - r1["n"]).max() < 1e-12
+    assert np.abs(r0["q"] - r1["q"]).max() < 1e-12
+    assert np.abs(r0["F"] - r1["F"]).max() < 1e-10
+    assert abs(r0["E"] - r1["E"]) < 1e-10 * abs(r0["E"])
+
+
+class _Alloc:
+    def __init__(self, P, alloc, free):
+        self.struct = P.Allocator(alloc, free, None)
+
+
+def test_allocator_errors(P):
+    """An allocator without free is rejected; one that returns no memory
+    fails the init with XLBOMD_E_NOMEM."""
+    B = P.binding
+    s = make_system("c1")
+    no_free = _Alloc(P, B._ALLOC_FN(lambda n, c: None), B._FREE_FN())
+    with pytest.raises(P.XlbomdError) as e:
+        P.XLBOMD(s, precision=P.FP64, allocator=no_free)
+    assert e.value.code == -1
+    empty = _Alloc(P, B._ALLOC_FN(lambda n, c: None), B._FREE_FN(lambda p, c: None))
+    with pytest.raises(P.XlbomdError) as e:
+        P.XLBOMD(s, precision=P.FP64, allocator=empty)
+    assert e.value.code == -2
