@@ -136,6 +136,11 @@ typedef struct {
                                      own stream                             */
     const xlbomd_allocator *allocator; /* device memory source; NULL =
                                      hipMalloc / hipFree                    */
+    int32_t foe_levels;           /* 0: the smallest level count meeting the
+                                     truncation target on the spectral
+                                     interval (2e-10 FP64, 1e-9 otherwise);
+                                     1..40: that count, raised where the
+                                     seed would leave |x / 2^(L+1)| <= 1   */
 } xlbomd_desc;
 
 typedef struct {

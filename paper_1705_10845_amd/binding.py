@@ -78,7 +78,7 @@ class Desc(ctypes.Structure):
         ("k0_gamma", ctypes.c_double), ("precision", ctypes.c_int32),
         ("scf_tol", ctypes.c_double), ("scf_max_iter", ctypes.c_int32),
         ("energy_every", ctypes.c_int32), ("stream", ctypes.c_void_p),
-        ("allocator", ctypes.POINTER(Allocator)),
+        ("allocator", ctypes.POINTER(Allocator)), ("foe_levels", ctypes.c_int32),
     ]
 
 
@@ -225,10 +225,11 @@ class XLBOMD:
     """One system living on the GPU (a library handle)."""
 
     def __init__(self, system, precision=FP64, scf_tol=None, scf_max_iter=300,
-                 energy_every=0, stream=None, allocator=None, **override):
+                 energy_every=0, stream=None, allocator=None, foe_levels=0, **override):
         """allocator: None (hipMalloc), "torch" (a TorchAllocator on the
         current device) or an object with a ctypes `struct` (Allocator);
-        it is kept alive with the handle."""
+        it is kept alive with the handle.  foe_levels: 0 chooses the level
+        count from the truncation target, 1..40 requests one."""
         s = system.replace(**override) if override else system
         self.nat, self.no = int(s.n_atoms), int(s.n_orb)
         self.kmax = int(s.kmax)
@@ -251,6 +252,7 @@ class XLBOMD:
             1e-6 if precision == FP32 else 1e-10)
         d.scf_max_iter, d.energy_every = scf_max_iter, energy_every
         d.stream = stream
+        d.foe_levels = foe_levels
         if allocator == "torch":
             allocator = TorchAllocator()
         self.allocator = allocator

@@ -954,6 +954,12 @@ template <typename TF, typename TR> struct Sys : SysBase {
         // truncation bound of the expansion vs the Fermi function: 2e-10 for
         // the all-FP64 mode, 1e-9 (charges within 1e-8) otherwise
         L = choose_levels(xmax, d.precision == XLBOMD_FP64 ? 2e-10 : 1e-9);
+        if (d.foe_levels > 0) {
+            // a requested count, raised where the seed would leave |y| <= 1
+            int Lmin = 1;
+            while (Lmin < 40 && std::ldexp(xmax, -(Lmin + 1)) > 1.0) ++Lmin;
+            L = std::max(d.foe_levels, Lmin);
+        }
         alloc_matrices(L);
         Lr = -1;
         ++expansion_id;
@@ -1655,6 +1661,7 @@ void validate(const xlbomd_desc *d) {
     if (d->kernel_rank < 0 || d->kernel_rank > d->n_atoms || d->kernel_rank > 16)
         throw InvalidArg("kernel_rank must be in 0..min(n_atoms, 16)");
     if (d->kernel_every < 1) throw InvalidArg("kernel_every must be >= 1");
+    if (d->foe_levels < 0 || d->foe_levels > 40) throw InvalidArg("foe_levels must be in 0..40");
     if (d->krylov_mode < 0 || d->krylov_mode > 2) throw InvalidArg("krylov_mode is 0, 1 or 2");
     if (!(d->k0_gamma >= 0.0 && d->k0_gamma <= 1.0))
         throw InvalidArg("k0_gamma must be in (0, 1], or 0 for the automatic rule");

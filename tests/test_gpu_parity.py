@@ -330,3 +330,30 @@ def test_sparse_seed_other_orbital_counts(gpu, no):
               f"{err:.2e}, L={rep['foe_levels']}")
         assert dq < 1e-8
         assert err < tol_r
+
+
+def test_requested_level_count(gpu):
+    """foe_levels in the descriptor: one level more than the automatic count
+    is used as asked; a request of 1 is raised to the smallest count that
+    keeps the seed's argument within [-1, 1].  Charges of every run against
+    the oracle (the raised count's truncation bound, 5.9e-10 per orbital at
+    this spectral range, keeps them within 1e-8)."""
+    name, spec = CASES[1]
+    s = _system(name, spec)
+    m = R.Model(s)
+    n = _rand_n(s.n_atoms, 1)
+    el = R.electronic(m, s.pos, n)
+    out = {}
+    for req in (0, None, 1):
+        lv = 0 if req is None else req
+        if req is None:
+            lv = out[0][1] + 1
+        g = gpu.XLBOMD(s, precision=gpu.FP64, scf_tol=1e-9, foe_levels=lv)
+        q, rep = g.solve(n)
+        g.close()
+        out[req] = (np.abs(q - el.q).max(), rep["foe_levels"])
+        print(f"foe_levels {lv}: L = {rep['foe_levels']}, max|dq| {out[req][0]:.2e}")
+    auto_l = out[0][1]
+    assert out[None][1] == auto_l + 1
+    assert 1 < out[1][1] <= auto_l
+    assert all(v[0] < 1e-8 for v in out.values())
