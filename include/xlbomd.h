@@ -156,6 +156,9 @@ typedef struct {
     int32_t foe_levels, ns_iters, mu_reruns, scf_iters, kernel_rank;
     int32_t has_energy;/* 1 if the energy fields are valid                  */
     double k0_gamma;   /* the K0 constant in use                            */
+    double ms_step;    /* device time of the reported step in milliseconds
+                          (HIP events on the handle's stream; xlbomd_step
+                          only, 0 elsewhere)                                 */
 } xlbomd_report;
 
 /* Create a system: copies the descriptor's arrays to the device, solves the

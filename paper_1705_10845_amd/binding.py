@@ -87,7 +87,8 @@ class Report(ctypes.Structure):
         "omega", "e_band", "e_coul", "e_rep", "te_s", "e_kin", "e_total",
         "rms_res", "mu", "d_nelec")] + [(k, ctypes.c_int32) for k in (
             "step", "foe_levels", "ns_iters", "mu_reruns", "scf_iters",
-            "kernel_rank", "has_energy")] + [("k0_gamma", ctypes.c_double)]
+            "kernel_rank", "has_energy")] + [("k0_gamma", ctypes.c_double),
+                                             ("ms_step", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -256,6 +256,21 @@ struct SysBase {
 
     // Optional live timing of the dense products with HIP events recorded on
     // the library stream around each launch.
+    // duration of a step on the stream (reported when a report is asked)
+    hipEvent_t step_ev[2] = {nullptr, nullptr};
+    void step_timer(bool start) {
+        if (!step_ev[0]) {
+            XL_HIP(hipEventCreate(&step_ev[0]));
+            XL_HIP(hipEventCreate(&step_ev[1]));
+        }
+        XL_HIP(hipEventRecord(step_ev[start ? 0 : 1], st));
+    }
+    double step_ms() {
+        XL_HIP(hipEventSynchronize(step_ev[1]));
+        float ms = 0.f;
+        XL_HIP(hipEventElapsedTime(&ms, step_ev[0], step_ev[1]));
+        return ms;
+    }
     struct Prof {
         bool on = false;
         std::vector<hipEvent_t> ev;
@@ -1708,7 +1723,13 @@ int xlbomd_step(xlbomd_system *h, int32_t n_steps, xlbomd_report *last) {
             const int ev = s.d.energy_every;
             const bool is_last = (i + 1 == n_steps);
             const bool want = ev > 0 && ((s.step_no + 1) % ev == 0);
+            const bool timed = is_last && last;
+            if (timed) s.step_timer(true);
             s.md_step(want, is_last ? last : nullptr);
+            if (timed) {
+                s.step_timer(false);
+                last->ms_step = s.step_ms();
+            }
         }
         s.sync();
     });
@@ -2067,6 +2088,8 @@ void xlbomd_destroy(xlbomd_system *h) {
         (void)hipStreamSynchronize(h->s->st);
         if (h->s->hscal) (void)hipHostFree(h->s->hscal);
         for (hipEvent_t e : h->s->prof.ev) (void)hipEventDestroy(e);
+        for (hipEvent_t e : h->s->step_ev)
+            if (e) (void)hipEventDestroy(e);
         if (h->s->own_stream) (void)hipStreamDestroy(h->s->st);
     }
     delete h;

@@ -326,3 +326,16 @@ def test_dt_ladder_scaling(P):
     (r3, e3) = rungs[0.1]
     assert 3.5 < r2 / r3 < 4.5
     assert 13.0 < e2 / e3 < 19.0
+
+
+def test_report_step_time(P):
+    """The report of xlbomd_step carries the device time of its last step,
+    and the forces call, which runs no step, reports none."""
+    s = make_system("c1")
+    g = P.XLBOMD(s, precision=P.FP64, scf_tol=1e-10)
+    rep = g.step(3)
+    _, e = g.forces()
+    g.close()
+    print(f"ms_step {rep['ms_step']:.3f}")
+    assert 0.0 < rep["ms_step"] < 1e4
+    assert e["ms_step"] == 0.0
