@@ -46,6 +46,8 @@ __global__ __launch_bounds__(CHOL_PT) void chol_panel_kernel(int n, int ld, int 
     acc += blockIdx.y;
     __shared__ double Ld[CB][CB + 1];        // factored diagonal block
     const int w = q - p, lane = threadIdx.x;
+    // w is a multiple of CB: eight independent loads in flight per thread
+#pragma unroll 8
     for (int t = lane; t < CB * w; t += CHOL_PT)
         Lp[t / w][t % w] = A[(long)(q + t / w) * ld + p + t % w];
     __syncthreads();
@@ -90,6 +92,7 @@ __global__ __launch_bounds__(CHOL_PT) void chol_panel_kernel(int n, int ld, int 
     double *rowp = A + (long)i * ld;
 #pragma unroll
     for (int j = 0; j < CB; ++j) x[j] = rowp[q + j];
+#pragma unroll 8
     for (int k = 0; k < w; ++k) {
         const double lik = rowp[p + k];
 #pragma unroll
