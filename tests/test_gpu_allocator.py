@@ -62,3 +62,51 @@ def test_allocator_errors(P):
     with pytest.raises(P.XlbomdError) as e:
         P.XLBOMD(s, precision=P.FP64, allocator=empty)
     assert e.value.code == -2
+
+
+def test_torch_allocator_under_batch_stepping(P):
+    """Three systems share one TorchAllocator and step together through
+    xlbomd_step_batch, evaluating the free energy every other step.  The
+    energy workspace, allocated on demand at the first evaluation, comes
+    through the Python callback from the library's worker threads.
+    The charges equal those of the same systems stepped alone on hipMalloc
+    memory, and every buffer is given back when the handles close."""
+    import threading
+    from synth import lattice_system
+    from paper_1705_10845_amd.binding import step_batch
+
+    def systems():
+        return [lattice_system(n, "c4", seed=100 + n, rank=r)
+                for n, r in ((16, 2), (40, 3), (70, 4))]
+
+    alone = []
+    for s in systems():
+        g = P.XLBOMD(s, precision=P.MIXED, energy_every=2)
+        g.step(5, report=False)
+        alone.append(g.charges()[1])
+        g.close()
+
+    a = P.TorchAllocator()
+    inner = a._fns[0]
+    callers = []
+
+    def alloc(n, ctx):
+        callers.append(threading.get_ident())
+        return inner(n, ctx)
+
+    fn = P.binding._ALLOC_FN(alloc)
+    a._fns = (fn, a._fns[1], inner)
+    a.struct = P.Allocator(fn, a._fns[1], None)
+
+    gs = [P.XLBOMD(s, precision=P.MIXED, energy_every=2, allocator=a) for s in systems()]
+    n_init = len(callers)
+    reps, st, rc = step_batch(gs, 5)
+    assert rc == 0 and st == [0, 0, 0]
+    workers = {t for t in callers[n_init:] if t != threading.get_ident()}
+    print(f"{n_init} allocations at init, {len(callers) - n_init} inside the batch "
+          f"from {len(workers)} worker threads; {a.bytes_held / 1e6:.1f} MB held")
+    assert workers
+    for g, q in zip(gs, alone):
+        assert np.abs(g.charges()[1] - q).max() <= 1e-12
+        g.close()
+    assert len(a.live) == 0
