@@ -357,3 +357,35 @@ def test_requested_level_count(gpu):
     assert out[None][1] == auto_l + 1
     assert 1 < out[1][1] <= auto_l
     assert all(v[0] < 1e-8 for v in out.values())
+
+
+@pytest.mark.parametrize("tmpl", ["c1", "c2"])
+@pytest.mark.parametrize("prec_name", ["FP64", "MIXED_BF16X3"])
+def test_single_atom(gpu, tmpl, prec_name):
+    """The degenerate system of one atom (1 orbital, or 4).  The electron
+    count fixes its net charge at zero, so the residual, the kernel's
+    direction, K r and the force all vanish, and the atom moves in a straight
+    line.  The free energy is the oracle's; for one orbital at half filling
+    mu sits on the level and T S = 2 T ln 2 exactly."""
+    prec = getattr(gpu, prec_name)
+    vel = np.array([[0.1, -0.2, 0.05]])
+    s = lattice_system(1, tmpl, seed=8, rank=1).replace(vel=vel)
+    st = R.init_state(R.Model(s), scf_tol=1e-11)
+    g = gpu.XLBOMD(s, precision=prec, scf_tol=1e-9)
+    F, e = g.forces()
+    n, q = g.charges()
+    dO = abs(e["omega"] - st.energy["omega"]) / abs(st.energy["omega"])
+    print(f"{tmpl} {prec_name}: q {q[0]:.1e} |F| {np.abs(F).max():.1e} rel dOmega {dO:.1e} "
+          f"TS {e['te_s']:.15f} (oracle {st.energy['te_s']:.15f})")
+    qtol = 1e-12 if prec == gpu.FP64 else 1e-9
+    assert abs(q[0]) < qtol and np.abs(F).max() < 1e-12
+    assert dO < 1e-8
+    if tmpl == "c1":
+        assert abs(e["te_s"] - 2.0 * s.te * np.log(2.0)) < 1e-8 * e["te_s"]
+    steps = 10
+    g.step(steps, report=False)
+    state = g.get_state()
+    assert np.abs(state["pos"] - (s.pos + steps * s.dt * vel)).max() < 1e-12
+    assert np.abs(state["vel"] - vel).max() < 1e-12
+    assert np.abs(state["n_hist"]).max() < qtol and np.abs(state["kr"]).max() < qtol
+    g.close()
