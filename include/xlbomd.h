@@ -100,7 +100,9 @@ typedef struct {
  *   E_rep = sum_{I<J} rep_a exp(-r/rep_decay) s(r)
  *   q_I = sum_a D[Ia,Ia] - n_electrons/n_atoms */
 typedef struct {
-    int32_t n_atoms, n_orb;
+    int32_t n_atoms, n_orb;       /* n_orb in 1..8; N = n_atoms*n_orb at most
+                                     46336, so that a padded N x N matrix has
+                                     fewer than 2^31 elements               */
     const double *pos;            /* n_atoms*3                              */
     const double *vel;            /* n_atoms*3, NULL = zero                 */
     const double *mass;           /* n_atoms                                */

@@ -1664,6 +1664,9 @@ void validate(const xlbomd_desc *d) {
     if (!d) throw InvalidArg("null descriptor");
     if (d->n_atoms <= 0 || d->n_orb <= 0 || d->n_orb > 8)
         throw InvalidArg("n_atoms must be > 0 and n_orb in 1..8");
+    // a padded N x N matrix stays below 2^31 elements (46336 = 362 * 128)
+    if ((long)d->n_atoms * d->n_orb > 46336)
+        throw InvalidArg("n_atoms * n_orb must be at most 46336");
     if (d->allocator && (!d->allocator->alloc || !d->allocator->free))
         throw InvalidArg("allocator needs both alloc and free");
     if (!d->pos || !d->mass || !d->onsite || !d->hop_block || !d->hubbard_u)

@@ -26,6 +26,8 @@ def _small(**kw):
 CASES = [
     ("empty", dict(n_atoms=0), "n_atoms"),
     ("negative atoms", dict(n_atoms=-3), "n_atoms"),
+    ("above the size limit", dict(n_atoms=46337), "n_atoms * n_orb"),
+    ("size limit by orbitals", dict(n_atoms=5793, n_orb=8), "n_atoms * n_orb"),
     ("no orbitals", dict(n_orb=0), "n_orb"),
     ("nine orbitals", dict(n_orb=9), "n_orb"),
     ("no electrons", dict(n_electrons=0.0), "n_electrons"),
