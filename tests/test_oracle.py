@@ -97,6 +97,51 @@ def test_dimer_closed_form():
     assert abs(np.sum(el.H0 * el.D) - cf["eband"]) < 1e-13
 
 
+
+def _fermi_entropy(f):
+    """Per-orbital entropy -[f ln f + (1-f) ln(1-f)] of an occupation f."""
+    return -(f * math.log(f) + (1.0 - f) * math.log(1.0 - f))
+
+
+@pytest.mark.parametrize("ne", [0.3, 1.0, 1.7])
+def test_single_orbital_atom_closed_form(ne):
+    """One atom with one orbital: H is the scalar h = onsite + jitter, D is
+    the electron count itself, 2 f(beta (h - mu)) = ne gives
+    mu = h - T ln(2/ne - 1), the net charge and the force vanish, the band
+    energy is h ne and S = 2 s(ne/2) (2 ln 2 at half filling)."""
+    s = lattice_system(1, "c1", seed=8, rank=1).replace(n_electrons=ne)
+    m = R.Model(s)
+    el = R.electronic(m, s.pos, np.zeros(1))
+    h = float(s.onsite[0] + s.onsite_jitter[0])
+    T = s.te
+    assert abs(el.mu - (h - T * math.log(2.0 / ne - 1.0))) < 1e-12
+    assert abs(el.D[0, 0] - ne) < 1e-13 and abs(el.q[0]) < 1e-13
+    assert abs(np.sum(el.H0 * el.D) - h * ne) < 1e-13
+    assert abs(R.entropy(m, el) - 2.0 * _fermi_entropy(ne / 2.0)) < 1e-12
+    st = R.init_state(m, scf_tol=1e-11)
+    assert np.abs(st.force).max() == 0.0
+    if ne == 1.0:
+        assert abs(st.energy["te_s"] - 2.0 * T * math.log(2.0)) < 1e-13
+
+
+def test_four_orbital_atom_against_root_finder():
+    """One atom with four orbitals and no hopping inside the atom: H is
+    diagonal, so D = diag(2 f(beta (e_a - mu))) with mu the root of the
+    electron count, found here by scipy's brentq on the scalar equation."""
+    from scipy.optimize import brentq
+    s = lattice_system(1, "c2", seed=8, rank=1)
+    m = R.Model(s)
+    el = R.electronic(m, s.pos, np.zeros(1))
+    e = s.onsite + s.onsite_jitter
+    beta = 1.0 / s.te
+    occ = lambda mu: 2.0 / (1.0 + np.exp(beta * (e - mu)))
+    mu = brentq(lambda x: occ(x).sum() - s.n_electrons, e.min() - 5, e.max() + 5, xtol=1e-15)
+    f = occ(mu) / 2.0
+    assert abs(el.mu - mu) < 1e-11
+    assert np.abs(el.D - np.diag(2.0 * f)).max() < 1e-12
+    assert abs(R.entropy(m, el) - 2.0 * sum(_fermi_entropy(x) for x in f)) < 1e-11
+
+
 def test_trace_equals_electron_count():
     s = lattice_system(40, "c2", seed=11)
     m = R.Model(s)
