@@ -135,7 +135,13 @@ typedef struct {
     int32_t energy_every;         /* energy evaluation period (0 = never
                                      inside xlbomd_step)                    */
     void *stream;                 /* hipStream_t to run on; NULL = library's
-                                     own stream                             */
+                                     own stream.  Every call synchronises
+                                     with this stream before it returns
+                                     (the chemical potential, the level
+                                     count and the kernel's rank are
+                                     decided on the host from device
+                                     values), so calls cannot be captured
+                                     into a HIP graph                       */
     const xlbomd_allocator *allocator; /* device memory source; NULL =
                                      hipMalloc / hipFree                    */
     int32_t foe_levels;           /* 0: the smallest level count meeting the
