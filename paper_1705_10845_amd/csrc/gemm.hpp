@@ -532,15 +532,17 @@ __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs<T> p, int ntil
     epilogue_block<T, SYM>(p, bz, ti, tj, wr * 64 + x * 16, wc * 16 * YB + y * 16, fr, fc, acc);
 }
 
+// CU count of the current device, read once (thread-safe initialisation:
+// systems stepped by several host threads share it)
 inline int device_cus() {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
+    static const int cus = [] {
+        int dev = 0, n = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            cus <= 0)
-            cus = 256;
-    }
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n <= 0)
+            return 256;
+        return n;
+    }();
     return cus;
 }
 
