@@ -230,6 +230,18 @@ struct SysBase {
         mem.ptrs.push_back(p);
         return (T *)p;
     }
+    // gives a buffer from dev() back before destruction (a grown buffer
+    // replaces it), once the stream has drained so that no queued work
+    // still uses it; the caller drops its pointer
+    void release(void *p) {
+        if (!p) return;
+        sync();
+        const auto it = std::find(mem.ptrs.begin(), mem.ptrs.end(), p);
+        if (it == mem.ptrs.end()) return;
+        mem.ptrs.erase(it);
+        if (mem.al.free) mem.al.free(p, mem.al.ctx);
+        else (void)hipFree(p);
+    }
     ModelDev md{};
 
     // device arrays (FP64)
@@ -888,6 +900,11 @@ template <typename TF, typename TR> struct Sys : SysBase {
     }
     void alloc_resp(int nb) {
         if (nb <= bcap) return;
+        // the smaller batch buffers go back before the larger ones are taken
+        this->release(Zp); this->release(Ap); this->release(Tb); this->release(Xb);
+        for (auto &q : Sd) { this->release(q); q = nullptr; }
+        Zp = Ap = Tb = Xb = nullptr;
+        bcap = 0;
         TR *zp = this->template dev<TR>(mat() * nb), *ap = this->template dev<TR>(mat() * nb),
            *tb = this->template dev<TR>(mat() * nb);
         Zp = zp; Ap = ap; Tb = tb;
@@ -1343,6 +1360,9 @@ template <typename TF, typename TR> struct Sys : SysBase {
                                (const float *)Y2r, ub, (long)Np, s16(Sd[1]), sm, s2);
             XL_LAUNCH_CHECK();
             if (!Pb || pb_cap < nb) {
+                this->release(Pb);
+                Pb = nullptr;
+                pb_cap = 0;
                 Pb = this->template dev<double>(mat() * nb);
                 pb_cap = nb;
             }
@@ -1505,6 +1525,10 @@ template <typename TF, typename TR> struct Sys : SysBase {
     int chol_cap = 0;
     double *chol_batch(int nb) {       // nb padded Np x Np FP64 matrices
         if (nb > chol_cap) {
+            this->release(cholA);
+            this->release(cholP);
+            cholA = cholP = nullptr;
+            chol_cap = 0;
             cholA = this->template dev<double>(mat() * nb);
             cholP = this->template dev<double>((size_t)NB * Np * nb);
             if (!cholOut) {

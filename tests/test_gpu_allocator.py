@@ -110,3 +110,40 @@ def test_torch_allocator_under_batch_stepping(P):
         assert np.abs(g.charges()[1] - q).max() <= 1e-12
         g.close()
     assert len(a.live) == 0
+
+
+def test_grown_buffers_are_returned(P):
+    """Block-mode kernels grow the response batch from one direction at
+    init to three in the steps.  The smaller batch buffers go back to the
+    allocator when the larger ones are taken, not at close.  The trajectory
+    equals the one on hipMalloc memory."""
+    from synth import lattice_system
+
+    def system():
+        return lattice_system(40, "c3", seed=12, rank=3, krylov_mode=1, k0_gamma=0.1)
+
+    g = P.XLBOMD(system(), precision=P.MIXED_BF16X3)
+    g.step(5, report=False)
+    q0 = g.charges()[1]
+    g.close()
+
+    a = P.TorchAllocator()
+    inner_free = a._fns[1]
+    freed = []
+
+    def free(ptr, ctx):
+        freed.append(ptr)
+        return inner_free(ptr, ctx)
+
+    fn = P.binding._FREE_FN(free)
+    a._fns = (a._fns[0], fn, inner_free)
+    a.struct = P.Allocator(a._fns[0], fn, None)
+    g = P.XLBOMD(system(), precision=P.MIXED_BF16X3, allocator=a)
+    g.step(5, report=False)
+    early = len(freed)
+    q1 = g.charges()[1]
+    g.close()
+    print(f"{early} buffers returned before close, {len(freed) - early} at close")
+    assert early > 0
+    assert len(a.live) == 0
+    assert np.abs(q1 - q0).max() <= 1e-12
