@@ -1,12 +1,14 @@
-"""Writes c3_n8192_sample.txt: the oracle's charges on a seeded sample of
-atoms of the small-gap workload (2048 atoms x 4 orbitals, N = 8192,
-T_e = 0.02) at a fixed, seeded charge vector n, and its chemical potential.
+"""Writes <name>_n<N>_sample.txt: the oracle's charges on a seeded sample of
+atoms of a workload at a fixed, seeded charge vector n, and its chemical
+potential.  Workloads: c3 (small gap, 2048 atoms x 4 orbitals, N = 8192,
+T_e = 0.02) and c5 (4096 randomly packed atoms x 4 orbitals, N = 16384).
 
 Calls only the oracle (the Fermi-Dirac density of Section IV.B, Eq. 36,
 at fixed electron number, and the net Mulliken charges of Section VI);
 numpy's eigh stands in for the oracle's Jacobi sweeps at this size.
 
-    python tests/golden/make_c3_sample.py     (about two minutes of CPU)
+    python tests/golden/make_sample.py c3    (about two minutes of CPU)
+    python tests/golden/make_sample.py c5    (about ten minutes, ~15 GB)
 """
 import os
 import sys
@@ -36,18 +38,23 @@ def _eigh_rows(H):
     return w, np.ascontiguousarray(V.T)
 
 
-def main():
-    s = make_system("c3")
+def sample_path(name, n_orbitals):
+    return os.path.join(HERE, f"{name}_n{n_orbitals}_sample.txt")
+
+
+def main(name):
+    s = make_system(name)
     n = charge_vector(s.n_atoms)
     ref = R.electronic(R.Model(s), s.pos, n, eig=_eigh_rows)
     atoms = sample_atoms(s.n_atoms)
-    path = os.path.join(HERE, "c3_n8192_sample.txt")
+    path = sample_path(name, s.n)
     with open(path, "w") as f:
-        f.write("# oracle charges of the c3 workload (2048 atoms x 4 orbitals, Te = 0.02)\n")
+        f.write(f"# oracle charges of the {name} workload ({s.n_atoms} atoms x {s.n_orb} "
+                f"orbitals, Te = {s.te})\n")
         f.write(f"# at n = 0.02 N(0,1) (PCG64 seed {N_SEED}, mean removed); "
                 f"atoms sampled with seed {SAMPLE_SEED}\n")
         f.write("# D = 2 f(H[n]) at fixed electron number (Section IV.B, Eq. 36), net\n")
-        f.write("# Mulliken charges (Section VI); written by make_c3_sample.py from the\n")
+        f.write("# Mulliken charges (Section VI); written by make_sample.py from the\n")
         f.write("# oracle only\n")
         f.write(f"mu {ref.mu:.17e}\n")
         for a in atoms:
@@ -56,4 +63,4 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1] if len(sys.argv) > 1 else "c3")

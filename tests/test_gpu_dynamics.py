@@ -273,16 +273,16 @@ def test_split_expansion_matches_fp64_at_n4096(P):
 
 
 
-def _golden_c3():
-    """The oracle's sample for the small-gap workload and its recipe."""
+def _golden(name, n_orbitals):
+    """The oracle's stored sample for a workload and its recipe."""
     import importlib.util
     here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-    spec = importlib.util.spec_from_file_location("make_c3_sample",
-                                                  os.path.join(here, "make_c3_sample.py"))
+    spec = importlib.util.spec_from_file_location("make_sample",
+                                                  os.path.join(here, "make_sample.py"))
     gen = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(gen)
     mu, atoms, q = None, [], []
-    for line in open(os.path.join(here, "c3_n8192_sample.txt")):
+    for line in open(gen.sample_path(name, n_orbitals)):
         if line.startswith("#"):
             continue
         a, v = line.split()
@@ -301,7 +301,7 @@ def test_small_gap_workload_at_n8192(P):
     stored by a script that runs the oracle alone.  The bound is the one of
     the N = 4096 case: 8 times the 1e-9 truncation target per atom, rounded
     up to 1e-8."""
-    gen, mu_ref, atoms, q_ref = _golden_c3()
+    gen, mu_ref, atoms, q_ref = _golden("c3", 8192)
     s = make_system("c3")
     n = gen.charge_vector(s.n_atoms)
     g = P.XLBOMD(s, precision=P.MIXED_BF16X3, scf_tol=1e-5)
@@ -309,6 +309,26 @@ def test_small_gap_workload_at_n8192(P):
     g.close()
     err = np.abs(q[atoms] - q_ref).max()
     print(f"N=8192 MIXED_BF16X3, {rep['foe_levels']} levels: sampled charges vs oracle "
+          f"{err:.2e}, mu {rep['mu']:.12f} vs {mu_ref:.12f}")
+    assert err < 1e-8
+    assert abs(rep["mu"] - mu_ref) < 1e-9
+
+
+
+def test_random_packing_workload_at_n16384(P):
+    """The largest workload (4096 randomly packed atoms x 4 orbitals,
+    N = 16384, irregular neighbour counts) at a fixed n in the headline
+    precision, against the oracle's stored sample of 128 atoms and its
+    chemical potential; the bound is the one of the N = 4096 case.  A loose
+    initial SCF keeps the test short: the solve at n does not depend on it."""
+    gen, mu_ref, atoms, q_ref = _golden("c5", 16384)
+    s = make_system("c5")
+    n = gen.charge_vector(s.n_atoms)
+    g = P.XLBOMD(s, precision=P.MIXED_BF16X3, scf_tol=1e-3)
+    q, rep = g.solve(n)
+    g.close()
+    err = np.abs(q[atoms] - q_ref).max()
+    print(f"N=16384 MIXED_BF16X3, {rep['foe_levels']} levels: sampled charges vs oracle "
           f"{err:.2e}, mu {rep['mu']:.12f} vs {mu_ref:.12f}")
     assert err < 1e-8
     assert abs(rep["mu"] - mu_ref) < 1e-9
