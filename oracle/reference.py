@@ -360,6 +360,11 @@ class State:
     el: Electronic
     step: int = 0
     energy: Dict[str, float] = field(default_factory=dict)
+    # the last low-rank build for the dynamics stopped at rank 0 although a
+    # positive rank was asked for (a zero or floor-level residual, e.g. just
+    # after the converged SCF): the next step builds again, whatever the
+    # refresh period (reading of Section V.E's on-the-fly reuse)
+    pending: bool = False
 
 
 AUTO_GAMMA_ITERS = 20
@@ -417,13 +422,15 @@ def init_state(model, pos=None, vel=None, scf_tol=1e-10, gamma=None,
         model.gamma_used = gamma
     el, _ = scf(model, pos, gamma, rank, tol=scf_tol)
     hist = np.tile(el.n, (s.kmax + 1, 1))            # Eq. 20: ndot(t0) = 0
+    pending = False
     if s.krylov_mode == 2:
         K, V = kernel_full(model, el), None
     else:
         kres = kernel_sm(model, el, gamma, rank, mode=s.krylov_mode)
         K, V = kres.K, kres.V
+        pending = rank > 0 and kres.rank == 0
     st = State(pos=pos, vel=vel, force=forces(model, pos, el), n_hist=hist,
-               kr=K @ el.r, K=K, V=V, el=el)
+               kr=K @ el.r, K=K, V=V, el=el, pending=pending)
     st.energy = energy_report(model, st)
     return st
 
@@ -455,18 +462,20 @@ def md_step(model, st, gamma=None, rank=None, want_energy=True):
     el = electronic(model, pos, n_new)
     F = forces(model, pos, el)
     step = st.step + 1
+    pending = False
     if (step % s.kernel_every == 0 or st.K is None) and s.krylov_mode == 2:
         K, V = kernel_full(model, el), None
-    elif step % s.kernel_every == 0 or st.K is None:
+    elif step % s.kernel_every == 0 or st.K is None or st.pending:
         kres = kernel_sm(model, el, gamma, rank, mode=s.krylov_mode,
                          v_prev=st.V)
         K, V = kres.K, kres.V
+        pending = rank > 0 and kres.rank == 0
     else:
         K, V = st.K, st.V
     kr = K @ el.r
     vel = vel + 0.5 * dt * F / m
     nst = State(pos=pos, vel=vel, force=F, n_hist=hist, kr=kr, K=K, V=V,
-                el=el, step=step)
+                el=el, step=step, pending=pending)
     if want_energy:
         nst.energy = energy_report(model, nst)
     return nst

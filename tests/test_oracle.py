@@ -434,3 +434,20 @@ def test_auto_gamma_bounds_the_stiffest_mode():
     assert 0.94 * lam_exact <= lam <= lam_exact * (1 + 1e-12)
     assert g * (1.0 + lam_exact) <= 1.6
     assert g >= 0.95 * 1.5 / (1.0 + lam_exact) - 0.01
+
+
+def test_kernel_after_converged_init_is_built_at_the_first_step():
+    # reading of Section V.E (kernel reused between rebuilds): right after a
+    # converged SCF the residual is rounding noise, the build for the
+    # dynamics stops at rank 0 (K0 alone), and the first MD step builds
+    # again whatever the refresh period; later steps reuse that kernel
+    s = make_system("c1", kernel_every=50, rank=2)
+    m = R.Model(s)
+    st = R.init_state(m, scf_tol=1e-11)
+    assert st.pending and st.V.shape[1] == 0
+    assert np.allclose(st.K, -s.k0_gamma * np.eye(m.nat))
+    st1 = R.md_step(m, st, want_energy=False)
+    assert not st1.pending and st1.V.shape[1] == 2
+    assert not np.allclose(st1.K, -s.k0_gamma * np.eye(m.nat))
+    st2 = R.md_step(m, st1, want_energy=False)
+    assert st2.K is st1.K and not st2.pending
