@@ -145,10 +145,21 @@ typedef struct {
     const xlbomd_allocator *allocator; /* device memory source; NULL =
                                      hipMalloc / hipFree                    */
     int32_t foe_levels;           /* 0: the smallest level count meeting the
-                                     truncation target on the spectral
-                                     interval (2e-10 FP64, 1e-9 otherwise);
-                                     1..40: that count, raised where the
-                                     seed would leave |x / 2^(L+1)| <= 1   */
+                                     truncation target foe_tol on the
+                                     spectral interval; 1..40: that count,
+                                     raised where the seed would leave
+                                     |x / 2^(L+1)| <= 1                     */
+    double foe_tol;               /* truncation target of the expansion, the
+                                     largest deviation of the L-level map
+                                     from the Fermi function on the
+                                     interval: 0 = 2e-10 (FP64) / 1e-9
+                                     (other precisions); else in
+                                     [1e-14, 1e-3]                          */
+    double mu_tol;                /* the expansion is rerun at the corrected
+                                     chemical potential while beta |dmu| is
+                                     above this: 0 = 1e-6 (FP64) / 1e-3
+                                     (other precisions); else in
+                                     [1e-12, 1e-1]                          */
 } xlbomd_desc;
 
 typedef struct {
@@ -207,8 +218,12 @@ int xlbomd_get_charges(xlbomd_system *h, double *n_out, double *q_out);
 /* Overwrite the dynamical state: positions and velocities (n_atoms*3), the
  * n history (kmax+1 rows of n_atoms: n(t), n(t-dt), ...) and the stored
  * K r(t) used for the next n update (n_atoms).  Any of them may be NULL to
- * keep the current value.  The electronic solve, forces and kernel are
- * recomputed at the new state (kr, if given, is kept as passed). */
+ * keep the current value.  The electronic solve, the forces and the
+ * trajectory's kernel are recomputed at the new state (kr, if given, is
+ * kept as passed); the chemical-potential history restarts from that
+ * solve and the step count is kept.  This is a frozen-state entry point
+ * (parity checks, perturbations); an exact checkpoint of everything the
+ * next step reads is xlbomd_save_state / xlbomd_load_state. */
 int xlbomd_set_state(xlbomd_system *h, const double *pos, const double *vel,
                      const double *n_hist, const double *kr);
 
@@ -216,9 +231,30 @@ int xlbomd_set_state(xlbomd_system *h, const double *pos, const double *vel,
 int xlbomd_get_state(xlbomd_system *h, double *pos, double *vel,
                      double *n_hist, double *kr);
 
+/* Checkpoint / resume.  A checkpoint holds everything the next step reads:
+ * positions, velocities and forces, the n history of Eq. 23, K r(t), the
+ * trajectory's kernel (directions V, W = J V - V, the previous build's
+ * directions, the full kernel of krylov_mode 2), the chemical-potential
+ * history that predicts the next solve's mu, the step count and the K0
+ * constant.  Stepping a handle after xlbomd_load_state repeats, bit for
+ * bit, what the saved handle did after xlbomd_save_state.
+ *   xlbomd_state_size: *bytes = the checkpoint size of this handle.
+ *   xlbomd_save_state: writes the checkpoint into buf (caller-owned host
+ *     memory of at least xlbomd_state_size bytes; `bytes` is its size).
+ *   xlbomd_load_state: restores a checkpoint written by a handle with the
+ *     same descriptor (atoms, orbitals, kmax, kernel capacity, Krylov mode,
+ *     precision); XLBOMD_E_INVALID otherwise or if `bytes` does not match.
+ *     Charges, forces and energies asked for before the next step are
+ *     evaluated at the restored state. */
+int xlbomd_state_size(xlbomd_system *h, size_t *bytes);
+int xlbomd_save_state(xlbomd_system *h, void *buf, size_t bytes);
+int xlbomd_load_state(xlbomd_system *h, const void *buf, size_t bytes);
+
 /* Electronic solve at the current positions for the charge vector n
  * (n_atoms): writes q[n] (n_atoms) and, if rep != NULL, mu, RMS(q-n) and
- * the FOE statistics.  Does not change the dynamical state. */
+ * the FOE statistics.  Does not change the dynamical state; a later
+ * xlbomd_forces energy, xlbomd_get_charges or xlbomd_kernel_update first
+ * solves again at the MD state. */
 int xlbomd_solve(xlbomd_system *h, const double *n, double *q_out,
                  xlbomd_report *rep);
 
@@ -229,8 +265,11 @@ int xlbomd_response(xlbomd_system *h, int32_t count, const double *v,
                     double *dq_out);
 
 /* Apply the rank-m kernel built at the last xlbomd_solve to r (n_atoms):
- * kr_out = K_m r (Eq. 50 in closed Woodbury form); rank = -1 applies the
- * full kernel (J - I)^-1 of Eq. 43 (krylov_mode 2 construction). */
+ * kr_out = K_m r (Eq. 50 in closed Woodbury form), the first direction
+ * along K0 r and the next ones sequential Krylov directions; rank = -1
+ * applies the full kernel (J - I)^-1 of Eq. 43 (krylov_mode 2
+ * construction).  The kernel is built in storage of its own: the
+ * trajectory's kernel, applied between rebuilds, is not changed. */
 int xlbomd_kernel_apply(xlbomd_system *h, int32_t rank, const double *r,
                         double *kr_out);
 
@@ -250,8 +289,8 @@ int xlbomd_kernel_apply(xlbomd_system *h, int32_t rank, const double *r,
  * XLBOMD_E_DIVERGED if an iterate could not be evaluated (no chemical
  * potential, non-finite spectral bounds) or its RMS residual is above 1e3;
  * *n_eval and rms_hist then cover the evaluations before it, n_out is not
- * written.  The MD history and K r are not touched; the handle's
- * electronic state (charges, density) is left at the last evaluated n. */
+ * written.  The MD history, K r and the trajectory's kernel are not
+ * touched (the SCF's kernels are built in storage of their own). */
 int xlbomd_scf(xlbomd_system *h, const double *n0, int32_t rank, double gamma, double tol,
                int32_t max_iter, double *n_out, double *rms_hist, int32_t *n_eval);
 

@@ -79,6 +79,7 @@ class Desc(ctypes.Structure):
         ("scf_tol", ctypes.c_double), ("scf_max_iter", ctypes.c_int32),
         ("energy_every", ctypes.c_int32), ("stream", ctypes.c_void_p),
         ("allocator", ctypes.POINTER(Allocator)), ("foe_levels", ctypes.c_int32),
+        ("foe_tol", ctypes.c_double), ("mu_tol", ctypes.c_double),
     ]
 
 
@@ -133,6 +134,9 @@ def lib():
         L.xlbomd_get_charges.argtypes = [vp, _dp, _dp]
         L.xlbomd_set_state.argtypes = [vp, _dp, _dp, _dp, _dp]
         L.xlbomd_get_state.argtypes = [vp, _dp, _dp, _dp, _dp]
+        L.xlbomd_state_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.xlbomd_save_state.argtypes = [vp, ctypes.c_void_p, ctypes.c_size_t]
+        L.xlbomd_load_state.argtypes = [vp, ctypes.c_void_p, ctypes.c_size_t]
         L.xlbomd_solve.argtypes = [vp, _dp, _dp, ctypes.POINTER(Report)]
         L.xlbomd_response.argtypes = [vp, ctypes.c_int32, _dp, _dp]
         L.xlbomd_kernel_apply.argtypes = [vp, ctypes.c_int32, _dp, _dp]
@@ -154,7 +158,8 @@ def lib():
 EXPORTED = ("xlbomd_init_system", "xlbomd_step", "xlbomd_step_batch",
             "xlbomd_kernel_update",
             "xlbomd_forces", "xlbomd_get_charges", "xlbomd_set_state",
-            "xlbomd_get_state", "xlbomd_solve", "xlbomd_response",
+            "xlbomd_get_state", "xlbomd_state_size", "xlbomd_save_state",
+            "xlbomd_load_state", "xlbomd_solve", "xlbomd_response",
             "xlbomd_kernel_apply", "xlbomd_scf", "xlbomd_profile", "xlbomd_selftest_gemm",
             "xlbomd_selftest_gemm_time", "xlbomd_selftest_gemm_presplit",
             "xlbomd_destroy", "xlbomd_last_error",
@@ -226,11 +231,14 @@ class XLBOMD:
     """One system living on the GPU (a library handle)."""
 
     def __init__(self, system, precision=FP64, scf_tol=None, scf_max_iter=300,
-                 energy_every=0, stream=None, allocator=None, foe_levels=0, **override):
+                 energy_every=0, stream=None, allocator=None, foe_levels=0,
+                 foe_tol=0.0, mu_tol=0.0, **override):
         """allocator: None (hipMalloc), "torch" (a TorchAllocator on the
         current device) or an object with a ctypes `struct` (Allocator);
         it is kept alive with the handle.  foe_levels: 0 chooses the level
-        count from the truncation target, 1..40 requests one."""
+        count from the truncation target, 1..40 requests one.  foe_tol and
+        mu_tol override the truncation target and the chemical-potential
+        rerun threshold (0 = the precision's defaults)."""
         s = system.replace(**override) if override else system
         self.nat, self.no = int(s.n_atoms), int(s.n_orb)
         self.kmax = int(s.kmax)
@@ -254,6 +262,7 @@ class XLBOMD:
         d.scf_max_iter, d.energy_every = scf_max_iter, energy_every
         d.stream = stream
         d.foe_levels = foe_levels
+        d.foe_tol, d.mu_tol = float(foe_tol), float(mu_tol)
         if allocator == "torch":
             allocator = TorchAllocator()
         self.allocator = allocator
@@ -304,6 +313,20 @@ class XLBOMD:
         _check(lib().xlbomd_get_state(self._h, _ptr(pos), _ptr(vel),
                                       _ptr(hist), _ptr(kr)))
         return dict(pos=pos, vel=vel, n_hist=hist, kr=kr)
+
+    def save_state(self) -> bytes:
+        """Checkpoint of everything the next step reads (opaque bytes)."""
+        size = ctypes.c_size_t(0)
+        _check(lib().xlbomd_state_size(self._h, ctypes.byref(size)))
+        buf = ctypes.create_string_buffer(size.value)
+        _check(lib().xlbomd_save_state(self._h, buf, size.value))
+        return buf.raw
+
+    def load_state(self, blob: bytes):
+        """Restore a checkpoint from save_state of a handle with the same
+        descriptor; the next steps repeat the saved run bit for bit."""
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        _check(lib().xlbomd_load_state(self._h, buf, len(blob)))
 
     def solve(self, n):
         n = _c(n, (self.nat,))

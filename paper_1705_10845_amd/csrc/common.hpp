@@ -23,6 +23,9 @@ struct Diverged : std::runtime_error {
 struct NoMem : std::runtime_error {
     explicit NoMem(const std::string &m) : std::runtime_error(m) {}
 };
+struct StateError : std::runtime_error {   // call not valid in the handle's state
+    explicit StateError(const std::string &m) : std::runtime_error(m) {}
+};
 
 #define XL_HIP(call)                                                          \
     do {                                                                      \

@@ -256,6 +256,41 @@ struct SysBase {
     int head = 0;              // ring index of n(t) in hist
     int mcap = 0, rank_built = 0, rank_prev = 0, step_no = 0;
     int bcap = 0;              // response batch capacity
+    double *fscr = nullptr;    // forces of an energy evaluation (the MD forces stay)
+    double *rdiag = nullptr;   // residual handed to a diagnostic kernel build
+    // a kernel for the dynamics whose build stopped at rank 0 (a zero or
+    // floor-level residual, e.g. right after a converged SCF) is rebuilt at
+    // the next step, whatever the refresh period
+    bool kernel_pending = false;
+    // the electronic state (D, q, r) belongs to a diagnostic solve
+    // (xlbomd_solve, xlbomd_scf) or to nothing yet (a restored checkpoint),
+    // not to the MD state n(t), R(t)
+    bool el_stale = false;
+
+    // The trajectory's kernel lives in V, W, Vprev, gj (with rank_built,
+    // rank_prev, full_built).  Diagnostic calls (xlbomd_kernel_apply,
+    // xlbomd_scf) build theirs in a second set swapped in for the call, so
+    // the MD kernel applied between rebuilds is never replaced by theirs.
+    struct KernSet {
+        double *V = nullptr, *W = nullptr, *Vprev = nullptr, *gj = nullptr;
+        int rank_built = 0, rank_prev = 0;
+        bool full_built = false;
+    } kdiag;
+    void swap_kernel_set();
+    struct DiagKernel {
+        SysBase &s;
+        explicit DiagKernel(SysBase &s_) : s(s_) {
+            if (!s.kdiag.V) {
+                s.kdiag.V = s.dev<double>((size_t)s.mcap * s.nat);
+                s.kdiag.W = s.dev<double>((size_t)s.mcap * s.nat);
+                s.kdiag.Vprev = s.dev<double>((size_t)s.mcap * s.nat);
+            }
+            s.swap_kernel_set();
+        }
+        ~DiagKernel() { s.swap_kernel_set(); }
+        DiagKernel(const DiagKernel &) = delete;
+        DiagKernel &operator=(const DiagKernel &) = delete;
+    };
 
     // electronic state of the last solve
     double mu = 0.0, mu_prev = 0.0, mu_prev2 = 0.0;
@@ -318,6 +353,16 @@ struct SysBase {
 
     void sync() { XL_HIP(hipStreamSynchronize(st)); }
 
+    // truncation target of the expansion against the Fermi function, and
+    // the threshold on beta |dmu| above which the expansion is rerun at the
+    // corrected chemical potential (descriptor values, else by precision)
+    double trunc_tol() const {
+        return d.foe_tol > 0.0 ? d.foe_tol : (d.precision == XLBOMD_FP64 ? 2e-10 : 1e-9);
+    }
+    double mu_tol() const {
+        return d.mu_tol > 0.0 ? d.mu_tol : (d.precision == XLBOMD_FP64 ? 1e-6 : 1e-3);
+    }
+
     void upload_model(const xlbomd_desc *ds) {
         d = *ds;
         if (d.allocator) mem.al = *d.allocator;   // kept by value
@@ -349,6 +394,7 @@ struct SysBase {
         mcap = std::max(1, std::min(d.kernel_rank, 16));
         A(V, (size_t)mcap * nat); A(W, (size_t)mcap * nat); A(Vprev, (size_t)mcap * nat);
         A(vtmp, nat); A(vin, (size_t)mcap * nat); A(qp, (size_t)mcap * nat); A(hb, (size_t)mcap * nat);
+        A(fscr, 3 * nat); A(rdiag, nat);
         A(ub, (size_t)mcap * Np);
         A(part, (size_t)mcap * ((Np + 63) / 64) * N + 3 * (size_t)N);
         void *hp = nullptr;
@@ -402,7 +448,7 @@ struct SysBase {
     virtual void foe(double mu0) = 0;       // expansion at mu0 -> Z, Y, g, dmu
     virtual void finish_density() = 0;      // D_c and charges
     virtual void responses(int nb, const double *v, double *qout, double *wout) = 0;
-    virtual void forces_parts() = 0;
+    virtual void forces_parts(double *F) = 0;   // forces into F (3 n_atoms), energy parts
     virtual double entropy_ts() = 0;        // Te * S at the corrected state
     virtual int levels_cap() const = 0;
 
@@ -486,7 +532,7 @@ struct SysBase {
         spectral_tighten();
         if (!std::isfinite(elo) || !std::isfinite(ehi)) throw Diverged("non-finite spectral bounds");
         double mu0 = have_guess ? mu_guess : initial_mu();
-        const double tau = (d.precision == XLBOMD_FP64) ? 1e-6 : 1e-3;
+        const double tau = mu_tol();
         reruns = 0;
         ns_total = 0;
         // N(mu) = Tr D is strictly increasing: keep a bracket [mlo, mhi]
@@ -535,14 +581,19 @@ struct SysBase {
     // floor: a kernel for the dynamics (applied to later residuals) is K0
     // when the residual's RMS is at or below 1e-8 (its direction is rounding
     // noise); the SCF applies each kernel to its own residual (no floor).
-    int build_kernel(int m, int mode, bool use_prev, bool floor = true) {
+    // `res` is the residual the directions start from (default: r of the
+    // last solve).  A build for the dynamics (floor) that ends at rank 0
+    // although m > 0 leaves kernel_pending set: the next step rebuilds.
+    int build_kernel(int m, int mode, bool use_prev, bool floor = true,
+                     const double *res = nullptr) {
+        if (!res) res = r;
         m = std::min(m, mcap);
         if (d.kernel_rank <= 0) m = 0;
         const double gam = d.k0_gamma;
         int rank = 0;
         if (m > 0) {
             // v_1 = K0 r / |K0 r|, K0 = -gamma I
-            hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(1024), 0, st, nat, 0, V, r, -gam, V,
+            hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(1024), 0, st, nat, 0, V, res, -gam, V,
                                scal + 24);
             XL_LAUNCH_CHECK();
             XL_HIP(hipMemcpyAsync(hscal + 24, scal + 24, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -583,23 +634,39 @@ struct SysBase {
             }
         }
         rank_built = rank;
+        full_built = false;
         if (rank > 0) {
             XL_HIP(hipMemcpyAsync(Vprev, V, (size_t)rank * nat * sizeof(double),
                                   hipMemcpyDeviceToDevice, st));
             rank_prev = rank;
+        } else {
+            rank_prev = 0;      // a rank-0 build leaves no directions to reuse
         }
+        if (floor) kernel_pending = (m > 0 && rank == 0);
         return rank;
     }
 
+    // K_m r with the low-rank kernel last built (at most mcap directions)
     void apply_kernel(const double *rin, double *out) {
+        if (rank_built < 0 || rank_built > mcap)
+            throw StateError("no low-rank kernel of rank " + std::to_string(rank_built) +
+                             " can be applied (capacity " + std::to_string(mcap) + ")");
         hipLaunchKernelGGL(kernel_apply_kernel, dim3(1), dim3(1024), 0, st, nat, rank_built, V, W,
                            rin, d.k0_gamma, out, scal + 32);
         XL_LAUNCH_CHECK();
     }
 
+    // re-solve at the MD state n(t), R(t) when the electronic state belongs
+    // to a diagnostic solve or a restored checkpoint (forces unchanged)
+    void refresh_electronic() {
+        if (!el_stale) return;
+        solve(hist_row(0), mu_prev, mu_known > 0);
+        el_stale = false;
+    }
+
     // ---- energy report at the current state ----
     void energy(xlbomd_report *rep) {
-        forces_parts();
+        forces_parts(fscr);
         hipLaunchKernelGGL(sum_rows_kernel, dim3(1), dim3(1024), 0, st, nat, 3, epart, scal + 40);
         XL_LAUNCH_CHECK();
         hipLaunchKernelGGL(kinetic_kernel, dim3(1), dim3(1024), 0, st, nat, vel, mass, scal + 44);
@@ -639,8 +706,8 @@ struct SysBase {
     int *gjflag = nullptr;
     bool full_built = false;
     void build_full_kernel() {
-        if (!gj) {
-            gj = dev<double>((size_t)2 * nat * nat);
+        if (!gj) gj = dev<double>((size_t)2 * nat * nat);   // per kernel set
+        if (!gjf) {                                           // shared work space
             gjf = dev<double>(nat);
             dirs = dev<double>((size_t)mcap * nat);
             qdir = dev<double>((size_t)mcap * nat);
@@ -692,14 +759,15 @@ struct SysBase {
         XL_LAUNCH_CHECK();
         head = dst;
         solve(hist_row(0), predict_mu(), mu_known > 0);
+        el_stale = false;
         push_mu();
-        forces_parts();
+        forces_parts(force);
         ++step_no;
         if (full_mode()) {
             if (step_no % std::max(1, d.kernel_every) == 0 || !full_built) build_full_kernel();
             apply_full(r, kr);
         } else {
-            if (step_no % std::max(1, d.kernel_every) == 0)
+            if (step_no % std::max(1, d.kernel_every) == 0 || kernel_pending)
                 build_kernel(d.kernel_rank, d.krylov_mode, true);
             apply_kernel(r, kr);
         }
@@ -784,7 +852,8 @@ struct SysBase {
         head = 0;
         mu_known = 0;
         push_mu();
-        forces_parts();
+        el_stale = false;
+        forces_parts(force);
         rank_prev = 0;
         if (full_mode()) {
             build_full_kernel();
@@ -842,6 +911,113 @@ struct SysBase {
         return ok;
     }
 };
+
+// ---- checkpoint: everything the next step reads ----
+namespace {
+struct CkHead {
+    uint64_t magic;
+    int32_t version, nat, no, kmax, mcap, krylov_mode, precision, full;
+    int32_t step_no, rank_built, rank_prev, mu_known, kernel_pending;
+    double mu, mu_prev, mu_prev2, k0_gamma;
+};
+static_assert(sizeof(CkHead) % 8 == 0, "checkpoint header keeps the doubles aligned");
+constexpr uint64_t kCkMagic = 0x584c424f4d44434bull;   // "XLBOMDCK"
+
+size_t ck_doubles(const SysBase &s) {
+    const size_t nat = s.nat, K = s.d.kmax + 1, m = s.mcap;
+    return 9 * nat + K * nat + nat + 3 * m * nat + (s.full_mode() ? 2 * nat * nat : 0);
+}
+size_t state_bytes(const SysBase &s) { return sizeof(CkHead) + 8 * ck_doubles(s); }
+
+void save_state(SysBase &s, char *buf) {
+    CkHead h{};
+    h.magic = kCkMagic;
+    h.version = 1;
+    h.nat = s.nat; h.no = s.no; h.kmax = s.d.kmax; h.mcap = s.mcap;
+    h.krylov_mode = s.d.krylov_mode; h.precision = s.d.precision;
+    h.full = s.full_built ? 1 : 0;
+    h.step_no = s.step_no; h.rank_built = s.rank_built; h.rank_prev = s.rank_prev;
+    h.mu_known = s.mu_known; h.kernel_pending = s.kernel_pending ? 1 : 0;
+    h.mu = s.mu; h.mu_prev = s.mu_prev; h.mu_prev2 = s.mu_prev2; h.k0_gamma = s.d.k0_gamma;
+    std::memcpy(buf, &h, sizeof(h));
+    double *p = reinterpret_cast<double *>(buf + sizeof(h));
+    const size_t nat = s.nat, m = s.mcap;
+    auto get = [&](const double *src, size_t n) {
+        if (src) XL_HIP(hipMemcpyAsync(p, src, n * sizeof(double), hipMemcpyDeviceToHost, s.st));
+        else std::memset(p, 0, n * sizeof(double));
+        p += n;
+    };
+    get(s.pos, 3 * nat);
+    get(s.vel, 3 * nat);
+    get(s.force, 3 * nat);
+    for (int k = 0; k <= s.d.kmax; ++k) get(s.hist_row(k), nat);
+    get(s.kr, nat);
+    get(s.V, m * nat);
+    get(s.W, m * nat);
+    get(s.Vprev, m * nat);
+    if (s.full_mode()) get(s.full_built ? s.gj : nullptr, 2 * nat * nat);
+    s.sync();
+}
+
+void load_state(SysBase &s, const char *buf, size_t bytes) {
+    if (bytes != state_bytes(s)) throw InvalidArg("checkpoint size does not match this handle");
+    CkHead h;
+    std::memcpy(&h, buf, sizeof(h));
+    if (h.magic != kCkMagic || h.version != 1) throw InvalidArg("not an xlbomd checkpoint");
+    if (h.nat != s.nat || h.no != s.no || h.kmax != s.d.kmax || h.mcap != s.mcap ||
+        h.krylov_mode != s.d.krylov_mode || h.precision != s.d.precision)
+        throw InvalidArg("checkpoint written by a handle with another descriptor");
+    if (h.rank_built < 0 || h.rank_built > (h.full ? s.nat : s.mcap) || h.rank_prev < 0 ||
+        h.rank_prev > s.mcap || h.mu_known < 0 || h.mu_known > 2 || !(h.k0_gamma > 0.0))
+        throw InvalidArg("checkpoint fields out of range");
+    const double *p = reinterpret_cast<const double *>(buf + sizeof(h));
+    const size_t nat = s.nat, m = s.mcap;
+    auto put = [&](double *dst, size_t n) {
+        XL_HIP(hipMemcpyAsync(dst, p, n * sizeof(double), hipMemcpyHostToDevice, s.st));
+        p += n;
+    };
+    put(s.pos, 3 * nat);
+    put(s.vel, 3 * nat);
+    put(s.force, 3 * nat);
+    for (int k = 0; k <= s.d.kmax; ++k) put(s.hist + (size_t)k * nat, nat);
+    s.head = 0;
+    put(s.kr, nat);
+    put(s.V, m * nat);
+    put(s.W, m * nat);
+    put(s.Vprev, m * nat);
+    if (s.full_mode()) {
+        if (h.full) {
+            if (!s.gj) s.gj = s.dev<double>(2 * nat * nat);
+            put(s.gj, 2 * nat * nat);
+        } else {
+            p += 2 * nat * nat;
+        }
+    }
+    s.sync();
+    s.full_built = h.full != 0;
+    s.step_no = h.step_no;
+    s.rank_built = h.rank_built;
+    s.rank_prev = h.rank_prev;
+    s.mu_known = h.mu_known;
+    s.kernel_pending = h.kernel_pending != 0;
+    s.mu = h.mu;
+    s.mu_prev = h.mu_prev;
+    s.mu_prev2 = h.mu_prev2;
+    s.d.k0_gamma = h.k0_gamma;
+    s.have_energy = false;
+    s.el_stale = true;    // D, q, r are solved again before anything reads them
+}
+}  // namespace
+
+void SysBase::swap_kernel_set() {
+    std::swap(V, kdiag.V);
+    std::swap(W, kdiag.W);
+    std::swap(Vprev, kdiag.Vprev);
+    std::swap(gj, kdiag.gj);
+    std::swap(rank_built, kdiag.rank_built);
+    std::swap(rank_prev, kdiag.rank_prev);
+    std::swap(full_built, kdiag.full_built);
+}
 
 // ---------------------------------------------------------------------------
 // Precision-dependent dense algebra.  TF: expansion (density matrix, charges,
@@ -985,7 +1161,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
         const double xmax = beta * std::max(std::fabs(elo - mu0), std::fabs(ehi - mu0)) * 1.02 + 1e-12;
         // truncation bound of the expansion vs the Fermi function: 2e-10 for
         // the all-FP64 mode, 1e-9 (charges within 1e-8) otherwise
-        L = choose_levels(xmax, d.precision == XLBOMD_FP64 ? 2e-10 : 1e-9);
+        L = choose_levels(xmax, trunc_tol());
         if (d.foe_levels > 0) {
             // a requested count, raised where the seed would leave |y| <= 1
             int Lmin = 1;
@@ -1287,9 +1463,9 @@ template <typename TF, typename TR> struct Sys : SysBase {
         XL_LAUNCH_CHECK();
     }
 
-    void forces_parts() override {
+    void forces_parts(double *F) override {
         hipLaunchKernelGGL((forces_kernel<TF>), dim3(ceil_div((long)nat * 64, 256)), dim3(256), 0,
-                           st, md, Dc, q, ncur, vpot, force, epart);
+                           st, md, Dc, q, ncur, vpot, F, epart);
         XL_LAUNCH_CHECK();
     }
 
@@ -1552,32 +1728,45 @@ template <typename TF, typename TR> struct Sys : SysBase {
         a.n = Np; a.ld = Np;
         attach_ws(a);                    // split-k for the N x N products
         const double *T0 = as64(Z[0], 0, 2.0);          // T0 = 2 Z_0
-        // one batch: I + T0, then A_0 .. A_{L-1} (the factorisation
-        // overwrites its copies); L + 1 <= 16 outputs
-        if (L + 1 > 16) throw InvalidArg("entropy: more than 15 expansion levels");
-        double *C = chol_batch(L + 1);
-        // I + T0 over the padded array: the padding is an identity block
-        // (ln det 1 = 0), so the factorisation runs on whole 128-blocks
-        hipLaunchKernelGGL(add_diag_copy_kernel, dim3(ceil_div((long)mat(), 256)), dim3(256), 0, st,
-                           Np, Np, T0, 1.0, C);
-        XL_LAUNCH_CHECK();
-        for (int k = 0; k < L; ++k) {
-            double *Ck = C + (size_t)(k + 1) * mat();
-            if constexpr (std::is_same<TF, double>::value) {
-                // the expansion's own A_k
-                XL_HIP(hipMemcpyAsync(Ck, Ak[k], mat() * sizeof(double), hipMemcpyDeviceToDevice, st));
-            } else {
-                // FP32 expansion: A_k again in FP64 from Z_k
-                const double *Zk = as64(Z[k], 2, 1.0);
-                GemmArgs<double> b = a;
-                b.A0 = Zk; b.B0 = Zk; b.alpha = 4.0; b.gamma = 1.0; b.C = Ck;
-                gemm(b, true, st);
+        // log-determinants of I + T0 (index 0) and A_0 .. A_{L-1} (index
+        // k + 1), factorised in batches of at most 16 matrices (the
+        // factorisation overwrites its copies)
+        const int nmat = L + 1, cap = std::min(nmat, 16);
+        double *C = chol_batch(cap);
+        std::vector<double> lds(nmat);
+        for (int i0 = 0; i0 < nmat; i0 += cap) {
+            const int nb = std::min(cap, nmat - i0);
+            for (int j = 0; j < nb; ++j) {
+                const int i = i0 + j;
+                double *Cj = C + (size_t)j * mat();
+                if (i == 0) {
+                    // I + T0 over the padded array: the padding is an
+                    // identity block (ln det 1 = 0), so the factorisation
+                    // runs on whole 128-blocks
+                    hipLaunchKernelGGL(add_diag_copy_kernel, dim3(ceil_div((long)mat(), 256)),
+                                       dim3(256), 0, st, Np, Np, T0, 1.0, Cj);
+                    XL_LAUNCH_CHECK();
+                    continue;
+                }
+                const int k = i - 1;
+                if constexpr (std::is_same<TF, double>::value) {
+                    // the expansion's own A_k
+                    XL_HIP(hipMemcpyAsync(Cj, Ak[k], mat() * sizeof(double),
+                                          hipMemcpyDeviceToDevice, st));
+                } else {
+                    // FP32 expansion: A_k again in FP64 from Z_k
+                    const double *Zk = as64(Z[k], 2, 1.0);
+                    GemmArgs<double> b = a;
+                    b.A0 = Zk; b.B0 = Zk; b.alpha = 4.0; b.gamma = 1.0; b.C = Cj;
+                    gemm(b, true, st);
+                }
             }
+            logdets(nb);
+            for (int j = 0; j < nb; ++j) lds[i0 + j] = hscal[48 + j];
         }
-        logdets(L + 1);
         const double ln2 = std::log(2.0);
-        double lnF = std::ldexp(-N * ln2 + hscal[48], L);   // ln det(I + T0) first
-        for (int k = 0; k < L; ++k) lnF += std::ldexp(N * ln2 - hscal[49 + k], L - 1 - k);
+        double lnF = std::ldexp(-N * ln2 + lds[0], L);   // ln det(I + T0) first
+        for (int k = 0; k < L; ++k) lnF += std::ldexp(N * ln2 - lds[1 + k], L - 1 - k);
         // X_eff = 2^(L+1) atanh(T0) = T0 q(W), W = T0^2, q(w) = sum_j c_j w^j
         // with c_j = 2^(L+1) / (2j + 1), truncated where the next term is
         // below 1e-14 in the trace; q by Paterson-Stockmeyer: baby steps
@@ -1707,6 +1896,10 @@ void validate(const xlbomd_desc *d) {
     if (d->krylov_mode < 0 || d->krylov_mode > 2) throw InvalidArg("krylov_mode is 0, 1 or 2");
     if (!(d->k0_gamma >= 0.0 && d->k0_gamma <= 1.0))
         throw InvalidArg("k0_gamma must be in (0, 1], or 0 for the automatic rule");
+    if (d->foe_tol != 0.0 && !(d->foe_tol >= 1e-14 && d->foe_tol <= 1e-3))
+        throw InvalidArg("foe_tol must be 0 or in [1e-14, 1e-3]");
+    if (d->mu_tol != 0.0 && !(d->mu_tol >= 1e-12 && d->mu_tol <= 1e-1))
+        throw InvalidArg("mu_tol must be 0 or in [1e-12, 1e-1]");
     if (d->precision < XLBOMD_FP64 || d->precision > XLBOMD_MIXED_BF16X3)
         throw InvalidArg("precision must be XLBOMD_FP64, XLBOMD_FP32, XLBOMD_MIXED or "
                          "XLBOMD_MIXED_BF16X3");
@@ -1801,8 +1994,14 @@ int xlbomd_kernel_update(xlbomd_system *h, int32_t rank) {
         SysBase &s = *h->s;
         const int m = rank > 0 ? rank : s.d.kernel_rank;
         if (m > s.mcap) throw InvalidArg("rank above the descriptor's kernel_rank");
-        s.build_kernel(m, s.d.krylov_mode, true);
-        s.apply_kernel(s.r, s.kr);
+        s.refresh_electronic();
+        if (s.full_mode()) {
+            s.build_full_kernel();
+            s.apply_full(s.r, s.kr);
+        } else {
+            s.build_kernel(m, s.d.krylov_mode, true);
+            s.apply_kernel(s.r, s.kr);
+        }
         s.sync();
     });
 }
@@ -1812,6 +2011,7 @@ int xlbomd_forces(xlbomd_system *h, double *forces, xlbomd_report *energy) {
     return guarded([&] {
         SysBase &s = *h->s;
         if (energy) {
+            s.refresh_electronic();
             s.energy(energy);
             s.fill_report(energy);
         }
@@ -1826,6 +2026,7 @@ int xlbomd_get_charges(xlbomd_system *h, double *n_out, double *q_out) {
     if (!h || !h->s) return fail(XLBOMD_E_INVALID, "null handle");
     return guarded([&] {
         SysBase &s = *h->s;
+        if (q_out) s.refresh_electronic();
         if (n_out)
             XL_HIP(hipMemcpyAsync(n_out, s.hist_row(0), s.nat * sizeof(double),
                                   hipMemcpyDeviceToHost, s.st));
@@ -1853,15 +2054,20 @@ int xlbomd_set_state(xlbomd_system *h, const double *pos, const double *vel,
         s.sync();
         s.mu_known = 0;
         s.solve(s.hist_row(0), 0.0, false);
+        s.el_stale = false;
         s.push_mu();
-        s.forces_parts();
+        s.forces_parts(s.force);
+        // the trajectory's kernel at the new state (its K r unless kr is
+        // given); block mode restarts its direction history
         s.rank_prev = 0;
-        if (kr) {
-            XL_HIP(hipMemcpyAsync(s.kr, kr, b1, hipMemcpyHostToDevice, s.st));
+        if (s.full_mode()) {
+            s.build_full_kernel();
+            s.apply_full(s.r, s.kr);
         } else {
             s.build_kernel(s.d.kernel_rank, s.d.krylov_mode, false);
             s.apply_kernel(s.r, s.kr);
         }
+        if (kr) XL_HIP(hipMemcpyAsync(s.kr, kr, b1, hipMemcpyHostToDevice, s.st));
         s.sync();
     });
 }
@@ -1883,11 +2089,30 @@ int xlbomd_get_state(xlbomd_system *h, double *pos, double *vel, double *n_hist,
     });
 }
 
+int xlbomd_state_size(xlbomd_system *h, size_t *bytes) {
+    if (!h || !h->s || !bytes) return fail(XLBOMD_E_INVALID, "null argument");
+    return guarded([&] { *bytes = state_bytes(*h->s); });
+}
+
+int xlbomd_save_state(xlbomd_system *h, void *buf, size_t bytes) {
+    if (!h || !h->s || !buf) return fail(XLBOMD_E_INVALID, "null argument");
+    return guarded([&] {
+        if (bytes < state_bytes(*h->s)) throw InvalidArg("checkpoint buffer too small");
+        save_state(*h->s, static_cast<char *>(buf));
+    });
+}
+
+int xlbomd_load_state(xlbomd_system *h, const void *buf, size_t bytes) {
+    if (!h || !h->s || !buf) return fail(XLBOMD_E_INVALID, "null argument");
+    return guarded([&] { load_state(*h->s, static_cast<const char *>(buf), bytes); });
+}
+
 int xlbomd_solve(xlbomd_system *h, const double *n, double *q_out, xlbomd_report *rep) {
     if (!h || !h->s || !n) return fail(XLBOMD_E_INVALID, "null argument");
     return guarded([&] {
         SysBase &s = *h->s;
         XL_HIP(hipMemcpyAsync(s.vtmp, n, s.nat * sizeof(double), hipMemcpyHostToDevice, s.st));
+        s.el_stale = true;
         s.solve(s.vtmp, s.mu, s.mu_known > 0);
         if (q_out)
             XL_HIP(hipMemcpyAsync(q_out, s.q, s.nat * sizeof(double), hipMemcpyDeviceToHost, s.st));
@@ -1918,14 +2143,15 @@ int xlbomd_kernel_apply(xlbomd_system *h, int32_t rank, const double *rr, double
     return guarded([&] {
         SysBase &s = *h->s;
         if (rank < -1 || rank > s.mcap) throw InvalidArg("rank above capacity");
-        XL_HIP(hipMemcpyAsync(s.r, rr, s.nat * sizeof(double), hipMemcpyHostToDevice, s.st));
+        XL_HIP(hipMemcpyAsync(s.rdiag, rr, s.nat * sizeof(double), hipMemcpyHostToDevice, s.st));
+        SysBase::DiagKernel scope(s);        // the trajectory's kernel stays
         s.rank_prev = 0;
         if (rank == -1) {
             s.build_full_kernel();
-            s.apply_full(s.r, s.vtmp);
+            s.apply_full(s.rdiag, s.vtmp);
         } else {
-            s.build_kernel(rank, 0, false, false);
-            s.apply_kernel(s.r, s.vtmp);
+            s.build_kernel(rank, 0, false, false, s.rdiag);
+            s.apply_kernel(s.rdiag, s.vtmp);
         }
         XL_HIP(hipMemcpyAsync(kr_out, s.vtmp, s.nat * sizeof(double), hipMemcpyDeviceToHost, s.st));
         s.sync();
@@ -1946,6 +2172,8 @@ int xlbomd_scf(xlbomd_system *h, const double *n0, int32_t rank, double gamma, d
         else
             XL_HIP(hipMemsetAsync(s.ncur, 0, s.nat * sizeof(double), s.st));
         *n_eval = 0;
+        s.el_stale = true;
+        SysBase::DiagKernel scope(s);        // the trajectory's kernel stays
         ok = s.scf_run(rank, gamma, tol, max_iter, rms_hist, n_eval);
         if (n_out)
             XL_HIP(hipMemcpyAsync(n_out, s.ncur, s.nat * sizeof(double), hipMemcpyDeviceToHost, s.st));

@@ -227,6 +227,18 @@ def _eigh_rows(H):
     return w, np.ascontiguousarray(V.T)
 
 
+_C2_REF = {}
+
+
+def _c2_oracle(s, n):
+    """The oracle's solve of the N = 4096 workload at n (eigh for Jacobi),
+    shared by the tests at this size."""
+    key = n.tobytes()
+    if key not in _C2_REF:
+        _C2_REF[key] = R.electronic(R.Model(s), s.pos, n, eig=_eigh_rows)
+    return _C2_REF[key]
+
+
 def test_split_expansion_matches_fp64_at_n4096(P):
     """The 4096-orbital workload the bench times, at a fixed n.
 
@@ -238,8 +250,8 @@ def test_split_expansion_matches_fp64_at_n4096(P):
     times it, i.e. 1.6e-9 (FP64) and 8e-9 (MIXED_BF16X3) before rounding and
     the chemical potential's tolerance.
 
-    MIXED shares the 1e-9 target (8e-9 per atom); FP32 is held to 3e-5, the
-    size its FP32 products reach at this N (see the bound below).
+    MIXED shares the 1e-9 target (8e-9 per atom).  FP32 does not meet the
+    1e-6 bound at this size (test_fp32_expansion_at_n4096).
 
     Between the two GPU paths: MIXED_BF16X3 runs the inverse of every level
     in split bf16x3 and refines Z_{k+1} once against an FP64 residual; its
@@ -248,11 +260,10 @@ def test_split_expansion_matches_fp64_at_n4096(P):
     s = make_system("c2")
     n = 0.02 * np.random.default_rng(6).standard_normal(s.n_atoms)
     n -= n.mean()
-    m = R.Model(s)
-    ref = R.electronic(m, s.pos, n, eig=_eigh_rows)
+    ref = _c2_oracle(s, n)
     out = {}
-    for prec in (P.FP64, P.MIXED_BF16X3, P.MIXED, P.FP32):
-        g = P.XLBOMD(s, precision=prec, scf_tol=2e-5 if prec == P.FP32 else 1e-9)
+    for prec in (P.FP64, P.MIXED_BF16X3, P.MIXED):
+        g = P.XLBOMD(s, precision=prec, scf_tol=1e-9)
         q, rep = g.solve(n)
         out[prec] = q
         g.close()
@@ -261,15 +272,29 @@ def test_split_expansion_matches_fp64_at_n4096(P):
               f"mu {rep['mu']:.12f} vs {ref.mu:.12f}")
     assert np.abs(out[P.FP64] - ref.q).max() < 2e-9
     assert np.abs(out[P.MIXED_BF16X3] - ref.q).max() < 1e-8
-    # MIXED: FP64 expansion with the 1e-9 target.  FP32: besides the rounding
-    # of beta (H - mu) (~eps32 beta |H| on the near-mu levels), every FP32
-    # product over k = 4096 carries ~eps32 sqrt(k) relative error, and the
-    # recursion doubles errors near mu at each of its 5 levels: ~1e-5
+    # MIXED: FP64 expansion with the 1e-9 target
     assert np.abs(out[P.MIXED] - ref.q).max() < 1e-8
-    assert np.abs(out[P.FP32] - ref.q).max() < 3e-5
     dq = np.abs(out[P.FP64] - out[P.MIXED_BF16X3]).max()
     print(f"N=4096 charges, split path vs FP64 path: {dq:.2e}")
     assert dq < 1e-8
+
+
+@pytest.mark.xfail(reason="XLBOMD_FP32 has no higher-precision refinement: besides "
+                   "the rounding of beta (H - mu) (~eps32 beta |H| on the near-mu "
+                   "levels), every FP32 product over k = 4096 carries ~eps32 sqrt(k) "
+                   "relative error, and the recursion doubles errors near mu at each "
+                   "of its 5 levels: ~1e-5 against the 1e-6 bound", strict=False)
+def test_fp32_expansion_at_n4096(P):
+    s = make_system("c2")
+    n = 0.02 * np.random.default_rng(6).standard_normal(s.n_atoms)
+    n -= n.mean()
+    ref = _c2_oracle(s, n)
+    g = P.XLBOMD(s, precision=P.FP32, scf_tol=2e-5)
+    q, rep = g.solve(n)
+    g.close()
+    err = np.abs(q - ref.q).max()
+    print(f"N=4096 FP32: charges vs oracle {err:.2e}")
+    assert err < 1e-6
 
 
 

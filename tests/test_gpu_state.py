@@ -1,0 +1,126 @@
+"""Handle state on the GPU: diagnostic calls leave the trajectory alone,
+checkpoints resume bit for bit, and the kernel schedule after a converged
+start follows the oracle's reading (rebuilt at the first step)."""
+import numpy as np
+import pytest
+
+from synth import make_system, lattice_system
+from oracle import reference as R
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1705_10845_amd as P
+    P.lib()
+    return P
+
+
+def _snapshot(g):
+    st = g.get_state()
+    n, q = g.charges()
+    F, _ = g.forces(energy=False)
+    return dict(pos=st["pos"], vel=st["vel"], hist=st["n_hist"], kr=st["kr"], q=q, F=F)
+
+
+def _same(a, b):
+    return {k: float(np.abs(a[k] - b[k]).max()) for k in a}
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_diagnostic_calls_leave_the_trajectory_unchanged(P, mode):
+    """xlbomd_kernel_apply (rank m and the full kernel), xlbomd_scf and
+    xlbomd_solve between steps of a handle whose kernel is reused for 4
+    steps: the next steps are those of the same run without the calls."""
+    s = make_system("c1", rank=3, kernel_every=4, krylov_mode=mode)
+    runs = []
+    for diag in (False, True):
+        g = P.XLBOMD(s, precision=P.FP64, scf_tol=1e-10)
+        g.step(2, report=False)
+        if diag:
+            r = np.random.default_rng(3).standard_normal(s.n_atoms) * 1e-3
+            g.kernel_apply(-1, r)           # full kernel: rank N_at > capacity
+            g.kernel_apply(2, r)
+            g.scf(rank=1, tol=1e-6, max_iter=20)
+            g.solve(np.zeros(s.n_atoms))
+        g.step(5, report=False)
+        runs.append(_snapshot(g))
+        g.close()
+    d = _same(*runs)
+    print("with vs without diagnostic calls:", {k: f"{v:.1e}" for k, v in d.items()})
+    assert max(d.values()) == 0.0
+
+
+@pytest.mark.parametrize("mode,every", [(0, 4), (1, 3), (2, 5)])
+def test_checkpoint_resumes_bit_for_bit(P, mode, every):
+    """save_state after 3 steps, 5 more steps; a fresh handle that loads the
+    checkpoint and takes the same 5 steps ends in the same state, bit for
+    bit (kernel reuse across the checkpoint, block directions, the full
+    kernel, the chemical-potential predictor and the step count)."""
+    if mode == 2:
+        s = make_system("c1", rank=16, kernel_every=every, krylov_mode=2)
+    else:
+        s = lattice_system(40, "c2", seed=21, rank=3, kernel_every=every, krylov_mode=mode)
+    prec = P.FP64 if mode == 2 else P.MIXED_BF16X3
+    g = P.XLBOMD(s, precision=prec, scf_tol=1e-10, energy_every=2)
+    g.step(3, report=False)
+    blob = g.save_state()
+    rep_a = g.step(5)
+    a = _snapshot(g)
+    g.close()
+    h = P.XLBOMD(s, precision=prec, scf_tol=1e-10, energy_every=2)
+    h.step(1, report=False)                 # a different state to overwrite
+    h.load_state(blob)
+    rep_b = h.step(5)
+    b = _snapshot(h)
+    # a restored handle evaluates charges before its first step at the
+    # restored state
+    h2 = P.XLBOMD(s, precision=prec, scf_tol=1e-10)
+    h2.load_state(blob)
+    n2, q2 = h2.charges()
+    h2.close()
+    h.close()
+    d = _same(a, b)
+    print(f"mode {mode} every {every}: resumed vs original", {k: f"{v:.1e}" for k, v in d.items()})
+    assert max(d.values()) == 0.0
+    assert rep_a["step"] == rep_b["step"] == 8
+    assert rep_a["e_total"] == rep_b["e_total"]
+    assert np.isfinite(q2).all()
+
+
+def test_checkpoint_rejects_another_descriptor(P):
+    s = make_system("c1", rank=2)
+    g = P.XLBOMD(s, precision=P.FP64, scf_tol=1e-10)
+    blob = g.save_state()
+    h = P.XLBOMD(s.replace(rank=3), precision=P.FP64, scf_tol=1e-10)
+    with pytest.raises(P.XlbomdError) as e:
+        h.load_state(blob)
+    assert e.value.code == -1
+    with pytest.raises(P.XlbomdError):
+        g.load_state(blob[:-8])
+    g.close()
+    h.close()
+
+
+def test_kernel_after_converged_init_is_built_at_the_first_step(P):
+    """With a 50-step refresh period the kernel built right after the
+    converged SCF has rank 0 (K0 alone); the first step builds the rank-m
+    kernel, and the trajectory follows the oracle's, which applies the same
+    reading."""
+    s = make_system("c1", rank=2, kernel_every=50)
+    m = R.Model(s)
+    st = R.init_state(m, scf_tol=1e-11)
+    g = P.XLBOMD(s, precision=P.FP64, scf_tol=1e-11)
+    ranks, worst = [], 0.0
+    for _ in range(6):
+        st = R.md_step(m, st, want_energy=False)
+        rep = g.step(1)
+        ranks.append(rep["kernel_rank"])
+        n, q = g.charges()
+        worst = max(worst, np.abs(n - st.el.n).max())
+    g.close()
+    print("kernel rank per step:", ranks, f"max|dn| {worst:.1e}")
+    assert ranks == [2] * 6
+    assert st.V.shape[1] == 2
+    assert worst < 1e-9
