@@ -30,6 +30,7 @@ principles molecular dynamics"):
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional
@@ -284,6 +285,7 @@ class KernelResult:
     K: np.ndarray          # explicit N_at x N_at kernel K_m
     V: np.ndarray          # directions actually used (N_at x m')
     rank: int
+    W: Optional[np.ndarray] = None   # their images (J - I) v_j (N_at x m')
 
 
 def _orth(x, V):
@@ -296,6 +298,24 @@ def _orth(x, V):
     return y, nrm
 
 
+def kernel_from_images(gamma, V, W):
+    """The Sherman-Morrison sequence of Eq. 50 from K0 = -gamma I over given
+    orthonormal directions V (columns, in order) whose images
+    w_j = (J - I) v_j are given in W: a kernel whose images were evaluated
+    at different times (the directions an earlier build left plus those
+    added since)."""
+    nat = V.shape[0]
+    J = (1.0 - 1.0 / gamma) * np.eye(nat)
+    K = -gamma * np.eye(nat)
+    for j in range(V.shape[1]):
+        v = V[:, j]
+        u = W[:, j] + v - J @ v
+        J = J + np.outer(u, v)
+        Ku = K @ u
+        K = K - np.outer(Ku, v @ K) / (1.0 + v @ Ku)
+    return K
+
+
 def kernel_sm(model, el, gamma, m, mode=0, v_prev=None, resp=None,
               floor=R_FLOOR):
     """Rank-m kernel by the Sherman-Morrison sequence (Eq. 50).
@@ -303,8 +323,12 @@ def kernel_sm(model, el, gamma, m, mode=0, v_prev=None, resp=None,
     K0 = -gamma I, i.e. J0 = (1 - 1/gamma) I (Eqs. 48-49).  Directions:
       mode 0: v_1 = K0 r / |K0 r| (Eq. 51), then each v_j is K_{j-1} r
               orthogonalised against v_1..v_{j-1} (Section V.F);
-      mode 1: v_1 as above, then the previous build's directions
-              v_prev[:, 0..m-2], orthogonalised in that order.
+      mode 1: v_1 as above, then the previous build's images
+              w_j = (J - I) v_j, passed as v_prev[:, 0..m-2], orthogonalised
+              in that order: the directions do not depend on this build's
+              responses (all m can be evaluated together), and successive
+              builds are a subspace iteration with J - I, which turns the
+              directions towards its stiffest modes.
     A direction whose orthogonalised norm falls below 1e-10 of its raw norm
     ends the sequence (the space is exhausted).  For a kernel that the
     dynamics will apply to later residuals, a residual with RMS at or below
@@ -320,6 +344,7 @@ def kernel_sm(model, el, gamma, m, mode=0, v_prev=None, resp=None,
     K = -gamma * np.eye(nat)
     r = el.r
     Vs = np.zeros((nat, 0))
+    Ws = np.zeros((nat, 0))
     for i in range(m):
         if mode == 1 and i > 0:
             if v_prev is None or i - 1 >= v_prev.shape[1]:
@@ -336,13 +361,15 @@ def kernel_sm(model, el, gamma, m, mode=0, v_prev=None, resp=None,
         if nrm <= 1e-10 * raw:
             break
         v = v / nrm
-        u = resp(v) - J @ v
+        jv = resp(v)
+        u = jv - J @ v
         J = J + np.outer(u, v)
         Ku = K @ u
         vK = v @ K
         K = K - np.outer(Ku, vK) / (1.0 + v @ Ku)
         Vs = np.column_stack([Vs, v])
-    return KernelResult(K=K, V=Vs, rank=Vs.shape[1])
+        Ws = np.column_stack([Ws, jv - v])
+    return KernelResult(K=K, V=Vs, rank=Vs.shape[1], W=Ws)
 
 
 # ---------------------------------------------------------------------------
@@ -358,6 +385,9 @@ class State:
     K: Optional[np.ndarray]       # explicit kernel of the last build
     V: Optional[np.ndarray]       # its directions
     el: Electronic
+    W: Optional[np.ndarray] = None  # their images (J - I) v_j
+    n_rb: int = 0                   # columns of V from the last rebuild
+    W_rb: Optional[np.ndarray] = None  # the last rebuild's images (block mode)
     step: int = 0
     energy: Dict[str, float] = field(default_factory=dict)
     # the last low-rank build for the dynamics stopped at rank 0 although a
@@ -374,11 +404,12 @@ def auto_gamma(model, el, iters=AUTO_GAMMA_ITERS):
     """K0 = -gamma I with gamma from the stiffest charge-response mode.
 
     Power iteration v <- -J v / |J v| from v = r/|r| (e_0 if r = 0) gives
-    |lambda_max(J)| ~ |J v|; gamma = floor(100 * 1.5 / (1 + |lambda|)) / 100
-    clipped to [0.01, 1] keeps every eigenvalue of K0 (J - I) below 1.5, so
-    the kernel SCF contracts and the electronic Verlet stays stable on modes
-    the low-rank update does not capture.  The 0.01 grid makes the choice
-    insensitive to rounding.
+    |lambda_max(J)| ~ |J v|; gamma = 1.5 / (1 + |lambda|) rounded down to
+    two significant digits, clipped to [1e-4, 1], keeps every eigenvalue e
+    of K0 (J - I) below 1.5, so the kernel SCF contracts and the electronic
+    Verlet step (stable for kappa e < 4, Section II.F) stays stable on modes
+    the low-rank update does not capture.  The relative grid makes the
+    choice insensitive to rounding in lambda.
     """
     r = el.r
     v = r.copy() if np.linalg.norm(r) > 0 else np.eye(model.nat)[0]
@@ -388,8 +419,12 @@ def auto_gamma(model, el, iters=AUTO_GAMMA_ITERS):
         w = response(model, el, v)
         lam = np.linalg.norm(w)
         v = -w / lam
-    g = np.floor(100.0 * 1.5 / (1.0 + lam)) / 100.0
-    return float(min(1.0, max(0.01, g))), float(lam)
+    g0 = 1.5 / (1.0 + lam)
+    g = 1.0
+    if g0 < 1.0:
+        sc = 10.0 ** (1.0 - math.floor(math.log10(g0)))
+        g = math.floor(g0 * sc) / sc
+    return float(min(1.0, max(1e-4, g))), float(lam)
 
 
 def scf(model, pos, gamma, m, tol=1e-10, max_iter=200, n0=None,
@@ -424,13 +459,14 @@ def init_state(model, pos=None, vel=None, scf_tol=1e-10, gamma=None,
     hist = np.tile(el.n, (s.kmax + 1, 1))            # Eq. 20: ndot(t0) = 0
     pending = False
     if s.krylov_mode == 2:
-        K, V = kernel_full(model, el), None
+        K, V, W = kernel_full(model, el), None, None
     else:
         kres = kernel_sm(model, el, gamma, rank, mode=s.krylov_mode)
-        K, V = kres.K, kres.V
+        K, V, W = kres.K, kres.V, kres.W
         pending = rank > 0 and kres.rank == 0
     st = State(pos=pos, vel=vel, force=forces(model, pos, el), n_hist=hist,
-               kr=K @ el.r, K=K, V=V, el=el, pending=pending)
+               kr=K @ el.r, K=K, V=V, W=W, el=el, pending=pending,
+               n_rb=0 if V is None else V.shape[1], W_rb=W)
     st.energy = energy_report(model, st)
     return st
 
@@ -463,19 +499,38 @@ def md_step(model, st, gamma=None, rank=None, want_energy=True):
     F = forces(model, pos, el)
     step = st.step + 1
     pending = False
+    n_rb, W_rb = st.n_rb, st.W_rb
     if (step % s.kernel_every == 0 or st.K is None) and s.krylov_mode == 2:
-        K, V = kernel_full(model, el), None
+        K, V, W = kernel_full(model, el), None, None
     elif step % s.kernel_every == 0 or st.K is None or st.pending:
         kres = kernel_sm(model, el, gamma, rank, mode=s.krylov_mode,
-                         v_prev=st.V)
-        K, V = kres.K, kres.V
+                         v_prev=st.W_rb)
+        K, V, W = kres.K, kres.V, kres.W
+        n_rb, W_rb = kres.rank, kres.W
         pending = rank > 0 and kres.rank == 0
+    elif getattr(s, "kernel_otf", 0) > 0:
+        # Section V.E: the previous step's kernel is the estimate K0(t) that
+        # one rank-1 update along v = K0(t) r / |K0(t) r| improves; the
+        # updates accumulate between rebuilds in a window of kernel_otf
+        # directions (the oldest leaves when it is full)
+        V, W, n_rb, W_rb = st.V, st.W, st.n_rb, st.W_rb
+        if V.shape[1] - n_rb >= s.kernel_otf:
+            V = np.delete(V, n_rb, axis=1)
+            W = np.delete(W, n_rb, axis=1)
+        cand = st.K @ el.r
+        raw = np.linalg.norm(cand)
+        v, nrm = _orth(cand, V)
+        if raw > 0.0 and nrm > 1e-10 * raw:
+            v = v / nrm
+            V = np.column_stack([V, v])
+            W = np.column_stack([W, response(model, el, v) - v])
+        K = kernel_from_images(gamma, V, W)
     else:
-        K, V = st.K, st.V
+        K, V, W, n_rb, W_rb = st.K, st.V, st.W, st.n_rb, st.W_rb
     kr = K @ el.r
     vel = vel + 0.5 * dt * F / m
     nst = State(pos=pos, vel=vel, force=F, n_hist=hist, kr=kr, K=K, V=V,
-                el=el, step=step, pending=pending)
+                W=W, el=el, step=step, pending=pending, n_rb=n_rb, W_rb=W_rb)
     if want_energy:
         nst.energy = energy_report(model, nst)
     return nst
