@@ -118,7 +118,10 @@ typedef struct {
     int32_t kmax;                 /* 5, 6 or 7: Table I row                 */
     int32_t kernel_rank;          /* m in 0..min(n_atoms, 16) (0 = K0 only) */
     int32_t kernel_every;         /* rebuild the kernel every k steps (>=1) */
-    int32_t krylov_mode;          /* 0 sequential Krylov, 1 block, 2 full
+    int32_t krylov_mode;          /* 0 sequential Krylov (v_{j+1} from this
+                                     build's w_j = (J - I) v_j), 1 block (v_1
+                                     and the previous build's w_j, all m
+                                     responses in one batch), 2 full
                                      kernel (J - I)^-1 from n_atoms responses
                                      in batches of min(kernel_rank, 16),
                                      rebuilt every kernel_every steps; the
@@ -127,8 +130,8 @@ typedef struct {
                                      at init from the stiffest response mode:
                                      20 power iterations v <- -Jv/|Jv| from
                                      r/|r| give |lambda|, and gamma =
-                                     floor(150/(1+|lambda|))/100 in
-                                     [0.01, 1]                              */
+                                     1.5/(1+|lambda|) rounded down to two
+                                     significant digits, in [1e-4, 1]       */
     int32_t precision;            /* xlbomd_precision                       */
     double scf_tol;               /* RMS residual of the initial SCF        */
     int32_t scf_max_iter;
@@ -160,6 +163,17 @@ typedef struct {
                                      above this: 0 = 1e-6 (FP64) / 1e-3
                                      (other precisions); else in
                                      [1e-12, 1e-1]                          */
+    int32_t kernel_otf;           /* on-the-fly rank-1 updates between
+                                     rebuilds (Section V.E), 0 = none: at
+                                     every step that does not rebuild, the
+                                     previous step's kernel K0 gets one
+                                     rank-1 update along K0 r / |K0 r|
+                                     (orthogonalised against the kept
+                                     directions, response at the current
+                                     state); up to kernel_otf such directions
+                                     are kept after the rebuild's, the oldest
+                                     leaving first.  kernel_rank + kernel_otf
+                                     <= 16                                  */
 } xlbomd_desc;
 
 typedef struct {
@@ -234,7 +248,7 @@ int xlbomd_get_state(xlbomd_system *h, double *pos, double *vel,
 /* Checkpoint / resume.  A checkpoint holds everything the next step reads:
  * positions, velocities and forces, the n history of Eq. 23, K r(t), the
  * trajectory's kernel (directions V, W = J V - V, the previous build's
- * directions, the full kernel of krylov_mode 2), the chemical-potential
+ * W for block mode, the full kernel of krylov_mode 2), the chemical-potential
  * history that predicts the next solve's mu, the step count and the K0
  * constant.  Stepping a handle after xlbomd_load_state repeats, bit for
  * bit, what the saved handle did after xlbomd_save_state.

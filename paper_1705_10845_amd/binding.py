@@ -80,6 +80,7 @@ class Desc(ctypes.Structure):
         ("energy_every", ctypes.c_int32), ("stream", ctypes.c_void_p),
         ("allocator", ctypes.POINTER(Allocator)), ("foe_levels", ctypes.c_int32),
         ("foe_tol", ctypes.c_double), ("mu_tol", ctypes.c_double),
+        ("kernel_otf", ctypes.c_int32),
     ]
 
 
@@ -263,6 +264,7 @@ class XLBOMD:
         d.stream = stream
         d.foe_levels = foe_levels
         d.foe_tol, d.mu_tol = float(foe_tol), float(mu_tol)
+        d.kernel_otf = int(getattr(s, "kernel_otf", 0))
         if allocator == "torch":
             allocator = TorchAllocator()
         self.allocator = allocator

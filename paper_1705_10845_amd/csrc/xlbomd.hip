@@ -255,6 +255,9 @@ struct SysBase {
     double *hscal = nullptr;   // pinned host scalars
     int head = 0;              // ring index of n(t) in hist
     int mcap = 0, rank_built = 0, rank_prev = 0, step_no = 0;
+    // columns of V, W from the last rebuild, and on-the-fly directions
+    // appended after them since (rank_built = rank_rb + otf_count)
+    int rank_rb = 0, otf_count = 0;
     int bcap = 0;              // response batch capacity
     double *fscr = nullptr;    // forces of an energy evaluation (the MD forces stay)
     double *rdiag = nullptr;   // residual handed to a diagnostic kernel build
@@ -267,13 +270,13 @@ struct SysBase {
     // not to the MD state n(t), R(t)
     bool el_stale = false;
 
-    // The trajectory's kernel lives in V, W, Vprev, gj (with rank_built,
-    // rank_prev, full_built).  Diagnostic calls (xlbomd_kernel_apply,
+    // The trajectory's kernel lives in V, W, Vprev (the previous build's
+    // images W, block mode), gj (with rank_built, rank_prev, full_built).  Diagnostic calls (xlbomd_kernel_apply,
     // xlbomd_scf) build theirs in a second set swapped in for the call, so
     // the MD kernel applied between rebuilds is never replaced by theirs.
     struct KernSet {
         double *V = nullptr, *W = nullptr, *Vprev = nullptr, *gj = nullptr;
-        int rank_built = 0, rank_prev = 0;
+        int rank_built = 0, rank_prev = 0, rank_rb = 0, otf_count = 0;
         bool full_built = false;
     } kdiag;
     void swap_kernel_set();
@@ -391,7 +394,7 @@ struct SysBase {
         A(scal, 64); A(cvec, 8);
         A(lz_v, N); A(lz_vp, N); A(lz_w, N); A(lz_v0, N); A(lz_ab, 2 * LZ_M);
         A(nbl, (size_t)nat * NB_MAX); A(nbc, nat);
-        mcap = std::max(1, std::min(d.kernel_rank, 16));
+        mcap = std::max(1, std::min(d.kernel_rank + d.kernel_otf, 16));
         A(V, (size_t)mcap * nat); A(W, (size_t)mcap * nat); A(Vprev, (size_t)mcap * nat);
         A(vtmp, nat); A(vin, (size_t)mcap * nat); A(qp, (size_t)mcap * nat); A(hb, (size_t)mcap * nat);
         A(fscr, 3 * nat); A(rdiag, nat);
@@ -602,8 +605,10 @@ struct SysBase {
             if (hscal[24 + 1] > 0.0 && (!floor || rms_r > 1e-8)) rank = 1;
         }
         if (rank > 0 && mode == 1) {
-            // block mode: v_1 plus the previous build's directions,
-            // orthogonalised in order, all responses in one batch
+            // block mode: v_1 plus the previous build's images
+            // w_j = (J - I) v_j (kept in Vprev), orthogonalised in order,
+            // all responses in one batch; successive builds form a
+            // subspace iteration with J - I towards its stiffest modes
             if (use_prev)
                 for (int j = 1; j < m && j - 1 < rank_prev; ++j) {
                     hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(1024), 0, st, nat, j, V,
@@ -634,9 +639,11 @@ struct SysBase {
             }
         }
         rank_built = rank;
+        rank_rb = rank;
+        otf_count = 0;
         full_built = false;
         if (rank > 0) {
-            XL_HIP(hipMemcpyAsync(Vprev, V, (size_t)rank * nat * sizeof(double),
+            XL_HIP(hipMemcpyAsync(Vprev, W, (size_t)rank * nat * sizeof(double),
                                   hipMemcpyDeviceToDevice, st));
             rank_prev = rank;
         } else {
@@ -644,6 +651,39 @@ struct SysBase {
         }
         if (floor) kernel_pending = (m > 0 && rank == 0);
         return rank;
+    }
+
+    // On-the-fly rank-1 update between rebuilds (Section V.E): the previous
+    // step's kernel is the estimate K0(t), improved by one rank-1 update
+    // along v = K0(t) r / |K0(t) r| orthogonalised against the kept
+    // directions, with its response at the current state.  The updates
+    // accumulate after the rebuild's directions in a window of kernel_otf
+    // columns; when it is full the oldest leaves first.
+    void otf_update() {
+        const int win = std::min(d.kernel_otf, mcap - rank_rb);
+        if (win <= 0) return;
+        apply_kernel(r, vtmp);                          // K0(t) r(t)
+        if (otf_count >= win) {
+            const size_t b = nat * sizeof(double);
+            for (int j = rank_rb; j + 1 < rank_built; ++j) {
+                XL_HIP(hipMemcpyAsync(V + (size_t)j * nat, V + (size_t)(j + 1) * nat, b,
+                                      hipMemcpyDeviceToDevice, st));
+                XL_HIP(hipMemcpyAsync(W + (size_t)j * nat, W + (size_t)(j + 1) * nat, b,
+                                      hipMemcpyDeviceToDevice, st));
+            }
+            --otf_count;
+            rank_built = rank_rb + otf_count;
+        }
+        const int j = rank_built;
+        hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(1024), 0, st, nat, j, V, vtmp, 1.0,
+                           V + (size_t)j * nat, scal + 24);
+        XL_LAUNCH_CHECK();
+        XL_HIP(hipMemcpyAsync(hscal + 24, scal + 24, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        if (!(hscal[24] > 0.0 && hscal[25] > 1e-10 * hscal[24])) return;
+        responses(1, V + (size_t)j * nat, qp, W + (size_t)j * nat);
+        ++otf_count;
+        rank_built = rank_rb + otf_count;
     }
 
     // K_m r with the low-rank kernel last built (at most mcap directions)
@@ -769,6 +809,8 @@ struct SysBase {
         } else {
             if (step_no % std::max(1, d.kernel_every) == 0 || kernel_pending)
                 build_kernel(d.kernel_rank, d.krylov_mode, true);
+            else if (d.kernel_otf > 0)
+                otf_update();
             apply_kernel(r, kr);
         }
         hipLaunchKernelGGL(kick_drift_kernel, dim3(nthr3), dim3(256), 0, st, nat, 0.5 * dt, 0.0,
@@ -787,9 +829,11 @@ struct SysBase {
 
     // K0 = -gamma I with gamma from the stiffest charge-response mode (the
     // descriptor's k0_gamma == 0): power iteration v <- -J v / |J v| from
-    // v = r/|r| gives |lambda_max(J)| ~ |J v|, and gamma =
-    // floor(100 * 1.5 / (1 + |lambda|)) / 100 in [0.01, 1] keeps every
-    // eigenvalue of K0 (J - I) below 1.5.  At the solve of the current n.
+    // v = r/|r| gives |lambda_max(J)| ~ |J v|, and gamma = 1.5 / (1 +
+    // |lambda|) rounded down to two significant digits, in [1e-4, 1], keeps
+    // every eigenvalue of K0 (J - I) below 1.5, inside the stability range
+    // kappa e < 4 of the electronic Verlet step.  At the solve of the
+    // current n.
     double auto_gamma(int iters = 20) {
         // v = r / |r| (scale 1); r = 0 falls back to e_0
         hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(1024), 0, st, nat, 0, V, r, 1.0, vin,
@@ -813,9 +857,16 @@ struct SysBase {
             sync();
             lam = hscal[24];
         }
-        const double g = std::floor(100.0 * 1.5 / (1.0 + lam)) / 100.0;
+        // 1.5 / (1 + |lambda|) rounded down to two significant digits (a
+        // relative grid keeps the choice insensitive to rounding in lambda)
+        const double g0 = 1.5 / (1.0 + lam);
+        double g = 1.0;
+        if (g0 < 1.0) {
+            const double sc = std::pow(10.0, 1.0 - std::floor(std::log10(g0)));
+            g = std::floor(g0 * sc) / sc;
+        }
         if (debug()) std::fprintf(stderr, "[xlbomd] auto gamma: |lambda| %.4f gamma %.2f\n", lam, g);
-        return std::min(1.0, std::max(0.01, g));
+        return std::min(1.0, std::max(1e-4, g));
     }
 
     // ---- initial state (Eqs. 20, 52) ----
@@ -918,6 +969,7 @@ struct CkHead {
     uint64_t magic;
     int32_t version, nat, no, kmax, mcap, krylov_mode, precision, full;
     int32_t step_no, rank_built, rank_prev, mu_known, kernel_pending;
+    int32_t rank_rb, otf_count;
     double mu, mu_prev, mu_prev2, k0_gamma;
 };
 static_assert(sizeof(CkHead) % 8 == 0, "checkpoint header keeps the doubles aligned");
@@ -938,6 +990,7 @@ void save_state(SysBase &s, char *buf) {
     h.full = s.full_built ? 1 : 0;
     h.step_no = s.step_no; h.rank_built = s.rank_built; h.rank_prev = s.rank_prev;
     h.mu_known = s.mu_known; h.kernel_pending = s.kernel_pending ? 1 : 0;
+    h.rank_rb = s.rank_rb; h.otf_count = s.otf_count;
     h.mu = s.mu; h.mu_prev = s.mu_prev; h.mu_prev2 = s.mu_prev2; h.k0_gamma = s.d.k0_gamma;
     std::memcpy(buf, &h, sizeof(h));
     double *p = reinterpret_cast<double *>(buf + sizeof(h));
@@ -968,7 +1021,8 @@ void load_state(SysBase &s, const char *buf, size_t bytes) {
         h.krylov_mode != s.d.krylov_mode || h.precision != s.d.precision)
         throw InvalidArg("checkpoint written by a handle with another descriptor");
     if (h.rank_built < 0 || h.rank_built > (h.full ? s.nat : s.mcap) || h.rank_prev < 0 ||
-        h.rank_prev > s.mcap || h.mu_known < 0 || h.mu_known > 2 || !(h.k0_gamma > 0.0))
+        h.rank_prev > s.mcap || h.mu_known < 0 || h.mu_known > 2 || !(h.k0_gamma > 0.0) ||
+        h.rank_rb < 0 || h.otf_count < 0 || (!h.full && h.rank_rb + h.otf_count != h.rank_built))
         throw InvalidArg("checkpoint fields out of range");
     const double *p = reinterpret_cast<const double *>(buf + sizeof(h));
     const size_t nat = s.nat, m = s.mcap;
@@ -1000,6 +1054,8 @@ void load_state(SysBase &s, const char *buf, size_t bytes) {
     s.rank_prev = h.rank_prev;
     s.mu_known = h.mu_known;
     s.kernel_pending = h.kernel_pending != 0;
+    s.rank_rb = h.rank_rb;
+    s.otf_count = h.otf_count;
     s.mu = h.mu;
     s.mu_prev = h.mu_prev;
     s.mu_prev2 = h.mu_prev2;
@@ -1016,6 +1072,8 @@ void SysBase::swap_kernel_set() {
     std::swap(gj, kdiag.gj);
     std::swap(rank_built, kdiag.rank_built);
     std::swap(rank_prev, kdiag.rank_prev);
+    std::swap(rank_rb, kdiag.rank_rb);
+    std::swap(otf_count, kdiag.otf_count);
     std::swap(full_built, kdiag.full_built);
 }
 
@@ -1892,6 +1950,8 @@ void validate(const xlbomd_desc *d) {
     if (d->kernel_rank < 0 || d->kernel_rank > d->n_atoms || d->kernel_rank > 16)
         throw InvalidArg("kernel_rank must be in 0..min(n_atoms, 16)");
     if (d->kernel_every < 1) throw InvalidArg("kernel_every must be >= 1");
+    if (d->kernel_otf < 0 || d->kernel_rank + d->kernel_otf > 16)
+        throw InvalidArg("kernel_otf must be in 0..16 - kernel_rank");
     if (d->foe_levels < 0 || d->foe_levels > 40) throw InvalidArg("foe_levels must be in 0..40");
     if (d->krylov_mode < 0 || d->krylov_mode > 2) throw InvalidArg("krylov_mode is 0, 1 or 2");
     if (!(d->k0_gamma >= 0.0 && d->k0_gamma <= 1.0))

@@ -50,6 +50,7 @@ class System:
     krylov_mode: int           # 0 sequential Krylov, 1 block directions
     k0_gamma: float            # K0 = -gamma * I
     steps: int
+    kernel_otf: int = 0        # on-the-fly rank-1 directions kept between rebuilds
 
     @property
     def n(self) -> int:
@@ -144,7 +145,7 @@ CONFIGS = {
                hop_decay=1.2, hop_cutoff=5.0, taper_width=0.5,
                u_range=(0.8, 1.2), gamma_soft=1.0, rep_a=5.8, rep_decay=0.6,
                te=0.05, dt=0.5, kmax=5, rank=4, kernel_every=1,
-               krylov_mode=0, k0_gamma=0.1, steps=1000),
+               krylov_mode=0, k0_gamma=0.0, steps=1000),
     # Small-gap metallic case, N = 8192.
     "c3": dict(index=3, dims=(8, 16, 16), spacing=2.5, jitter=0.15, n_orb=4,
                onsite=_SP_ONSITE_SMALL_GAP, onsite_jitter=0.0,
@@ -165,7 +166,7 @@ CONFIGS = {
                hop_decay=1.2, hop_cutoff=5.0, taper_width=0.5,
                u_range=(0.8, 1.2), gamma_soft=1.0, rep_a=5.8, rep_decay=0.6,
                te=0.05, dt=0.5, kmax=5, rank=6, kernel_every=50,
-               krylov_mode=0, k0_gamma=0.0, steps=2000,
+               krylov_mode=0, k0_gamma=0.0, steps=2000, kernel_otf=10,
                n_atoms=4096, density=0.06, rmin=1.2),
 }
 
@@ -197,7 +198,7 @@ def _finish(name, cfg, rng, pos, n_atoms, overrides):
         dt=float(cfg["dt"]), kmax=int(cfg["kmax"]), rank=int(cfg["rank"]),
         kernel_every=int(cfg["kernel_every"]),
         krylov_mode=int(cfg["krylov_mode"]), k0_gamma=float(cfg["k0_gamma"]),
-        steps=int(cfg["steps"]))
+        steps=int(cfg["steps"]), kernel_otf=int(cfg.get("kernel_otf", 0)))
     sysd.update(overrides)
     return System(**sysd)
 

@@ -1,0 +1,81 @@
+"""Parity at the full size of the benchmarked workload (1024 atoms x 4
+orbitals, N = 4096), against the oracle's stored values
+(tests/golden/c2_n4096_full.txt, written by tests/golden/make_sample.py):
+charges, chemical potential, free energy and entropy, forces, canonical
+responses to two fixed unit directions (Section V.B) and K_4 r from the
+literal Sherman-Morrison sequence (Eqs. 48-51).
+
+The GPU state is set to the stored n (history filled with it) at the
+generated positions; the response is taken at that solve, and K_4 r is
+built from the oracle's residual r = q - n with the same sequential
+directions (K_m r depends only on their span).
+
+Bounds: FP64 charges within 2e-9 (per atom 8x the 2e-10 truncation target
+plus rounding), MIXED_BF16X3 within 1e-8 (8x its 1e-9 target); forces 1e-5;
+relative free energy 1e-8; responses and K_4 r relative to their largest
+element: 1e-6 (FP64 products) and 1e-3 (split bf16x3 products, ~2^-16
+relative per operand through 3 products per level).
+"""
+import importlib.util
+import os
+
+import numpy as np
+import pytest
+
+from synth import make_system
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _gen():
+    spec = importlib.util.spec_from_file_location(
+        "make_sample", os.path.join(HERE, "golden", "make_sample.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    return gen
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1705_10845_amd as P
+    P.lib()
+    return P
+
+
+BOUNDS = {
+    "FP64": dict(q=2e-9, mu=1e-9, F=1e-5, omega=1e-8, resp=1e-6, kr=1e-6),
+    "MIXED_BF16X3": dict(q=1e-8, mu=1e-9, F=1e-5, omega=1e-8, resp=1e-3, kr=1e-3),
+}
+
+
+@pytest.mark.parametrize("prec_name", ["FP64", "MIXED_BF16X3"])
+def test_c2_full_size_against_stored_oracle(P, prec_name):
+    gen = _gen()
+    scal, rows = gen.read_full("c2", 4096)
+    s = make_system("c2")
+    assert rows.shape == (s.n_atoms, 7)
+    n = gen.charge_vector(s.n_atoms)
+    q_ref, resp_ref, kr_ref, F_ref = rows[:, 0], rows[:, 1:3].T, rows[:, 3], rows[:, 4:7]
+    g = P.XLBOMD(s, precision=getattr(P, prec_name), scf_tol=1e-9, k0_gamma=gen.KERNEL_GAMMA)
+    g.set_state(n_hist=np.tile(n, (s.kmax + 1, 1)))
+    _, q = g.charges()
+    F, e = g.forces()
+    V = np.stack([gen.unit_direction(s.n_atoms, sd) for sd in gen.DIR_SEEDS])
+    dq = g.response(V)
+    kr = g.kernel_apply(gen.KERNEL_RANK, q_ref - n)
+    g.close()
+    err = dict(
+        q=np.abs(q - q_ref).max(),
+        mu=abs(e["mu"] - scal["mu"]),
+        F=np.abs(F - F_ref).max(),
+        omega=abs(e["omega"] - scal["omega"]) / abs(scal["omega"]),
+        resp=max(np.abs(dq[i] - resp_ref[i]).max() / np.abs(resp_ref[i]).max() for i in range(2)),
+        kr=np.abs(kr - kr_ref).max() / np.abs(kr_ref).max(),
+    )
+    print(f"N=4096 {prec_name} vs stored oracle:", {k: f"{v:.2e}" for k, v in err.items()},
+          f"TS {e['te_s']:.10f} (oracle {scal['te_s']:.10f})")
+    for k, b in BOUNDS[prec_name].items():
+        assert err[k] < b, (k, err[k], b)
+    assert abs(dq.sum(axis=1)).max() < 1e-8      # canonical: charge conserved
