@@ -152,7 +152,7 @@ CONFIGS = {
                hop_block="rand", hop_decay=1.2, hop_cutoff=5.0,
                taper_width=0.5, u_range=(0.8, 1.2), gamma_soft=1.0,
                rep_a=5.8, rep_decay=0.6, te=0.02, dt=0.5, kmax=5, rank=8,
-               kernel_every=1, krylov_mode=1, k0_gamma=0.0, steps=500),
+               kernel_every=1, krylov_mode=0, k0_gamma=0.0, steps=500),
     # Serving stream element template (sizes drawn per request).
     "c4": dict(index=4, dims=None, spacing=2.5, jitter=0.15, n_orb=4,
                onsite=_SP_ONSITE, onsite_jitter=0.0, hop_block="rand",
