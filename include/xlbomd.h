@@ -209,14 +209,47 @@ int xlbomd_init_system(const xlbomd_desc *desc, xlbomd_system **out);
  * restore a checkpoint taken with xlbomd_get_state via xlbomd_set_state. */
 int xlbomd_step(xlbomd_system *h, int32_t n_steps, xlbomd_report *last);
 
-/* Advance n_steps steps of `count` independent systems concurrently: each
- * handle is stepped by its own host thread on its own stream, so the device
- * overlaps their kernels.  Handles must be distinct and must not share a
- * stream (shared streams serialise).  reports (count entries) and status
- * (count entries) are optional.  Returns the first failing status, with the
- * system index in xlbomd_last_error(); the other systems still advance. */
+/* Advance n_steps steps of `count` independent systems concurrently.  When
+ * every handle takes planned steps (xlbomd_set_step_mode 1 or 2) one host
+ * thread enqueues each system's step on its own stream (a graph replay in
+ * mode 2) before waiting for any, so the device runs them together;
+ * otherwise each handle is stepped by its own host thread.  Handles must
+ * be distinct and must not share a stream (shared streams serialise).
+ * reports (count entries) and status (count entries) are optional.
+ * Returns the first failing status, with the system index in
+ * xlbomd_last_error(); the other systems still advance. */
 int xlbomd_step_batch(xlbomd_system *const *hs, int32_t count, int32_t n_steps,
                       xlbomd_report *reports, int32_t *status);
+
+/* How xlbomd_step and xlbomd_step_batch take a step.
+ *   0 (default): host decisions.  The level count of the expansion and its
+ *     Newton-Schulz schedule follow the step's spectral interval, the
+ *     expansion is rerun until the chemical potential is within the
+ *     threshold, and the Krylov directions stop at a breakdown; each of
+ *     these reads device values back to the host.
+ *   1: planned steps.  A plan (level count and schedule for the last
+ *     interval widened by 25%) is made on the host; every decision of a
+ *     step is then taken on the device: the interval and the predicted
+ *     chemical potential are checked against the plan, one rerun of the
+ *     expansion at the corrected chemical potential runs only when needed
+ *     (its launches skip themselves otherwise), D gets the second-order
+ *     correction, and the kernel's rank comes from the direction norms.
+ *     One synchronisation per step reads the step's status.  A step that
+ *     leaves its plan (interval beyond it, chemical potential not within the
+ *     threshold after one rerun, a non-finite value) is taken again with
+ *     host decisions from the state saved at its start, and the next step
+ *     is planned anew.
+ *   2: as 1, with each step replayed from a HIP graph captured once per
+ *     plan (the first step of a plan runs directly, the second is captured).
+ * Modes 1 and 2 need krylov_mode 0, kernel_every 1 and kernel_otf 0
+ * (XLBOMD_E_INVALID otherwise).  Steps that evaluate the energy do so after
+ * the planned step, with host synchronisation. */
+int xlbomd_set_step_mode(xlbomd_system *h, int32_t mode);
+
+/* Counters of planned steps since init: out[0] planned steps taken, out[1]
+ * of them replayed from a graph, out[2] graphs captured, out[3] planned
+ * steps that left their plan and were taken again with host decisions. */
+int xlbomd_step_stats(xlbomd_system *h, int64_t *out);
 
 /* Rebuild the low-rank kernel at the current state with rank `rank`
  * (<= 0 keeps the descriptor's rank) and refresh K r (Eqs. 50-51). */

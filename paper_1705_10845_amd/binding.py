@@ -128,6 +128,8 @@ def lib():
                                          ctypes.POINTER(vp)]
         L.xlbomd_step.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Report)]
         L.xlbomd_kernel_update.argtypes = [vp, ctypes.c_int32]
+        L.xlbomd_set_step_mode.argtypes = [vp, ctypes.c_int32]
+        L.xlbomd_step_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         L.xlbomd_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32,
                                         ctypes.c_int32, ctypes.POINTER(Report),
                                         ctypes.POINTER(ctypes.c_int32)]
@@ -157,7 +159,7 @@ def lib():
 
 
 EXPORTED = ("xlbomd_init_system", "xlbomd_step", "xlbomd_step_batch",
-            "xlbomd_kernel_update",
+            "xlbomd_set_step_mode", "xlbomd_step_stats", "xlbomd_kernel_update",
             "xlbomd_forces", "xlbomd_get_charges", "xlbomd_set_state",
             "xlbomd_get_state", "xlbomd_state_size", "xlbomd_save_state",
             "xlbomd_load_state", "xlbomd_solve", "xlbomd_response",
@@ -288,6 +290,16 @@ class XLBOMD:
         rep = Report()
         _check(lib().xlbomd_step(self._h, n, ctypes.byref(rep) if report else None))
         return rep.as_dict() if report else None
+
+    def set_step_mode(self, mode):
+        """0: host decisions; 1: planned steps (decisions on the device);
+        2: planned steps replayed from a captured HIP graph."""
+        _check(lib().xlbomd_set_step_mode(self._h, int(mode)))
+
+    def step_stats(self):
+        out = (ctypes.c_int64 * 4)()
+        _check(lib().xlbomd_step_stats(self._h, out))
+        return dict(planned=out[0], replays=out[1], captures=out[2], fallbacks=out[3])
 
     def kernel_update(self, rank=0):
         _check(lib().xlbomd_kernel_update(self._h, rank))

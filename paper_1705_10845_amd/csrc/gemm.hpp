@@ -106,6 +106,7 @@ template <typename T> struct GemmArgs {
     T *ws = nullptr;        // split-k partial tiles (nullptr: no split)
     long ws_elems = 0;
     bool split3 = false;    // FP32 only: bf16x3 products (gemm_bf3_kernel)
+    const int *skip = nullptr;  // device flag: the launch does nothing while it is set
 };
 
 constexpr int GT = 128;   // output tile edge
@@ -209,6 +210,7 @@ __device__ __forceinline__ void epilogue(const GemmArgs<T> &p, long bz, int ti, 
 template <typename T, bool SYM, int NW = 4>
 __global__ __launch_bounds__(64 * NW, 2) void gemm_tn_kernel(GemmArgs<T> p, int ntiles, int nfull,
                                                           int nsplit, int per_xcd) {
+    if (p.skip && *p.skip) return;   // skipped launch (device flag)
     // per_xcd: tail units per XCD
     using M = MF<T>;
     using acc_t = typename M::acc_t;
@@ -380,6 +382,7 @@ constexpr int B3P = 20;          // LDS row pitch in 32-bit words (40 bf16)
 template <bool SYM>
 __global__ __launch_bounds__(256, 2) void gemm_bf3_kernel(GemmArgs<float> p, int ntiles, int nfull,
                                                        int nsplit, int per_xcd) {
+    if (p.skip && *p.skip) return;   // skipped launch (device flag)
     using acc_t = f32x4;
     // [buffer][hi, lo][row i][k pairs]
     __shared__ __attribute__((aligned(16))) unsigned As[2][2][GT][B3P];
@@ -513,6 +516,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf3_kernel(GemmArgs<float> p, int
 template <typename T, bool SYM, int NW = 4>
 __global__ __launch_bounds__(256) void gemm_fixup_kernel(GemmArgs<T> p, int ntiles,
                                                          int nfull, int nsplit) {
+    if (p.skip && *p.skip) return;   // skipped launch (device flag)
     using acc_t = typename MF<T>::acc_t;
     constexpr int NTH = 64 * NW, WCN = NW / 2, YB = 16 / NW, NH = NTH / 256;
     const int ntail = ntiles - nfull;

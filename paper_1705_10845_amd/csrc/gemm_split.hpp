@@ -37,6 +37,7 @@ struct SplitArgs {
     long sA0 = 0, sB0 = 0, sA1 = 0, sB1 = 0, sX = 0, sC = 0;   // batch strides (elements)
     float *ws = nullptr;                          // split-k partial tiles (FP32)
     long ws_elems = 0;
+    const int *skip = nullptr;                    // device flag: skip the launch while set
 };
 
 // chunk permutation of LDS row r (values 0..3, rows in pairs): with it the
@@ -99,6 +100,7 @@ constexpr int BS_T = 512;
 template <bool SYM>
 __global__ __launch_bounds__(BS_T, 2) void gemm_bs_kernel(SplitArgs p, int ntiles, int nfull,
                                                        int nsplit, int per_xcd) {
+    if (p.skip && *p.skip) return;   // skipped launch (device flag)
     using acc_t = f32x4;
     // [buffer][hi, lo][row][16-byte chunk]: 32 k per row
     __shared__ __attribute__((aligned(16))) u32x4 As[2][2][GT][4];
@@ -227,6 +229,7 @@ __global__ __launch_bounds__(BS_T, 2) void gemm_bs_kernel(SplitArgs p, int ntile
 template <bool SYM>
 __global__ __launch_bounds__(BS_T) void gemm_bs_fixup_kernel(SplitArgs p, int ntiles, int nfull,
                                                              int nsplit) {
+    if (p.skip && *p.skip) return;   // skipped launch (device flag)
     const int ntail = ntiles - nfull;
     const int u = nfull + blockIdx.x;
     const int g = blockIdx.y, x = g >> 1, y = g & 1;
@@ -306,6 +309,7 @@ struct BwFrag {
 template <bool SYM>
 __global__ __launch_bounds__(BW_NTH, 1) void gemm_bw_kernel(SplitArgs p, int ntiles, int nfull,
                                                          int nsplit, int per_xcd) {
+    if (p.skip && *p.skip) return;   // skipped launch (device flag)
     using acc_t = f32x4;
     constexpr int NTH = BW_NTH;
     constexpr int NA = 2048 / NTH, NB = 1024 / NTH;   // 16-byte chunks per thread
@@ -482,6 +486,7 @@ __global__ __launch_bounds__(BW_NTH, 1) void gemm_bw_kernel(SplitArgs p, int nti
 template <bool SYM>
 __global__ __launch_bounds__(256) void gemm_bw_fixup_kernel(SplitArgs p, int ntiles, int nfull,
                                                             int nsplit) {
+    if (p.skip && *p.skip) return;   // skipped launch (device flag)
     constexpr int NTH = BW_NTH;
     const int ntail = ntiles - nfull;
     const int u = nfull + blockIdx.x;

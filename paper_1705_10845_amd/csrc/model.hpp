@@ -117,14 +117,16 @@ __global__ __launch_bounds__(1024) void minmax_kernel(int n, const double *lo,
 
 // Y = sc * (H - mu I) over the real n x n block, zero in the padding.
 // H[Ia,Ia] = onsite[a] + jit[Ia] + v[I];  H[Ia,Jb] = B_ab exp(-r/decay) s(r).
+// mu_dev != nullptr: mu is read from the device.
 template <typename T>
 __global__ __launch_bounds__(256) void build_seed_kernel(ModelDev m,
                                                          const double *v,
                                                          double mu, double sc,
-                                                         T *Y) {
+                                                         T *Y, const double *mu_dev) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
     if (j >= m.ld) return;
+    if (mu_dev) mu = *mu_dev;
     double val = 0.0;
     if (i < m.n && j < m.n) {
         const int I = i / m.no, a = i % m.no, J = j / m.no, b = j % m.no;
@@ -420,6 +422,7 @@ template <typename T> struct SpmmArgs {
     // and batch strides of the outputs C (elements) and Cs (bf16 elements)
     const double *u = nullptr;
     long su = 0, sC = 0, sCs = 0;
+    const int *skip = nullptr;          // device flag: skip the launch while set
 };
 template <typename T, int NO, bool SCALE>
 __device__ __forceinline__ void spmm_rows(const T *__restrict__ Yr, const T *__restrict__ B,
@@ -446,6 +449,7 @@ __device__ __forceinline__ void spmm_rows(const T *__restrict__ Yr, const T *__r
 }
 template <typename T, int NO>
 __global__ __launch_bounds__(256) void spmm_seed_kernel(SpmmArgs<T> p) {
+    if (p.skip && *p.skip) return;   // skipped launch (device flag)
     const int I = blockIdx.y;
     const long bz = blockIdx.z;
     const int ld = p.ld;
@@ -831,13 +835,16 @@ __global__ __launch_bounds__(1024) void orth_kernel(int nat, int j,
 
 // kr = K_m r with K_m = -gamma (I - W M V^T) + V M V^T, M = (V^T W)^-1
 // (Sherman-Morrison sequence in closed form), m <= 16.  One block.
-__global__ __launch_bounds__(1024) void kernel_apply_kernel(int nat, int m,
+__global__ __launch_bounds__(1024) void kernel_apply_kernel(int nat, int m_arg,
                                                             const double *V,
                                                             const double *W,
                                                             const double *r,
                                                             double gamma,
                                                             double *kr,
-                                                            double *info) {
+                                                            double *info,
+                                                            const int *m_dev) {
+    // m_dev != nullptr: the rank is read from the device (at most m_arg)
+    const int m = m_dev ? min(*m_dev, m_arg) : m_arg;
     __shared__ double sh[16];
     __shared__ double G[16][17];
     __shared__ double c[16];

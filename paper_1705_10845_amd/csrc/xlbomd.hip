@@ -37,6 +37,7 @@
 #include "gemm_split.hpp"
 #include "model.hpp"
 #include "chol.hpp"
+#include "planned.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -216,7 +217,13 @@ struct SysBase {
     DevFree mem;
     // n elements of device memory owned by the system: from the caller's
     // allocator when the descriptor gives one, else hipMalloc
+    // a captured step's launches are valid while no buffer has been
+    // allocated or given back since the capture
+    long alloc_epoch = 0;
+    bool capturing = false;      // a planned step is being captured into a graph
     template <typename T> T *dev(size_t n) {
+        if (capturing) throw StateError("device allocation during graph capture");
+        ++alloc_epoch;
         if (!mem.al.alloc) {
             T *p = dalloc<T>(n);
             mem.ptrs.push_back(p);
@@ -235,6 +242,8 @@ struct SysBase {
     // still uses it; the caller drops its pointer
     void release(void *p) {
         if (!p) return;
+        if (capturing) throw StateError("buffer release during graph capture");
+        ++alloc_epoch;
         sync();
         const auto it = std::find(mem.ptrs.begin(), mem.ptrs.end(), p);
         if (it == mem.ptrs.end()) return;
@@ -330,7 +339,7 @@ struct SysBase {
     } prof;
 
     void prof_begin() {
-        if (!prof.on) return;
+        if (!prof.on || capturing) return;
         if (prof.used + 2 > prof.ev.size()) {
             for (int i = 0; i < 256; ++i) {
                 hipEvent_t e;
@@ -341,7 +350,7 @@ struct SysBase {
         XL_HIP(hipEventRecord(prof.ev[prof.used], st));
     }
     void prof_end(double flops, int cls) {
-        if (!prof.on) return;
+        if (!prof.on || capturing) return;
         XL_HIP(hipEventRecord(prof.ev[prof.used + 1], st));
         prof.flops.push_back(flops);
         prof.cls.push_back(cls);
@@ -356,6 +365,12 @@ struct SysBase {
 
     void sync() { XL_HIP(hipStreamSynchronize(st)); }
 
+    // launches of foe_core skip themselves while *cur_skip is set (the
+    // second expansion of a planned step); seed_sparse: the last expansion
+    // used the sparse-dense seed products
+    const int *cur_skip = nullptr;
+    bool seed_sparse = false;
+
     // truncation target of the expansion against the Fermi function, and
     // the threshold on beta |dmu| above which the expansion is rerun at the
     // corrected chemical potential (descriptor values, else by precision)
@@ -364,6 +379,17 @@ struct SysBase {
     }
     double mu_tol() const {
         return d.mu_tol > 0.0 ? d.mu_tol : (d.precision == XLBOMD_FP64 ? 1e-6 : 1e-3);
+    }
+    // level count for the half-width xmax of the spectrum of beta (H - mu):
+    // the smallest meeting the truncation target, or the descriptor's
+    // request raised where the seed would leave |x / 2^(L+1)| <= 1
+    int levels_for(double xmax) const {
+        if (d.foe_levels > 0) {
+            int Lmin = 1;
+            while (Lmin < 40 && std::ldexp(xmax, -(Lmin + 1)) > 1.0) ++Lmin;
+            return std::max(d.foe_levels, Lmin);
+        }
+        return choose_levels(xmax, trunc_tol());
     }
 
     void upload_model(const xlbomd_desc *ds) {
@@ -454,6 +480,8 @@ struct SysBase {
     virtual void forces_parts(double *F) = 0;   // forces into F (3 n_atoms), energy parts
     virtual double entropy_ts() = 0;        // Te * S at the corrected state
     virtual int levels_cap() const = 0;
+    virtual void solve_planned() = 0;       // planned solve at n(t) = history row 0
+    virtual void kernel_planned() = 0;      // sequential kernel, rank on the device
 
     // ---- electronic solve at charges n (device, nat) ----
     void gershgorin() {
@@ -692,7 +720,7 @@ struct SysBase {
             throw StateError("no low-rank kernel of rank " + std::to_string(rank_built) +
                              " can be applied (capacity " + std::to_string(mcap) + ")");
         hipLaunchKernelGGL(kernel_apply_kernel, dim3(1), dim3(1024), 0, st, nat, rank_built, V, W,
-                           rin, d.k0_gamma, out, scal + 32);
+                           rin, d.k0_gamma, out, scal + 32, (const int *)nullptr);
         XL_LAUNCH_CHECK();
     }
 
@@ -786,6 +814,7 @@ struct SysBase {
     bool full_mode() const { return d.krylov_mode == 2; }
 
     void md_step(bool want_energy, xlbomd_report *rep) {
+        leave_planned();
         const double dt = d.dt;
         const int nthr3 = ceil_div(3 * nat, 256);
         hipLaunchKernelGGL(kick_drift_kernel, dim3(nthr3), dim3(256), 0, st, nat, 0.5 * dt, dt,
@@ -826,6 +855,213 @@ struct SysBase {
             rep->has_energy = want_energy ? 1 : 0;
         }
     }
+
+    // ---- planned steps: device-side decisions, optional HIP graph replay ----
+    // step_mode 0: host decisions (solve, spectral interval, mu reruns and
+    // Krylov breakdowns read back to the host).  1: planned steps, every
+    // decision on the device (planned.hpp), one synchronisation at the end
+    // of a step to read its status.  2: as 1, each step replayed from a HIP
+    // graph captured once per plan.  Planned steps need a kernel rebuilt
+    // every step from sequential Krylov directions without on-the-fly
+    // updates (krylov_mode 0, kernel_every 1, kernel_otf 0).
+    struct Plan {
+        int L = 0;            // levels of the expansion
+        double xmax = 0.0;    // half-width of beta (H - mu) the expansion is sized for
+        bool sparse = false;  // sparse-dense seed products
+    };
+    int step_mode = 0;
+    Plan plan{};
+    bool have_plan = false;
+    bool planned_ready = false;    // ordered n history and device mu history in place
+    double *psd = nullptr, *hps = nullptr;      // device block, pinned status copy
+    int *psi = nullptr, *hpi = nullptr;
+    double *snap = nullptr, *histtmp = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    long graph_epoch = -1, warm_epoch = -1;
+    long n_planned = 0, n_replays = 0, n_captures = 0, n_fallbacks = 0;
+
+    bool planned_capable() const {
+        return d.krylov_mode == 0 && d.kernel_every == 1 && d.kernel_otf == 0;
+    }
+    void drop_graph() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+        graph_epoch = -1;
+    }
+    size_t snap_len() const { return (size_t)(13 + d.kmax + 2 * mcap) * nat; }
+    // the plan: the interval of the last solve around the predicted mu,
+    // widened by 25%
+    void make_plan() {
+        const double mp = mu_known > 0 ? predict_mu() : mu;
+        const double x = beta * std::max(std::fabs(elo - mp), std::fabs(ehi - mp)) * 1.02 + 1e-12;
+        plan.xmax = 1.25 * x;
+        plan.L = levels_for(plan.xmax);
+        plan.sparse = sparse_seed();
+        have_plan = true;
+        drop_graph();
+    }
+    // n history in order (row k = n(t - k dt)), mu history on the device
+    void prepare_planned() {
+        if (!psd) {
+            psd = dev<double>(PS_COUNT);
+            psi = dev<int>(PI_COUNT);
+            snap = dev<double>(snap_len());
+            histtmp = dev<double>((size_t)(d.kmax + 1) * nat);
+            void *hp = nullptr;
+            XL_HIP(hipHostMalloc(&hp, PS_COUNT * sizeof(double) + PI_COUNT * sizeof(int),
+                                 hipHostMallocDefault));
+            hps = (double *)hp;
+            hpi = (int *)(hps + PS_COUNT);
+        }
+        const int K = d.kmax + 1;
+        if (head != 0) {
+            const size_t b = nat * sizeof(double);
+            for (int k = 0; k < K; ++k)
+                XL_HIP(hipMemcpyAsync(histtmp + (size_t)k * nat, hist_row(k), b,
+                                      hipMemcpyDeviceToDevice, st));
+            XL_HIP(hipMemcpyAsync(hist, histtmp, K * b, hipMemcpyDeviceToDevice, st));
+            head = 0;
+        }
+        std::fill(hps, hps + PS_COUNT, 0.0);
+        std::fill(hpi, hpi + PI_COUNT, 0);
+        hps[PS_MUP] = mu_prev;
+        hps[PS_MUPP] = mu_prev2;
+        hpi[PI_MUKNOWN] = mu_known;
+        XL_HIP(hipMemcpyAsync(psd, hps, PS_COUNT * sizeof(double), hipMemcpyHostToDevice, st));
+        XL_HIP(hipMemcpyAsync(psi, hpi, PI_COUNT * sizeof(int), hipMemcpyHostToDevice, st));
+        sync();
+        if (!have_plan) make_plan();
+        planned_ready = true;
+    }
+    // one planned step, enqueued (no host synchronisation)
+    void md_step_planned() {
+        const double dt = d.dt;
+        const int nthr3 = ceil_div(3 * nat, 256);
+        const int K = d.kmax + 1;
+        {   // the state at the start of the step
+            const size_t b = nat * sizeof(double);
+            double *p = snap;
+            auto put = [&](const double *src, size_t n) {
+                XL_HIP(hipMemcpyAsync(p, src, n * b, hipMemcpyDeviceToDevice, st));
+                p += n * nat;
+            };
+            put(pos, 3); put(vel, 3); put(force, 3); put(hist, K); put(kr, 1);
+            put(V, mcap); put(W, mcap);
+        }
+        hipLaunchKernelGGL(kick_drift_kernel, dim3(nthr3), dim3(256), 0, st, nat, 0.5 * dt, dt,
+                           force, mass, vel, pos);
+        XL_LAUNCH_CHECK();
+        const DampRow &row = kDamp[d.kmax - 5];
+        hipLaunchKernelGGL(verlet_shift_kernel, dim3(ceil_div(nat, 256)), dim3(256), 0, st, nat,
+                           d.kmax, row.kappa, row.alpha, (const double *)cvec, (const double *)kr,
+                           hist);
+        XL_LAUNCH_CHECK();
+        solve_planned();
+        forces_parts(force);
+        kernel_planned();
+        hipLaunchKernelGGL(kick_drift_kernel, dim3(nthr3), dim3(256), 0, st, nat, 0.5 * dt, 0.0,
+                           force, mass, vel, (double *)nullptr);
+        XL_LAUNCH_CHECK();
+        XL_HIP(hipMemcpyAsync(hps, psd, PS_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+        XL_HIP(hipMemcpyAsync(hpi, psi, PI_COUNT * sizeof(int), hipMemcpyDeviceToHost, st));
+    }
+    // enqueue one planned step: replay the captured graph, or capture it
+    // (when the previous planned step allocated nothing since), or run it
+    // directly (which may allocate buffers on its first run)
+    void planned_launch() {
+        if (!planned_ready) prepare_planned();
+        ++n_planned;
+        if (step_mode == 2) {
+            if (gexec && graph_epoch == alloc_epoch) {
+                XL_HIP(hipGraphLaunch(gexec, st));
+                ++n_replays;
+                return;
+            }
+            if (warm_epoch == alloc_epoch) {
+                drop_graph();
+                hipGraph_t gr = nullptr;
+                XL_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                capturing = true;
+                try {
+                    md_step_planned();
+                } catch (...) {
+                    capturing = false;
+                    (void)hipStreamEndCapture(st, &gr);
+                    if (gr) (void)hipGraphDestroy(gr);
+                    throw;
+                }
+                capturing = false;
+                XL_HIP(hipStreamEndCapture(st, &gr));
+                const hipError_t e = hipGraphInstantiate(&gexec, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                if (e != hipSuccess) {
+                    gexec = nullptr;
+                    throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+                }
+                graph_epoch = alloc_epoch;
+                ++n_captures;
+                XL_HIP(hipGraphLaunch(gexec, st));
+                ++n_replays;
+                return;
+            }
+        }
+        md_step_planned();
+        warm_epoch = alloc_epoch;
+    }
+    // wait for the planned step, commit it or, if it left its plan, restore
+    // the state it started from and take the step with host decisions
+    void planned_complete(bool want_energy, xlbomd_report *rep) {
+        sync();
+        if (hpi[PI_FLAGS] != 0) {
+            if (debug())
+                std::fprintf(stderr, "[xlbomd] planned step %d left its plan (flags %d): "
+                             "host decisions\n", step_no + 1, hpi[PI_FLAGS]);
+            const size_t b = nat * sizeof(double);
+            const int K = d.kmax + 1;
+            const double *p = snap;
+            auto get = [&](double *dst, size_t n) {
+                XL_HIP(hipMemcpyAsync(dst, p, n * b, hipMemcpyDeviceToDevice, st));
+                p += n * nat;
+            };
+            get(pos, 3); get(vel, 3); get(force, 3); get(hist, K); get(kr, 1);
+            get(V, mcap); get(W, mcap);
+            sync();
+            ++n_fallbacks;
+            planned_ready = false;
+            have_plan = false;          // planned again from this step's interval
+            drop_graph();
+            md_step(want_energy, rep);
+            return;
+        }
+        ++step_no;
+        mu = hps[PS_MU];
+        mu_prev2 = mu_prev;
+        mu_prev = mu;
+        mu_known = std::min(mu_known + 1, 2);
+        dmu = hps[PS_DMU];
+        rms = hps[PS_RMS];
+        sumq = hps[PS_SUMQ];
+        elo = hps[PS_ELO];
+        ehi = hps[PS_EHI];
+        reruns = hpi[PI_RERUN];
+        rank_built = rank_rb = hpi[PI_RANK];
+        otf_count = 0;
+        rank_prev = rank_built;
+        full_built = false;
+        kernel_pending = false;
+        el_stale = false;
+        have_energy = want_energy;
+        if (want_energy) energy(&last);
+        if (rep) {
+            if (want_energy) *rep = last;
+            else std::memset(rep, 0, sizeof(*rep));
+            fill_report(rep);
+            rep->has_energy = want_energy ? 1 : 0;
+        }
+    }
+    // any step or call with host decisions: the ordered history and the
+    // device mu history are set up again before the next planned step
+    void leave_planned() { planned_ready = false; }
 
     // K0 = -gamma I with gamma from the stiffest charge-response mode (the
     // descriptor's k0_gamma == 0): power iteration v <- -J v / |J v| from
@@ -1062,6 +1298,7 @@ void load_state(SysBase &s, const char *buf, size_t bytes) {
     s.d.k0_gamma = h.k0_gamma;
     s.have_energy = false;
     s.el_stale = true;    // D, q, r are solved again before anything reads them
+    s.leave_planned();
 }
 }  // namespace
 
@@ -1107,7 +1344,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
         // H itself (scale 1, no shift) in the seed buffer; the expansion
         // rebuilds its seed there
         hipLaunchKernelGGL((build_seed_kernel<TF>), dim3(ceil_div(Np, 256), Np), dim3(256), 0, st,
-                           md, vpot, 0.0, 1.0, Ys);
+                           md, vpot, 0.0, 1.0, Ys, (const double *)nullptr);
         XL_LAUNCH_CHECK();
         XL_HIP(hipMemcpyAsync(lz_v, lz_v0, N * sizeof(double), hipMemcpyDeviceToDevice, st));
         for (int j = 0; j < LZ_M; ++j) {
@@ -1186,6 +1423,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
 
     template <typename U> void run_gemm(GemmArgs<U> a, bool sym) {
         attach_ws(a);
+        if (cur_skip) a.skip = cur_skip;
         prof_begin();
         gemm(a, sym, st);
         prof_end(gemm_flops(sym, a.A1 ? 2 : 1) * a.batch, sizeof(U) == 8 ? 0 : (a.split3 ? 2 : 1));
@@ -1217,15 +1455,21 @@ template <typename TF, typename TR> struct Sys : SysBase {
 
     void foe(double mu0) override {
         const double xmax = beta * std::max(std::fabs(elo - mu0), std::fabs(ehi - mu0)) * 1.02 + 1e-12;
-        // truncation bound of the expansion vs the Fermi function: 2e-10 for
-        // the all-FP64 mode, 1e-9 (charges within 1e-8) otherwise
-        L = choose_levels(xmax, trunc_tol());
-        if (d.foe_levels > 0) {
-            // a requested count, raised where the seed would leave |y| <= 1
-            int Lmin = 1;
-            while (Lmin < 40 && std::ldexp(xmax, -(Lmin + 1)) > 1.0) ++Lmin;
-            L = std::max(d.foe_levels, Lmin);
-        }
+        foe_core(levels_for(xmax), xmax, mu0, nullptr, nullptr, sparse_seed(), scal, g);
+    }
+
+    // One expansion of L levels sized for the half-width xmax of the
+    // spectrum of beta (H - mu0) (the seed bound and the Newton-Schulz
+    // schedule of every level follow from L and xmax).  mu0 is read from
+    // the device when mu_dev is given; while *skip is set the product
+    // launches do nothing; `sparse` selects the sparse-dense seed products.
+    // The chemical-potential moments {N0, N', dmu, N''} go to st_out, the
+    // diagonal of dD/dmu to g_out.
+    void foe_core(int Lq, double xmax, double mu0, const double *mu_dev, const int *skip,
+                  bool sparse, double *st_out, double *g_out) {
+        L = Lq;
+        cur_skip = skip;
+        seed_sparse = sparse;
         alloc_matrices(L);
         Lr = -1;
         ++expansion_id;
@@ -1233,11 +1477,11 @@ template <typename TF, typename TR> struct Sys : SysBase {
         sc = std::ldexp(beta, -(L + 1));
         // Y = sc (H - mu0 I)
         hipLaunchKernelGGL((build_seed_kernel<TF>), dim3(ceil_div(Np, 256), Np), dim3(256), 0, st,
-                           md, vpot, mu0, sc, Ys);
+                           md, vpot, mu0, sc, Ys, mu_dev);
         XL_LAUNCH_CHECK();
         const double ymax = std::ldexp(xmax, -(L + 1)), ym2 = ymax * ymax;
         t0max = ymax * (1.0 - ym2 / 3.0 + 2.0 * ym2 * ym2 / 15.0);
-        if (sparse_seed()) {
+        if (sparse) {
             // Y2 = Y Y, Y3 = Y Y2, Y4 = Y Y3 (kept for the seed response),
             // Z0 = Y/2 - Y3/6 + Y Y4 / 15, each a sparse-dense product
             SpmmArgs<TF> a{};
@@ -1393,7 +1637,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
                            st, N, Np, Z[L], ZL2, m3);
         XL_LAUNCH_CHECK();
         hipLaunchKernelGGL((mu_step_kernel<TF>), dim3(1), dim3(1024), 0, st, N, Np, Z[L], ZL2, m3,
-                           beta, d.n_electrons, g, scal);
+                           beta, d.n_electrons, g_out, st_out);
         XL_LAUNCH_CHECK();
         if constexpr (FUSE_COPY) {
             convert(Ys, Ysr, 1.0);
@@ -1405,6 +1649,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
             }
             Lr = L;                     // response operands are current
         }
+        cur_skip = nullptr;
     }
 
     // One level on the split path.  A_k = I + 4 Z_k^2 in FP64 (kept for the
@@ -1473,6 +1718,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
     TF *Y4f = nullptr;                // FP64 Y^4 of the sparse seed (when TF != TR)
     void spmm(SpmmArgs<TF> a, int nb = 1) {
         a.nat = nat; a.ld = Np; a.nb = nbl; a.cnt = nbc;
+        if (cur_skip) a.skip = cur_skip;
         if (nb > 1 && Np > N) throw InvalidArg("spmm: batched products need an unpadded matrix");
         const dim3 g(ceil_div(Np, 256), nat, nb);
         switch (no) {
@@ -1518,6 +1764,154 @@ template <typename TF, typename TR> struct Sys : SysBase {
         run_gemm(a, true);
         hipLaunchKernelGGL((charges_kernel<TF>), dim3(1), dim3(1024), 0, st, nat, no, Np, Dc, zc,
                            ncur, q, r, scal + 16);
+        XL_LAUNCH_CHECK();
+    }
+
+    // ---- planned step: the solve and the kernel without host decisions ----
+    // The buffers one expansion writes.  A planned step runs a second
+    // expansion (the rerun at the corrected chemical potential) into a set
+    // of its own, swapped in for its enqueue, and copies it over the first
+    // only when it ran.
+    struct ExpSet {
+        std::vector<TF *> Z, Yk, Ak;
+        TF *Ys = nullptr, *Y2 = nullptr, *Y3 = nullptr, *E = nullptr, *Wk = nullptr;
+        TF *ZL2 = nullptr, *Y4f = nullptr;
+        double *m3 = nullptr, *g = nullptr;
+        std::vector<TR *> Zr, Yr;
+        TR *Ysr = nullptr, *Y2r = nullptr, *Y3r = nullptr, *Y4r = nullptr, *ZL2s = nullptr;
+        TR *Sy[3] = {};
+        TR *Asp = nullptr, *Esp = nullptr, *Ysp = nullptr, *Rsp = nullptr;
+        int Lcap = 0;
+    } alt;
+    void swap_set() {
+        std::swap(Z, alt.Z); std::swap(Yk, alt.Yk); std::swap(Ak, alt.Ak);
+        std::swap(Ys, alt.Ys); std::swap(Y2, alt.Y2); std::swap(Y3, alt.Y3);
+        std::swap(E, alt.E); std::swap(Wk, alt.Wk); std::swap(ZL2, alt.ZL2);
+        std::swap(Y4f, alt.Y4f); std::swap(m3, alt.m3); std::swap(g, alt.g);
+        std::swap(Zr, alt.Zr); std::swap(Yr, alt.Yr);
+        std::swap(Ysr, alt.Ysr); std::swap(Y2r, alt.Y2r); std::swap(Y3r, alt.Y3r);
+        std::swap(Y4r, alt.Y4r); std::swap(ZL2s, alt.ZL2s);
+        for (int q = 0; q < 3; ++q) std::swap(Sy[q], alt.Sy[q]);
+        std::swap(Asp, alt.Asp); std::swap(Esp, alt.Esp); std::swap(Ysp, alt.Ysp);
+        std::swap(Rsp, alt.Rsp); std::swap(Lcap, alt.Lcap);
+    }
+    // the second expansion's results replace the first's where it ran
+    void adopt() {
+        const int *sk = psi + PI_SKIP2;
+        auto cp = [&](const void *src, void *dst, size_t bytes) {
+            if (!src || !dst || src == dst) return;
+            const long n8 = (long)(bytes / 8);
+            hipLaunchKernelGGL(pred_copy_kernel, dim3(ceil_div(n8, 256)), dim3(256), 0, st, sk,
+                               src, dst, n8);
+            XL_LAUNCH_CHECK();
+        };
+        const size_t mf = mat() * sizeof(TF), mr = mat() * sizeof(TR);
+        for (int k = 0; k <= L; ++k) cp(alt.Z[k], Z[k], mf);
+        for (int k = 0; k < L; ++k) {
+            cp(alt.Yk[k], Yk[k], mf);
+            cp(alt.Ak[k], Ak[k], mf);
+        }
+        cp(alt.Ys, Ys, mf); cp(alt.Y2, Y2, mf); cp(alt.Y3, Y3, mf); cp(alt.ZL2, ZL2, mf);
+        if (seed_sparse) cp(alt.Y4r, Y4r, mr);
+        if constexpr (FUSE_COPY) {
+            for (int k = 0; k <= L; ++k) cp(alt.Zr[k], Zr[k], mr);
+            for (int k = 0; k < L; ++k) cp(alt.Yr[k], Yr[k], mr);
+            cp(alt.Ysr, Ysr, mr); cp(alt.Y2r, Y2r, mr); cp(alt.Y3r, Y3r, mr);
+            for (int q = 0; q < 3; ++q) cp(alt.Sy[q], Sy[q], mr);
+            cp(alt.ZL2s, ZL2s, mr);
+        }
+        cp(alt.g, g, (size_t)N * sizeof(double));
+    }
+    // D at the final chemical potential: P = Z_L Z_L^2, then the
+    // second-order correction with dmu from the device
+    TF *Pd = nullptr;
+    void finish_density_planned() {
+        if (!Pd) Pd = amat<TF>();
+        bool done = false;
+        if constexpr (FUSE_COPY) {
+            if (resp_split) {
+                SplitArgs a = sbase();
+                a.A0 = s16(Zr[L]); a.B0 = s16(ZL2s); a.Cd = Pd;
+                run_split<TR>(a, true);
+                done = true;
+            }
+        }
+        if (!done) {
+            auto a = base<TF>();
+            a.A0 = Z[L]; a.B0 = ZL2; a.C = Pd;
+            run_gemm(a, true);
+        }
+        hipLaunchKernelGGL((density_combine_kernel<TF>), dim3(ceil_div((long)mat(), 256)),
+                           dim3(256), 0, st, N, Np, (const TF *)Z[L], (const TF *)ZL2,
+                           (const TF *)Pd, (const double *)psd, beta, Dc);
+        XL_LAUNCH_CHECK();
+        hipLaunchKernelGGL((charges_kernel<TF>), dim3(1), dim3(1024), 0, st, nat, no, Np, Dc, zc,
+                           ncur, q, r, scal + 16);
+        XL_LAUNCH_CHECK();
+    }
+    void solve_planned() override {
+        XL_HIP(hipMemcpyAsync(ncur, hist, nat * sizeof(double), hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(gamma_matvec_kernel, dim3(ceil_div((long)nat * 64, 256)), dim3(256),
+                           0, st, md, 1, ncur, vpot);
+        XL_LAUNCH_CHECK();
+        gershgorin();
+        hipLaunchKernelGGL(neighbours_kernel, dim3(nat), dim3(64), 0, st, md, nbl, nbc);
+        hipLaunchKernelGGL(max_count_kernel, dim3(1), dim3(1024), 0, st, nat, (const int *)nbc,
+                           scal + 10);
+        XL_LAUNCH_CHECK();
+        lanczos();
+        hipLaunchKernelGGL(plan_interval_kernel, dim3(1), dim3(64), 0, st, (const double *)(scal + 8),
+                           (const double *)lz_ab, LZ_M, nat, beta, plan.xmax, plan.sparse ? 1 : 0,
+                           NB_MAX, psd, psi);
+        XL_LAUNCH_CHECK();
+        ns_total = 0;
+        foe_core(plan.L, plan.xmax, 0.0, psd + PS_MU0, nullptr, plan.sparse, scal, g);
+        hipLaunchKernelGGL(plan_mu_kernel, dim3(1), dim3(64), 0, st, (const double *)scal, beta,
+                           d.n_electrons, mu_tol(), psd, psi);
+        XL_LAUNCH_CHECK();
+        const int ns_first = ns_total;
+        swap_set();
+        if (!g) g = this->template dev<double>(Np);
+        try {
+            foe_core(plan.L, plan.xmax, 0.0, psd + PS_MU1, psi + PI_SKIP2, plan.sparse,
+                     psd + PS_ST2, g);
+        } catch (...) {
+            swap_set();
+            throw;
+        }
+        swap_set();
+        ns_total = ns_first;
+        hipLaunchKernelGGL(plan_mu2_kernel, dim3(1), dim3(64), 0, st, (const double *)scal,
+                           (const double *)(psd + PS_ST2), beta, mu_tol(), psd, psi);
+        XL_LAUNCH_CHECK();
+        adopt();
+        finish_density_planned();
+        hipLaunchKernelGGL(plan_finish_kernel, dim3(1), dim3(64), 0, st,
+                           (const double *)(scal + 16), nat, psd, psi);
+        XL_LAUNCH_CHECK();
+    }
+    // the sequential Krylov kernel with its rank decided on the device
+    void kernel_planned() override {
+        const int m = d.kernel_rank <= 0 ? 0 : std::min(d.kernel_rank, mcap);
+        const double gam = d.k0_gamma;
+        if (m > 0) {
+            hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(1024), 0, st, nat, 0, V, r, -gam, V,
+                               psd + PS_NRM);
+            XL_LAUNCH_CHECK();
+            for (int j = 0; j < m; ++j) {
+                responses(1, V + (size_t)j * nat, qp, W + (size_t)j * nat);
+                if (j + 1 == m) break;
+                hipLaunchKernelGGL(orth_kernel, dim3(1), dim3(1024), 0, st, nat, j + 1, V,
+                                   W + (size_t)j * nat, 1.0, V + (size_t)(j + 1) * nat,
+                                   psd + PS_NRM + 2 * (j + 1));
+                XL_LAUNCH_CHECK();
+            }
+        }
+        hipLaunchKernelGGL(plan_rank_kernel, dim3(1), dim3(64), 0, st,
+                           (const double *)(psd + PS_NRM), m, gam, nat, 1e-8, psi);
+        XL_LAUNCH_CHECK();
+        hipLaunchKernelGGL(kernel_apply_kernel, dim3(1), dim3(1024), 0, st, nat, m, V, W, r, gam,
+                           kr, scal + 32, (const int *)(psi + PI_RANK));
         XL_LAUNCH_CHECK();
     }
 
@@ -1567,6 +1961,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
         attach_ws(w);
         a.ws = w.ws;
         a.ws_elems = w.ws_elems;
+        if (cur_skip) a.skip = cur_skip;
         prof_begin();
         gemm_split(a, sym, st);
         prof_end(gemm_flops(sym, a.A1 ? 2 : 1) * a.batch, 2);
@@ -1585,7 +1980,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
                            st, nat, no, nb, sc, hb, (long)Np, ub);
         XL_LAUNCH_CHECK();
         const long s2 = 2 * sm;            // batch stride of split buffers
-        if (sparse_seed() && Np == N) {
+        if (seed_sparse && Np == N) {
             // G = (Y D) Y and P = (Y D) Y^3 as sparse-dense products (the
             // column scale applied to the rows of B), H13 = Y D Y^3 + Y^3 D Y
             // = P + P^T, and H2 = Y2 D Y2 on pre-split operands
@@ -2005,7 +2400,12 @@ int xlbomd_step(xlbomd_system *h, int32_t n_steps, xlbomd_report *last) {
             const bool want = ev > 0 && ((s.step_no + 1) % ev == 0);
             const bool timed = is_last && last;
             if (timed) s.step_timer(true);
-            s.md_step(want, is_last ? last : nullptr);
+            if (s.step_mode != 0) {
+                s.planned_launch();
+                s.planned_complete(want, is_last ? last : nullptr);
+            } else {
+                s.md_step(want, is_last ? last : nullptr);
+            }
             if (timed) {
                 s.step_timer(false);
                 last->ms_step = s.step_ms();
@@ -2025,6 +2425,34 @@ int xlbomd_step_batch(xlbomd_system *const *hs, int32_t count, int32_t n_steps,
             if (hs[i] == hs[j]) return fail(XLBOMD_E_INVALID, "handle repeated in batch");
     std::vector<int> rc(count, XLBOMD_OK);
     std::vector<std::string> msg(count);
+    bool all_planned = count > 0;
+    for (int i = 0; i < count; ++i) all_planned = all_planned && hs[i]->s->step_mode != 0;
+    if (all_planned) {
+        // planned steps from one host thread: every system's step (a graph
+        // replay in step mode 2) is enqueued on its own stream before any is
+        // waited for, so the device runs them concurrently
+        auto one = [&](int i, auto &&f) {
+            if (rc[i] != XLBOMD_OK) return;
+            rc[i] = guarded(f);
+            if (rc[i] != XLBOMD_OK) msg[i] = xlbomd_last_error();
+        };
+        for (int t = 0; t < n_steps; ++t) {
+            std::vector<char> want(count, 0);
+            for (int i = 0; i < count; ++i)
+                one(i, [&] {
+                    SysBase &s = *hs[i]->s;
+                    const int ev = s.d.energy_every;
+                    want[i] = ev > 0 && ((s.step_no + 1) % ev == 0);
+                    s.planned_launch();
+                });
+            for (int i = 0; i < count; ++i)
+                one(i, [&] {
+                    SysBase &s = *hs[i]->s;
+                    s.planned_complete(want[i] != 0,
+                                       (t + 1 == n_steps && reports) ? &reports[i] : nullptr);
+                });
+        }
+    } else {
     auto run = [&](int i) {
         rc[i] = xlbomd_step(hs[i], n_steps, reports ? &reports[i] : nullptr);
         if (rc[i] != XLBOMD_OK) msg[i] = xlbomd_last_error();
@@ -2037,6 +2465,7 @@ int xlbomd_step_batch(xlbomd_system *const *hs, int32_t count, int32_t n_steps,
         for (int i = 0; i < count; ++i) th.emplace_back(run, i);
         for (auto &x : th) x.join();
     }
+    }
     int first = XLBOMD_OK;
     for (int i = 0; i < count; ++i) {
         if (status) status[i] = rc[i];
@@ -2046,6 +2475,29 @@ int xlbomd_step_batch(xlbomd_system *const *hs, int32_t count, int32_t n_steps,
         }
     }
     return first;
+}
+
+int xlbomd_set_step_mode(xlbomd_system *h, int32_t mode) {
+    if (!h || !h->s) return fail(XLBOMD_E_INVALID, "null handle");
+    return guarded([&] {
+        SysBase &s = *h->s;
+        if (mode < 0 || mode > 2) throw InvalidArg("step mode must be 0, 1 or 2");
+        if (mode != 0 && !s.planned_capable())
+            throw InvalidArg("planned steps need krylov_mode 0, kernel_every 1 and kernel_otf 0");
+        if (mode != s.step_mode) s.drop_graph();
+        s.step_mode = mode;
+    });
+}
+
+int xlbomd_step_stats(xlbomd_system *h, int64_t *out) {
+    if (!h || !h->s || !out) return fail(XLBOMD_E_INVALID, "null argument");
+    return guarded([&] {
+        SysBase &s = *h->s;
+        out[0] = s.n_planned;
+        out[1] = s.n_replays;
+        out[2] = s.n_captures;
+        out[3] = s.n_fallbacks;
+    });
 }
 
 int xlbomd_kernel_update(xlbomd_system *h, int32_t rank) {
@@ -2112,6 +2564,7 @@ int xlbomd_set_state(xlbomd_system *h, const double *pos, const double *vel,
             s.head = 0;
         }
         s.sync();
+        s.leave_planned();
         s.mu_known = 0;
         s.solve(s.hist_row(0), 0.0, false);
         s.el_stale = false;
@@ -2402,6 +2855,8 @@ void xlbomd_destroy(xlbomd_system *h) {
     if (h->s) {
         (void)hipStreamSynchronize(h->s->st);
         if (h->s->hscal) (void)hipHostFree(h->s->hscal);
+        if (h->s->hps) (void)hipHostFree(h->s->hps);
+        h->s->drop_graph();
         for (hipEvent_t e : h->s->prof.ev) (void)hipEventDestroy(e);
         for (hipEvent_t e : h->s->step_ev)
             if (e) (void)hipEventDestroy(e);
