@@ -228,7 +228,8 @@ int xlbomd_step_batch(xlbomd_system *const *hs, int32_t count, int32_t n_steps,
  *     threshold, and the Krylov directions stop at a breakdown; each of
  *     these reads device values back to the host.
  *   1: planned steps.  A plan (level count and schedule for the last
- *     interval widened by 25%) is made on the host; every decision of a
+ *     interval widened by a margin, xlbomd_set_plan_margin) is made on the
+ *     host; every decision of a
  *     step is then taken on the device: the interval and the predicted
  *     chemical potential are checked against the plan, one rerun of the
  *     expansion at the corrected chemical potential runs only when needed
@@ -245,6 +246,14 @@ int xlbomd_step_batch(xlbomd_system *const *hs, int32_t count, int32_t n_steps,
  * (XLBOMD_E_INVALID otherwise).  Steps that evaluate the energy do so after
  * the planned step, with host synchronisation. */
 int xlbomd_set_step_mode(xlbomd_system *h, int32_t mode);
+
+/* Headroom of a plan: the level count and schedule are sized for the last
+ * spectral interval widened by (1 + margin) around the predicted chemical
+ * potential (0.25 by default; more headroom means more levels and fewer
+ * new plans).  In [-0.9, 10]; a negative margin makes every planned step
+ * leave its plan, so each is taken again with host decisions (a check of
+ * that path).  The next planned step makes a new plan. */
+int xlbomd_set_plan_margin(xlbomd_system *h, double margin);
 
 /* Counters of planned steps since init: out[0] planned steps taken, out[1]
  * of them replayed from a graph, out[2] graphs captured, out[3] planned

@@ -130,6 +130,7 @@ def lib():
         L.xlbomd_kernel_update.argtypes = [vp, ctypes.c_int32]
         L.xlbomd_set_step_mode.argtypes = [vp, ctypes.c_int32]
         L.xlbomd_step_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.xlbomd_set_plan_margin.argtypes = [vp, ctypes.c_double]
         L.xlbomd_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32,
                                         ctypes.c_int32, ctypes.POINTER(Report),
                                         ctypes.POINTER(ctypes.c_int32)]
@@ -159,7 +160,8 @@ def lib():
 
 
 EXPORTED = ("xlbomd_init_system", "xlbomd_step", "xlbomd_step_batch",
-            "xlbomd_set_step_mode", "xlbomd_step_stats", "xlbomd_kernel_update",
+            "xlbomd_set_step_mode", "xlbomd_set_plan_margin", "xlbomd_step_stats",
+            "xlbomd_kernel_update",
             "xlbomd_forces", "xlbomd_get_charges", "xlbomd_set_state",
             "xlbomd_get_state", "xlbomd_state_size", "xlbomd_save_state",
             "xlbomd_load_state", "xlbomd_solve", "xlbomd_response",
@@ -295,6 +297,11 @@ class XLBOMD:
         """0: host decisions; 1: planned steps (decisions on the device);
         2: planned steps replayed from a captured HIP graph."""
         _check(lib().xlbomd_set_step_mode(self._h, int(mode)))
+
+    def set_plan_margin(self, margin):
+        """Headroom of a plan's interval (0.25 by default; below 0 every
+        planned step leaves its plan)."""
+        _check(lib().xlbomd_set_plan_margin(self._h, float(margin)))
 
     def step_stats(self):
         out = (ctypes.c_int64 * 4)()

@@ -870,6 +870,7 @@ struct SysBase {
         bool sparse = false;  // sparse-dense seed products
     };
     int step_mode = 0;
+    double plan_margin = 0.25;     // headroom of a plan's interval
     Plan plan{};
     bool have_plan = false;
     bool planned_ready = false;    // ordered n history and device mu history in place
@@ -890,11 +891,11 @@ struct SysBase {
     }
     size_t snap_len() const { return (size_t)(13 + d.kmax + 2 * mcap) * nat; }
     // the plan: the interval of the last solve around the predicted mu,
-    // widened by 25%
+    // widened by plan_margin (25% unless set)
     void make_plan() {
         const double mp = mu_known > 0 ? predict_mu() : mu;
         const double x = beta * std::max(std::fabs(elo - mp), std::fabs(ehi - mp)) * 1.02 + 1e-12;
-        plan.xmax = 1.25 * x;
+        plan.xmax = (1.0 + plan_margin) * x;
         plan.L = levels_for(plan.xmax);
         plan.sparse = sparse_seed();
         have_plan = true;
@@ -2486,6 +2487,18 @@ int xlbomd_set_step_mode(xlbomd_system *h, int32_t mode) {
             throw InvalidArg("planned steps need krylov_mode 0, kernel_every 1 and kernel_otf 0");
         if (mode != s.step_mode) s.drop_graph();
         s.step_mode = mode;
+    });
+}
+
+int xlbomd_set_plan_margin(xlbomd_system *h, double margin) {
+    if (!h || !h->s) return fail(XLBOMD_E_INVALID, "null handle");
+    if (!(margin >= -0.9 && margin <= 10.0))
+        return fail(XLBOMD_E_INVALID, "plan margin must be in [-0.9, 10]");
+    return guarded([&] {
+        SysBase &s = *h->s;
+        s.plan_margin = margin;
+        s.have_plan = false;
+        s.drop_graph();
     });
 }
 

@@ -108,25 +108,34 @@ def test_energy_steps_between_planned_steps(P):
     assert stats["fallbacks"] == 0 and stats["replays"] >= 8
 
 
-def test_step_that_leaves_its_plan_is_taken_with_host_decisions(P):
-    """A chemical-potential threshold of 1e-12, below what one rerun of the
-    expansion reaches from the predicted chemical potential (the model
-    step's error is cubic in the first correction), makes planned steps
-    leave their plan; those steps are restored and taken again with host
-    decisions, and the run follows the one with host decisions throughout."""
-    s = make_system("c1")
+@pytest.mark.parametrize("prec", ["FP64", "MIXED_BF16X3"])
+def test_step_that_leaves_its_plan_is_taken_with_host_decisions(P, prec):
+    """A plan sized for half of the last interval (margin -0.5) makes every
+    planned step leave it (the interval check on the device); each step is
+    restored from the state saved at its start and taken again with host
+    decisions, so the run equals the one with host decisions throughout,
+    bit for bit, and then the default margin plans again."""
+    s = lattice_system(40, "c2", seed=11)
     out = []
     for mode in (0, 2):
-        g = P.XLBOMD(s, precision=P.FP64, scf_tol=1e-11, mu_tol=1e-12)
+        g = P.XLBOMD(s, precision=getattr(P, prec), scf_tol=1e-10)
         g.set_step_mode(mode)
-        g.step(10, report=False)
+        if mode:
+            g.set_plan_margin(-0.5)
+        g.step(6, report=False)
         out.append(_snap(g))
         stats = g.step_stats()
+        if mode:
+            g.set_plan_margin(0.25)
+            g.step(4, report=False)
+            after = g.step_stats()
         g.close()
     d = {k: float(np.abs(out[0][k] - out[1][k]).max()) for k in out[0]}
-    print("forced departures from the plan:", stats, {k: f"{v:.1e}" for k, v in d.items()})
-    assert stats["fallbacks"] >= 1
-    assert d["hist"] < 1e-9 and d["q"] < 1e-8 and d["F"] < 1e-6
+    print(f"{prec} forced departures from the plan:", stats, "then", after,
+          {k: f"{v:.1e}" for k, v in d.items()})
+    assert stats["fallbacks"] == 6 and stats["planned"] == 6
+    assert max(d.values()) == 0.0
+    assert after["fallbacks"] == 6 and after["replays"] >= 2
 
 
 def test_batch_of_graphs_alone_equals_in_the_mix(P):
