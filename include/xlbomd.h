@@ -387,6 +387,24 @@ int xlbomd_selftest_gemm_time(int32_t n, int32_t precision, int32_t sym, int32_t
 int xlbomd_selftest_gemm_presplit(int32_t n, int32_t sym, int32_t reps, const double *A,
                                   const double *B, double *C, double *ms_per_launch);
 
+/* The split product of xlbomd_selftest_gemm_presplit on device operands,
+ * allocating nothing: for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  A, B and C are device pointers to n x n row-major matrices
+ * stored as two bf16 planes, hi then lo n*n elements later (the value is
+ * hi + lo); C = A B^T, i.e. C[i][j] = sum_k A[i][k] B[j][k] (sym != 0: the
+ * upper block triangle is computed and mirrored, valid when A B^T is
+ * symmetric); C must not overlap A or B.  n is a positive multiple of 128
+ * up to 46336 whose split-k partial tiles fit the library's fixed scratch
+ * array of 32 MiB per device: every such n except some between 2176 and
+ * 3712, which return XLBOMD_E_INVALID naming the bytes needed.  The call is
+ * enqueued on `stream` (a hipStream_t; NULL = the null stream) and returns
+ * without waiting.  Every call on a device shares that device's scratch
+ * array, which keeps the last call's partial tiles: calls that overlap on
+ * one device (other streams, other threads) race. */
+int xlbomd_gemm_presplit_noalloc(int32_t n, int32_t sym, const void *A, const void *B,
+                                 void *C, void *stream);
+
 void xlbomd_destroy(xlbomd_system *h);
 
 /* Message of the last failed call on this thread ("" if none). */

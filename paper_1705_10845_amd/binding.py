@@ -151,6 +151,8 @@ def lib():
                                            ctypes.c_int32, _dp, _dp, _dp]
         L.xlbomd_selftest_gemm_time.argtypes = [ctypes.c_int32] * 5 + [_dp]
         L.xlbomd_selftest_gemm_presplit.argtypes = [ctypes.c_int32] * 3 + [_dp, _dp, _dp, _dp]
+        L.xlbomd_gemm_presplit_noalloc.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp,
+                                                   vp, vp]
         L.xlbomd_destroy.argtypes = [vp]
         L.xlbomd_destroy.restype = None
         L.xlbomd_last_error.restype = ctypes.c_char_p
@@ -167,6 +169,7 @@ EXPORTED = ("xlbomd_init_system", "xlbomd_step", "xlbomd_step_batch",
             "xlbomd_load_state", "xlbomd_solve", "xlbomd_response",
             "xlbomd_kernel_apply", "xlbomd_scf", "xlbomd_profile", "xlbomd_selftest_gemm",
             "xlbomd_selftest_gemm_time", "xlbomd_selftest_gemm_presplit",
+            "xlbomd_gemm_presplit_noalloc",
             "xlbomd_destroy", "xlbomd_last_error",
             "xlbomd_version")
 
@@ -219,6 +222,13 @@ def selftest_gemm_presplit(A, B, sym=False, reps=0):
     _check(lib().xlbomd_selftest_gemm_presplit(n, 1 if sym else 0, reps, _ptr(A), _ptr(B),
                                                _ptr(C), _ptr(ms)))
     return (C, float(ms[0])) if reps > 0 else C
+
+
+def gemm_presplit_noalloc(n, sym, A_ptr, B_ptr, C_ptr, stream=None):
+    """C = A B^T on pre-split device operands (device addresses of two bf16
+    planes each), enqueued on `stream` without allocating."""
+    _check(lib().xlbomd_gemm_presplit_noalloc(int(n), 1 if sym else 0, A_ptr, B_ptr, C_ptr,
+                                              stream))
 
 
 def step_batch(systems, n_steps=1):

@@ -2292,6 +2292,37 @@ template <typename TF, typename TR> struct Sys : SysBase {
 };
 
 // ---------------------------------------------------------------------------
+// Fixed scratch of the allocation-free split product: its split-k partial
+// tiles (FP32).  32 MiB per device, held until the process ends; every
+// multiple of 128 up to 46336 fits except some between 2176 and 3712.
+// ---------------------------------------------------------------------------
+constexpr long kScratchFloats = 8L << 20;
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch` per device
+
+// The device address of `scratch` on the current device, looked up once per
+// device with that device current (in host code the array's name is not a
+// device address)
+float *scratch_on_device() {
+    int dev = 0;
+    XL_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw InvalidArg("device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        XL_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw HipError("hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = static_cast<float *>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 struct xlbomd_system {
@@ -2860,6 +2891,29 @@ int xlbomd_selftest_gemm_presplit(int32_t n, int32_t sym, int32_t reps, const do
             (void)hipEventDestroy(e1);
             *ms_per_launch = ms / reps;
         }
+    });
+}
+
+int xlbomd_gemm_presplit_noalloc(int32_t n, int32_t sym, const void *A, const void *B,
+                                 void *C, void *stream) {
+    if (n <= 0 || n % 128 || n > 46336 || !A || !B || !C)
+        return fail(XLBOMD_E_INVALID, "n must be a positive multiple of 128 up to 46336 and "
+                                      "A, B, C device pointers");
+    return guarded([&] {
+        const long need = split_bs_ws_elems(n, sym != 0, 0, 1);
+        if (need > kScratchFloats)
+            throw InvalidArg("n = " + std::to_string(n) + (sym ? " (symmetric)" : "") +
+                             ": the split-k partial tiles need " + std::to_string(4 * need) +
+                             " bytes, above the " + std::to_string(4 * kScratchFloats) +
+                             "-byte scratch array");
+        SplitArgs ga;
+        ga.n = n; ga.ld = n; ga.pl = (long)n * n;
+        ga.A0 = static_cast<const uint16_t *>(A);
+        ga.B0 = static_cast<const uint16_t *>(B);
+        ga.C = static_cast<uint16_t *>(C);
+        ga.ws = scratch_on_device();
+        ga.ws_elems = kScratchFloats;
+        gemm_split(ga, sym != 0, static_cast<hipStream_t>(stream));
     });
 }
 
