@@ -166,14 +166,17 @@ __global__ void plan_mu2_kernel(const double *st1, const double *st2, double bet
     ps[PS_MU] = mu_e + dmu;
 }
 
-// Copy of n8 8-byte words from src to dst unless *skip is set.
-__global__ __launch_bounds__(256) void pred_copy_kernel(const int *skip, const void *src,
-                                                        void *dst, long n8) {
+// The copies of a table of (source, destination, 8-byte words) triples,
+// one per blockIdx.y, unless *skip is set; grid.x blocks stride the words.
+__global__ __launch_bounds__(256) void pred_copy_table_kernel(const int *skip, const long *tab) {
     if (*skip) return;
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n8)
-        reinterpret_cast<unsigned long long *>(dst)[i] =
-            reinterpret_cast<const unsigned long long *>(src)[i];
+    const long *e = tab + 3 * (long)blockIdx.y;
+    const unsigned long long *src = reinterpret_cast<const unsigned long long *>(e[0]);
+    unsigned long long *dst = reinterpret_cast<unsigned long long *>(e[1]);
+    const long n8 = e[2];
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n8;
+         i += (long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
 // D(mu_e + d) = (1 + bd/2) I + (-2 + bd^2/2) Z + (-2 bd) Z^2 + (-2 bd^2) Z Z^2,

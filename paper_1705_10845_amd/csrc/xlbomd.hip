@@ -880,6 +880,9 @@ struct SysBase {
     hipGraphExec_t gexec = nullptr;
     long graph_epoch = -1, warm_epoch = -1;
     long n_planned = 0, n_replays = 0, n_captures = 0, n_fallbacks = 0;
+    // a planned step begun by xlbomd_step_begin and not yet ended
+    bool in_flight = false, in_flight_energy = false;
+    hipEvent_t done_ev = nullptr;
 
     bool planned_capable() const {
         return d.krylov_mode == 0 && d.kernel_every == 1 && d.kernel_otf == 0;
@@ -900,6 +903,7 @@ struct SysBase {
         plan.sparse = sparse_seed();
         have_plan = true;
         drop_graph();
+        warm_epoch = -1;          // the new plan's first step runs directly (it may allocate)
     }
     // n history in order (row k = n(t - k dt)), mu history on the device
     void prepare_planned() {
@@ -1796,15 +1800,21 @@ template <typename TF, typename TR> struct Sys : SysBase {
         std::swap(Asp, alt.Asp); std::swap(Esp, alt.Esp); std::swap(Ysp, alt.Ysp);
         std::swap(Rsp, alt.Rsp); std::swap(Lcap, alt.Lcap);
     }
-    // the second expansion's results replace the first's where it ran
+    // the second expansion's results replace the first's where it ran: one
+    // launch over a table of (source, destination, words), copied to the
+    // device by the step itself from pinned host memory (the buffers' roles
+    // alternate between steps with the Newton-Schulz ping-pong, so each
+    // enqueue, and each captured graph, carries its own table; a direct step
+    // synchronises before the next rewrites it)
+    long *cp_tab = nullptr, *cp_host = nullptr;
+    int cp_cap = 0;
     void adopt() {
-        const int *sk = psi + PI_SKIP2;
+        std::vector<long> t;
         auto cp = [&](const void *src, void *dst, size_t bytes) {
             if (!src || !dst || src == dst) return;
-            const long n8 = (long)(bytes / 8);
-            hipLaunchKernelGGL(pred_copy_kernel, dim3(ceil_div(n8, 256)), dim3(256), 0, st, sk,
-                               src, dst, n8);
-            XL_LAUNCH_CHECK();
+            t.push_back(reinterpret_cast<long>(src));
+            t.push_back(reinterpret_cast<long>(dst));
+            t.push_back((long)(bytes / 8));
         };
         const size_t mf = mat() * sizeof(TF), mr = mat() * sizeof(TR);
         for (int k = 0; k <= L; ++k) cp(alt.Z[k], Z[k], mf);
@@ -1822,6 +1832,31 @@ template <typename TF, typename TR> struct Sys : SysBase {
             cp(alt.ZL2s, ZL2s, mr);
         }
         cp(alt.g, g, (size_t)N * sizeof(double));
+        const int n = (int)(t.size() / 3);
+        if (n > cp_cap) {
+            if (capturing) throw StateError("copy table grew during graph capture");
+            this->release(cp_tab);
+            cp_tab = nullptr;
+            if (cp_host) {
+                sync();
+                XL_HIP(hipHostFree(cp_host));
+                cp_host = nullptr;
+            }
+            cp_cap = 0;
+            cp_tab = this->template dev<long>(3 * (size_t)n);
+            void *hp = nullptr;
+            XL_HIP(hipHostMalloc(&hp, 3 * (size_t)n * sizeof(long), hipHostMallocDefault));
+            cp_host = (long *)hp;
+            cp_cap = n;
+        }
+        std::memcpy(cp_host, t.data(), t.size() * sizeof(long));
+        XL_HIP(hipMemcpyAsync(cp_tab, cp_host, t.size() * sizeof(long), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(pred_copy_table_kernel, dim3(256, n), dim3(256), 0, st,
+                           (const int *)(psi + PI_SKIP2), (const long *)cp_tab);
+        XL_LAUNCH_CHECK();
+    }
+    ~Sys() override {
+        if (cp_host) (void)hipHostFree(cp_host);
     }
     // D at the final chemical potential: P = Z_L Z_L^2, then the
     // second-order correction with dmu from the device
@@ -2426,6 +2461,7 @@ int xlbomd_step(xlbomd_system *h, int32_t n_steps, xlbomd_report *last) {
     if (n_steps < 0) return fail(XLBOMD_E_INVALID, "n_steps < 0");
     return guarded([&] {
         SysBase &s = *h->s;
+        if (s.in_flight) throw StateError("a step begun on this handle has not ended");
         for (int i = 0; i < n_steps; ++i) {
             const int ev = s.d.energy_every;
             const bool is_last = (i + 1 == n_steps);
@@ -2452,6 +2488,8 @@ int xlbomd_step_batch(xlbomd_system *const *hs, int32_t count, int32_t n_steps,
     if (!hs || count < 0 || n_steps < 0) return fail(XLBOMD_E_INVALID, "bad batch arguments");
     for (int i = 0; i < count; ++i)
         if (!hs[i] || !hs[i]->s) return fail(XLBOMD_E_INVALID, "null handle in batch");
+    for (int i = 0; i < count; ++i)
+        if (hs[i]->s->in_flight) return fail(XLBOMD_E_STATE, "a step begun on a handle has not ended");
     for (int i = 0; i < count; ++i)
         for (int j = i + 1; j < count; ++j)
             if (hs[i] == hs[j]) return fail(XLBOMD_E_INVALID, "handle repeated in batch");
@@ -2518,6 +2556,38 @@ int xlbomd_set_step_mode(xlbomd_system *h, int32_t mode) {
             throw InvalidArg("planned steps need krylov_mode 0, kernel_every 1 and kernel_otf 0");
         if (mode != s.step_mode) s.drop_graph();
         s.step_mode = mode;
+    });
+}
+
+int xlbomd_step_begin(xlbomd_system *h) {
+    if (!h || !h->s) return fail(XLBOMD_E_INVALID, "null handle");
+    return guarded([&] {
+        SysBase &s = *h->s;
+        if (s.step_mode == 0) throw StateError("xlbomd_step_begin takes planned steps (step mode 1 or 2)");
+        if (s.in_flight) throw StateError("a step begun on this handle has not ended");
+        if (!s.done_ev) XL_HIP(hipEventCreateWithFlags(&s.done_ev, hipEventDisableTiming));
+        const int ev = s.d.energy_every;
+        s.in_flight_energy = ev > 0 && ((s.step_no + 1) % ev == 0);
+        s.planned_launch();
+        XL_HIP(hipEventRecord(s.done_ev, s.st));
+        s.in_flight = true;
+    });
+}
+
+int xlbomd_step_end(xlbomd_system *h, int32_t wait, int32_t *done, xlbomd_report *rep) {
+    if (!h || !h->s || !done) return fail(XLBOMD_E_INVALID, "null argument");
+    *done = 0;
+    return guarded([&] {
+        SysBase &s = *h->s;
+        if (!s.in_flight) throw StateError("no step begun on this handle");
+        if (!wait) {
+            const hipError_t e = hipEventQuery(s.done_ev);
+            if (e == hipErrorNotReady) return;
+            if (e != hipSuccess) XL_HIP(e);
+        }
+        s.in_flight = false;
+        s.planned_complete(s.in_flight_energy, rep);
+        *done = 1;
     });
 }
 
@@ -2924,6 +2994,7 @@ void xlbomd_destroy(xlbomd_system *h) {
         if (h->s->hscal) (void)hipHostFree(h->s->hscal);
         if (h->s->hps) (void)hipHostFree(h->s->hps);
         h->s->drop_graph();
+        if (h->s->done_ev) (void)hipEventDestroy(h->s->done_ev);
         for (hipEvent_t e : h->s->prof.ev) (void)hipEventDestroy(e);
         for (hipEvent_t e : h->s->step_ev)
             if (e) (void)hipEventDestroy(e);
