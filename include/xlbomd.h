@@ -247,6 +247,20 @@ int xlbomd_step_batch(xlbomd_system *const *hs, int32_t count, int32_t n_steps,
  * the planned step, with host synchronisation. */
 int xlbomd_set_step_mode(xlbomd_system *h, int32_t mode);
 
+/* One planned step in two halves, for a caller that steps many systems
+ * from one thread and starts each system's next step as soon as its last
+ * one is done.  xlbomd_step_begin enqueues the step (step mode 1 or 2, else
+ * XLBOMD_E_STATE) and returns at once.  xlbomd_step_end finishes it: with
+ * wait == 0 it returns with *done = 0 while the device is still busy with
+ * the step, else (or once the step is done) it commits the step as
+ * xlbomd_step would (taking it again with host decisions if it left its
+ * plan, evaluating the energy on a step of the energy cadence), writes the
+ * report if rep != NULL and sets *done = 1.  Between the two calls no
+ * other call may use the handle; xlbomd_step and xlbomd_step_batch return
+ * XLBOMD_E_STATE on a handle with a step begun and not ended. */
+int xlbomd_step_begin(xlbomd_system *h);
+int xlbomd_step_end(xlbomd_system *h, int32_t wait, int32_t *done, xlbomd_report *rep);
+
 /* Headroom of a plan: the level count and schedule are sized for the last
  * spectral interval widened by (1 + margin) around the predicted chemical
  * potential (0.25 by default; more headroom means more levels and fewer

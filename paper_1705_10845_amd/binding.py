@@ -131,6 +131,9 @@ def lib():
         L.xlbomd_set_step_mode.argtypes = [vp, ctypes.c_int32]
         L.xlbomd_step_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         L.xlbomd_set_plan_margin.argtypes = [vp, ctypes.c_double]
+        L.xlbomd_step_begin.argtypes = [vp]
+        L.xlbomd_step_end.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(Report)]
         L.xlbomd_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32,
                                         ctypes.c_int32, ctypes.POINTER(Report),
                                         ctypes.POINTER(ctypes.c_int32)]
@@ -163,6 +166,7 @@ def lib():
 
 EXPORTED = ("xlbomd_init_system", "xlbomd_step", "xlbomd_step_batch",
             "xlbomd_set_step_mode", "xlbomd_set_plan_margin", "xlbomd_step_stats",
+            "xlbomd_step_begin", "xlbomd_step_end",
             "xlbomd_kernel_update",
             "xlbomd_forces", "xlbomd_get_charges", "xlbomd_set_state",
             "xlbomd_get_state", "xlbomd_state_size", "xlbomd_save_state",
@@ -307,6 +311,21 @@ class XLBOMD:
         """0: host decisions; 1: planned steps (decisions on the device);
         2: planned steps replayed from a captured HIP graph."""
         _check(lib().xlbomd_set_step_mode(self._h, int(mode)))
+
+    def step_begin(self):
+        """Enqueue one planned step and return at once."""
+        _check(lib().xlbomd_step_begin(self._h))
+
+    def step_end(self, wait=True, report=False):
+        """Finish the begun step: False while the device is still busy
+        (wait=False), else True (with the report dict when asked)."""
+        done = ctypes.c_int32(0)
+        rep = Report()
+        _check(lib().xlbomd_step_end(self._h, 1 if wait else 0, ctypes.byref(done),
+                                     ctypes.byref(rep) if report else None))
+        if not done.value:
+            return False
+        return rep.as_dict() if report else True
 
     def set_plan_margin(self, margin):
         """Headroom of a plan's interval (0.25 by default; below 0 every

@@ -1,23 +1,29 @@
 """Continuous-batching server for independent XL-BOMD systems on one GPU.
 
 Requests (a System and an arrival time) are admitted while their estimated
-HBM footprint fits the budget and a slot is free; each admitted system keeps
-its whole state resident on the device (its library handle) and is stepped
-by its own worker thread on its own HIP stream, so the kernels of all active
-systems overlap on the GPU.  Requests that arrive while others run are
-admitted as slots and memory free up.  Per-step latency (completion of step
-s minus completion of step s-1, or of the initial state for s = 1) and the
-queueing delay (arrival to admission) are recorded.
+HBM footprint fits the budget and a slot is free.  An admitted system is set
+up (ground state by the kernel SCF) by a worker thread, then joins the
+running set: its whole state stays resident on the device (its library
+handle) and it takes planned steps, every decision on the device, each
+replayed from the system's captured HIP graph on its own stream.  One host
+thread drives all running systems: it polls their steps and enqueues each
+system's next step as soon as its last one is done, so the device overlaps
+the steps of every running system and a small system is never held back by
+a large one.  Requests that arrive while others run are admitted as slots
+and memory free up.  Per-step latency (completion of step s minus
+completion of step s-1, or of the initial state for s = 1) and the queueing
+delay (arrival to admission) are recorded.
 
 Only scheduling lives here; every step runs in the HIP library.
 """
 from __future__ import annotations
 
 import sys
-import threading
 import time
+from collections import deque
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
-from typing import Dict, List, Optional, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -26,7 +32,7 @@ from .binding import MIXED, MIXED_BF16X3, FP32, FP64, XLBOMD
 _ESZ = {FP64: (8, 8), FP32: (4, 4), MIXED: (8, 4), MIXED_BF16X3: (8, 4)}
 
 
-def footprint_bytes(system, precision=MIXED, levels=10) -> int:
+def footprint_bytes(system, precision=MIXED, levels=10, planned=True) -> int:
     """Upper estimate of the device memory one system holds (no energy
     evaluation, which the server does not request).
 
@@ -34,10 +40,10 @@ def footprint_bytes(system, precision=MIXED, levels=10) -> int:
     powers Y, Y^2, Y^3 and four work matrices; responses: three matrices per
     direction (nine on the split path: four work matrices, the split rows
     of Y D, Y^2 D, Y^3 D and the FP64 Y D Y^3), plus the response-precision
-    copies of the
-    expansion operands (Z, Y, Y..Y^4) when the two precisions differ, and
-    on the split path the split Y, Y^2, Y^3, Z_L^2 and four level work
-    matrices.
+    copies of the expansion operands (Z, Y, Y..Y^4) when the two precisions
+    differ, and on the split path the split Y, Y^2, Y^3, Z_L^2 and four
+    level work matrices.  Planned steps hold a second set of the expansion
+    buffers (the rerun at the corrected chemical potential) and Z_L^3.
     """
     n = system.n_atoms * system.n_orb
     npad = -(-n // 128) * 128
@@ -46,8 +52,13 @@ def footprint_bytes(system, precision=MIXED, levels=10) -> int:
     mats_f = 3 * levels + 8
     if precision == MIXED_BF16X3:
         mats_r = 9 * m + 2 * levels + 13
+        set_r = 2 * levels + 9
     else:
         mats_r = 3 * m + ((2 * levels + 5) if ef != er else 0)
+        set_r = (2 * levels + 5) if ef != er else 0
+    if planned:
+        mats_f += 3 * levels + 8
+        mats_r += set_r
     vecs = 64 * system.n_atoms * 8 + 16 * npad * 8
     return npad * npad * (mats_f * ef + mats_r * er) + vecs
 
@@ -65,96 +76,163 @@ class RequestStats:
     error: Optional[str] = None
 
 
+@dataclass
+class _Running:
+    g: XLBOMD
+    st: RequestStats
+    need: int
+    done: int = 0
+    last: float = 0.0
+    fut: object = None     # step with host decisions in flight (step mode 0)
+
+
 class Server:
     def __init__(self, hbm_budget: int, max_slots: int = 8, precision=MIXED,
                  steps: int = 100, scf_tol: Optional[float] = None,
-                 verbose: bool = False):
+                 verbose: bool = False, step_mode: int = 2, init_workers: int = 4):
         self.verbose = verbose
-        self._done = 0
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.precision = precision
         self.steps = int(steps)
         self.scf_tol = scf_tol
-        self._lock = threading.Condition()
-        self._used = 0
-        self._active = 0
+        self.step_mode = int(step_mode)
+        self.init_workers = int(init_workers)
         self.peak_used = 0
         self.peak_active = 0
 
-    def _worker(self, system, st: RequestStats, need: int, t0: float):
-        try:
-            g = XLBOMD(system, precision=self.precision, scf_tol=self.scf_tol)
-            st.ready = time.perf_counter() - t0
-            last = st.ready
-            rep = None
-            for _ in range(self.steps):
-                rep = g.step(1, report=False)
-                now = time.perf_counter() - t0
-                st.step_latency.append(now - last)
-                last = now
-            n, q = g.charges()
-            st.final = dict(q=q, n=n)
-            g.close()
-        except Exception as e:          # reported, never hidden
-            st.error = repr(e)
-        finally:
-            st.finished = time.perf_counter() - t0
-            with self._lock:
-                self._used -= need
-                self._active -= 1
-                self._done += 1
-                done = self._done
-                self._lock.notify_all()
-            if self.verbose:
-                print(f"[serve] t={st.finished:7.2f}s done {done}: {st.name} "
-                      f"({'error ' + st.error if st.error else 'ok'})",
-                      file=sys.stderr, flush=True)
+    def _init(self, system):
+        g = XLBOMD(system, precision=self.precision, scf_tol=self.scf_tol)
+        if self.step_mode:
+            g.set_step_mode(self.step_mode)
+        return g
 
     def run(self, requests: Sequence[Tuple[float, object]], realtime=True):
         """Serve a stream of (arrival_s, System); returns (stats, summary)."""
         reqs = sorted(requests, key=lambda x: x[0])
-        t0 = time.perf_counter()
         stats: List[RequestStats] = []
-        threads = []
+        queue = deque()
         for arrival, system in reqs:
-            need = footprint_bytes(system, self.precision)
+            need = footprint_bytes(system, self.precision, planned=self.step_mode != 0)
             if need > self.budget:
                 raise ValueError(f"{system.name} needs {need} bytes > budget")
-            st = RequestStats(name=system.name,
-                              n_orb_total=system.n_atoms * system.n_orb,
+            st = RequestStats(name=system.name, n_orb_total=system.n_atoms * system.n_orb,
                               arrival=arrival)
             stats.append(st)
-            if realtime:
-                wait = arrival - (time.perf_counter() - t0)
-                if wait > 0:
-                    time.sleep(wait)
-            with self._lock:
-                while (self._used + need > self.budget
-                       or self._active >= self.max_slots):
-                    self._lock.wait()
-                self._used += need
-                self._active += 1
-                self.peak_used = max(self.peak_used, self._used)
-                self.peak_active = max(self.peak_active, self._active)
-            st.admitted = time.perf_counter() - t0
-            th = threading.Thread(target=self._worker,
-                                  args=(system, st, need, t0), daemon=True)
-            th.start()
-            threads.append(th)
-        for th in threads:
-            th.join()
-        wall = time.perf_counter() - t0
+            queue.append((arrival, system, st, need))
+        used = 0
+        starting = []                       # (future, st, need)
+        running: List[_Running] = []
+        pool = ThreadPoolExecutor(max_workers=self.init_workers)
+        # step mode 0 (host decisions, a host synchronisation per decision):
+        # each running system's step is taken by a worker thread
+        steppers = None if self.step_mode else ThreadPoolExecutor(max_workers=self.max_slots)
+
+        def begin(r):
+            if steppers is None:
+                r.g.step_begin()
+            else:
+                r.fut = steppers.submit(r.g.step, 1, False)
+
+        def end(r):
+            if steppers is None:
+                return bool(r.g.step_end(wait=False))
+            if not r.fut.done():
+                return False
+            r.fut.result()
+            return True
+
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0   # noqa: E731
+
+        def retire(st, need, g=None):
+            nonlocal used
+            if g is not None:
+                try:
+                    g.close()
+                except Exception as e:      # reported, never hidden
+                    st.error = st.error or repr(e)
+            used -= need
+            st.finished = now()
+            if self.verbose:
+                print(f"[serve] t={st.finished:7.2f}s done: {st.name} "
+                      f"({'error ' + st.error if st.error else 'ok'})", file=sys.stderr, flush=True)
+
+        try:
+            while queue or starting or running:
+                progressed = False
+                # admission: arrived, fits the budget, a slot is free
+                while queue:
+                    arrival, system, st, need = queue[0]
+                    if realtime and arrival > now():
+                        break
+                    if used + need > self.budget or \
+                            len(starting) + len(running) >= self.max_slots:
+                        break
+                    queue.popleft()
+                    used += need
+                    st.admitted = now()
+                    starting.append((pool.submit(self._init, system), st, need))
+                    self.peak_used = max(self.peak_used, used)
+                    self.peak_active = max(self.peak_active, len(starting) + len(running))
+                    progressed = True
+                # systems whose initial state is ready start stepping
+                for item in list(starting):
+                    fut, st, need = item
+                    if not fut.done():
+                        continue
+                    starting.remove(item)
+                    progressed = True
+                    try:
+                        g = fut.result()
+                    except Exception as e:
+                        st.error = repr(e)
+                        retire(st, need)
+                        continue
+                    st.ready = now()
+                    r = _Running(g=g, st=st, need=need, last=st.ready)
+                    try:
+                        begin(r)
+                        running.append(r)
+                    except Exception as e:
+                        st.error = repr(e)
+                        retire(st, need, g)
+                # poll running steps; start each system's next step at once
+                for r in list(running):
+                    try:
+                        if not end(r):
+                            continue
+                        t = now()
+                        r.st.step_latency.append(t - r.last)
+                        r.last = t
+                        r.done += 1
+                        progressed = True
+                        if r.done < self.steps:
+                            begin(r)
+                            continue
+                        n, q = r.g.charges()
+                        r.st.final = dict(q=q, n=n)
+                    except Exception as e:
+                        r.st.error = repr(e)
+                    running.remove(r)
+                    retire(r.st, r.need, r.g)
+                if not progressed:
+                    time.sleep(20e-6)
+        finally:
+            pool.shutdown(wait=True)
+            if steppers is not None:
+                steppers.shutdown(wait=True)
+        wall = now()
         lat = np.array([x for s in stats for x in s.step_latency])
-        queue = np.array([s.admitted - s.arrival for s in stats])
+        qd = np.array([s.admitted - s.arrival for s in stats])
         summary = dict(
             requests=len(stats), errors=sum(1 for s in stats if s.error),
             wall_s=wall, total_steps=int(lat.size),
             steps_per_s=lat.size / wall if wall > 0 else 0.0,
             p50_step_ms=float(np.percentile(lat, 50) * 1e3) if lat.size else None,
             p99_step_ms=float(np.percentile(lat, 99) * 1e3) if lat.size else None,
-            p50_queue_ms=float(np.percentile(queue, 50) * 1e3),
-            p99_queue_ms=float(np.percentile(queue, 99) * 1e3),
+            p50_queue_ms=float(np.percentile(qd, 50) * 1e3),
+            p99_queue_ms=float(np.percentile(qd, 99) * 1e3),
             peak_hbm_bytes=self.peak_used, hbm_budget=self.budget,
-            peak_active=self.peak_active)
+            peak_active=self.peak_active, step_mode=self.step_mode)
         return stats, summary
