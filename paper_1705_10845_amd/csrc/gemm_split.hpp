@@ -260,6 +260,10 @@ __global__ __launch_bounds__(BS_T) void gemm_bs_fixup_kernel(SplitArgs p, int nt
 // ---------------------------------------------------------------------------
 constexpr int BW_NTH = 512;
 constexpr int BW_M = 256;
+// smallest n for the 256 x 128 kernel: below it the few tiles of a product
+// leave its three-deep k pipeline latency-bound, and the 128 x 128 kernel
+// is faster (a 64-atom x 4-orbital step: 3.64 -> 2.87 ms; N = 512: -6%)
+constexpr int BW_MIN_N = 1024;
 constexpr int BW_TILE = BW_M * GT;     // elements of one tile
 
 inline int wide_tiles(int n, bool sym) {
@@ -507,7 +511,7 @@ __global__ __launch_bounds__(256) void gemm_bw_fixup_kernel(SplitArgs p, int nti
 
 inline long split_bs_ws_elems(int n, bool sym, int dual, long batch) {
     long e = split_ws_elems<float>(n, sym, dual, batch);
-    if (n % BW_M == 0) {
+    if (n % BW_M == 0 && n >= BW_MIN_N) {
         const int nt = wide_tiles(n, sym);
         const Sched s = schedule<float>(nt, (n / B3K) * (dual ? 2 : 1), batch, 1);
         e = std::max(e, (long)(nt - s.nfull) * s.nsplit * batch * BW_TILE);
@@ -519,7 +523,7 @@ inline void gemm_split(const SplitArgs &a, bool sym, hipStream_t st) {
     if (a.n % GT != 0 || a.ld % 8 != 0 || a.pl % 8 != 0)
         throw InvalidArg("gemm_split: n must be a multiple of 128");
     if (!a.C && !a.Cd) throw InvalidArg("gemm_split: no output");
-    if (a.n % BW_M == 0) {          // 256 x 128 tiles, one workgroup per CU
+    if (a.n % BW_M == 0 && a.n >= BW_MIN_N) {   // 256 x 128 tiles, one workgroup per CU
         const int ntiles = wide_tiles(a.n, sym);
         const int nkt = (a.n / B3K) * (a.A1 ? 2 : 1);
         Sched s = a.ws ? schedule<float>(ntiles, nkt, a.batch, 1) : Sched{ntiles, 1};
