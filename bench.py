@@ -59,12 +59,12 @@ ENERGY_EVERY = 10   # free-energy report cadence (every 10th step, in the timed 
 # region (product kernel + its split-k fix-up, averaged over the launches),
 # from `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` runs of this
 # script scaled by the same counters' readings for a 1 GiB device copy
-# (profiles/gemm_counters_n4096.md).  Valid only for the product-kernel
+# (profiles/gemm_hbm_traffic_n4096.md).  Valid only for the product-kernel
 # source they were measured with.
 GEMM_SRC = [os.path.join(ROOT, "paper_1705_10845_amd", "csrc", f)
             for f in ("gemm.hpp", "gemm_split.hpp")]
-TRAFFIC = {"sha256": "cfafb942c624886d056af671e4e013622f230383200c3b3df500610d535fe626",
-           "f64": 3.168e9, "bf3": 7.39e8}
+TRAFFIC = {"sha256": "668cfd643622746ab6b32dfd77afb4748ba854a3144c7efb8d8f6601c3efdb61",
+           "f64": 3.338e9, "bf3": 7.413e8}
 
 
 def gemm_src_hash():
@@ -151,16 +151,19 @@ def cpu_baseline():
             "exponent": p, "extrapolated_s_per_step_N4096": t4096}
 
 
-def serving(n_requests=64, slots=16, budget_gib=96):
+def serving(n_requests=64, slots=16, budget_gib=96, step_mode=2):
     """The serving workload: Poisson stream (200/s) of independent systems,
     16-512 atoms x 4 orbitals, Te U[0.02, 0.1], rank 2-6, 100 steps each,
-    admitted by HBM footprint; the headline (MIXED_BF16X3) path."""
+    admitted by HBM footprint; the headline (MIXED_BF16X3) precision.
+    step_mode 2: planned steps replayed from each system's graph, all
+    systems driven from one host thread; 0: host decisions, one worker
+    thread per running system."""
     from synth import serving_stream
     from paper_1705_10845_amd.serve import Server
     from paper_1705_10845_amd import MIXED_BF16X3
     stream = serving_stream(n_requests)
     srv = Server(hbm_budget=budget_gib << 30, max_slots=slots, precision=MIXED_BF16X3,
-                 steps=100, verbose=True)
+                 steps=100, verbose=False, step_mode=step_mode)
     stats, summ = srv.run(stream)
     if summ["errors"]:
         print("[bench] serving errors:", [s.error for s in stats if s.error][:3], file=sys.stderr)
@@ -169,7 +172,32 @@ def serving(n_requests=64, slots=16, budget_gib=96):
                         "orbitals (log-uniform), "
                         "Poisson 200/s, Te U[0.02,0.1], rank U{2..6}, 100 steps each, "
                         "MIXED_BF16X3")
+    print(f"[bench] serving (step mode {step_mode}): {summ['total_steps']} steps in "
+          f"{summ['wall_s']:.1f}s, p50 {summ['p50_step_ms']:.2f} ms, p99 "
+          f"{summ['p99_step_ms']:.2f} ms", file=sys.stderr, flush=True)
     return summ
+
+
+def time_graph(system, precision, steps, warmup):
+    """Steps/s of the same workload with planned steps replayed from a HIP
+    graph (no per-product timing in this mode)."""
+    from paper_1705_10845_amd import XLBOMD
+    g = XLBOMD(system, precision=precision, stream=_stream(), scf_tol=1e-9,
+               energy_every=ENERGY_EVERY)
+    g.set_step_mode(2)
+    if warmup:
+        g.step(max(warmup, 2), report=False)
+    _sync()
+    t0 = time.perf_counter()
+    rep = g.step(steps, report=True)
+    _sync()
+    dt = time.perf_counter() - t0
+    st = g.step_stats()
+    g.close()
+    print(f"[bench] mixed, planned graph steps: {steps} steps in {dt:.3f}s, {st}",
+          file=sys.stderr, flush=True)
+    return {"value": steps / dt, "ms_per_step": 1e3 * dt / steps, "steps": steps,
+            "foe_levels": rep["foe_levels"], "stats": st}
 
 
 def main():
@@ -186,6 +214,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving leg (p50/p99 step latency)")
     ap.add_argument("--serving-requests", type=int, default=64)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the planned-graph leg of the headline workload")
     ap.add_argument("--serving-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -277,8 +307,11 @@ def main():
         out["mixed_over_fp64_own_targets"] = mixed["steps_per_s"] / fp64t["steps_per_s"]
     if fp32 is not None:
         out["fp32"] = summary(fp32, args.steps)
+    if not args.no_graph:
+        out["mixed_planned_graph"] = time_graph(s, MIXED_BF16X3, args.steps, args.warmup)
     if not args.no_serving:
-        out["serving"] = serving(args.serving_requests)
+        out["serving"] = serving(args.serving_requests, step_mode=2)
+        out["serving_host_decisions"] = serving(args.serving_requests, step_mode=0)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
