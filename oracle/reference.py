@@ -26,6 +26,14 @@ principles molecular dynamics"):
                       rows of Table I.
   initial state       Eq. 20 with the ground state from the kernel SCF of
                       Eq. 52.
+  non-orthogonal      Section VI (the SCC-DFTB model: non-orthogonal atomic
+  basis               orbitals, Mulliken charges, Pulay forces), on the
+                      synthetic model: overlap S, H[n] = H0 + (S V + V S)/2
+                      with V the orbital potentials, the generalised
+                      eigenproblem through the Loewdin factor X = S^-1/2
+                      (H' = X H X), D = X D' X, q_I = sum_a (D S)[Ia,Ia] -
+                      Z_I, and the energy-weighted density matrix in the
+                      forces.
 """
 from __future__ import annotations
 
@@ -71,6 +79,7 @@ def lib():
         L.orc_fermi.restype = _c.c_double
         L.orc_fermi_divdiff.argtypes = [_c.c_double, _c.c_double, _c.c_double]
         L.orc_fermi_divdiff.restype = _c.c_double
+        L.orc_fermi_divdiff_matrix.argtypes = [_c.c_int, _dp, _c.c_double, _dp]
         L.orc_density.argtypes = [_c.c_int, _dp, _dp, _dp]
         L.orc_response_diag.argtypes = [_c.c_int, _dp, _dp, _c.c_double,
                                         _c.c_double, _dp, _dp]
@@ -137,6 +146,33 @@ class Model:
         """diag of the charge-dependent Hamiltonian part, per orbital."""
         return np.repeat(G @ n, self.no)
 
+    @property
+    def nonorth(self):
+        b = getattr(self.s, "overlap_block", None)
+        return b is not None and bool(np.any(np.asarray(b) != 0.0))
+
+    def overlap(self, pos):
+        """Overlap matrix S: the identity on each atom's own block and
+        S[Ia,Jb] = Bs_ab exp(-r/decay_s) s(r) between atoms (the hopping's
+        form with unit onsite entries, its own block and decay, the same
+        cutoff and ramp)."""
+        s = self.s
+        S = np.zeros((self.N, self.N))
+        rc = lib().orc_h0(self.nat, self.no, _f64(pos), np.ones(self.no),
+                          np.zeros(self.N), _f64(s.overlap_block),
+                          s.overlap_decay, s.hop_cutoff, s.taper_width, S)
+        assert rc == 0
+        return S
+
+    def loewdin(self, pos):
+        """(S, X = S^-1/2) from the eigen-decomposition of S (Jacobi)."""
+        S = self.overlap(pos)
+        ev, Vt = jacobi(S)
+        if ev.min() <= 0.0:
+            raise ValueError("overlap matrix is not positive definite")
+        X = Vt.T @ np.diag(1.0 / np.sqrt(ev)) @ Vt
+        return S, X
+
 
 # ---------------------------------------------------------------------------
 # Electronic solve (Section IV.A-B)
@@ -153,10 +189,17 @@ class Electronic:
     D: np.ndarray
     q: np.ndarray
     n: np.ndarray
+    S: Optional[np.ndarray] = None   # overlap (non-orthogonal basis)
+    X: Optional[np.ndarray] = None   # S^-1/2; eigenvectors of X H X in Vt
 
     @property
     def r(self):
         return self.q - self.n
+
+    def eigvecs(self):
+        """Generalised eigenvectors C (columns): H C = S C diag(evals),
+        C^T S C = I (orthonormal eigenvectors in the orthogonal basis)."""
+        return self.Vt.T if self.X is None else self.X @ self.Vt.T
 
 
 def jacobi(A, tol=1e-14, max_sweeps=60):
@@ -184,28 +227,46 @@ def density(Vt, f):
     return D
 
 
-def charges(model, D):
-    """Net Mulliken charges q_I = sum_a D[Ia,Ia] - Z_I (orthogonal basis)."""
-    return np.diag(D).reshape(model.nat, model.no).sum(axis=1) - model.zcore
+def charges(model, D, S=None):
+    """Net Mulliken charges q_I = sum_a (D S)[Ia,Ia] - Z_I (S = I: the
+    diagonal sums of the orthogonal basis)."""
+    pop = np.diag(D) if S is None else np.einsum("ij,ji->i", D, S)
+    return pop.reshape(model.nat, model.no).sum(axis=1) - model.zcore
 
 
-def electronic(model, pos, n, H0=None, G=None, eig=None):
+def hamiltonian(model, H0, G, n, S=None):
+    """H[n] = H0 + (S V + V S)/2, V = diag of the orbital potentials
+    (Gamma n on each atom's orbitals); S = I gives H0 + V."""
+    v = model.orbital_potential(G, n)
+    if S is None:
+        return H0 + np.diag(v)
+    return H0 + 0.5 * (S * v[None, :] + v[:, None] * S)
+
+
+def electronic(model, pos, n, H0=None, G=None, eig=None, ov=None):
     """One-shot solve of the linearised functional at fixed n.
 
     `eig` (default: `jacobi`) returns (eigenvalues, eigenvectors as rows);
     a library eigensolver may stand in for Jacobi on matrices too large for
-    it, the rest of the solve being unchanged."""
+    it, the rest of the solve being unchanged.  In a non-orthogonal basis
+    `ov` = (S, X) from `Model.loewdin` (computed here when not given); the
+    eigenproblem is that of H' = X H X, and D = X D' X."""
     if H0 is None:
         H0 = model.h0(pos)
     if G is None:
         G = model.gamma(pos)
-    H = H0 + np.diag(model.orbital_potential(G, n))
-    ev, Vt = (eig or jacobi)(H)
+    S = X = None
+    if model.nonorth:
+        S, X = ov if ov is not None else model.loewdin(pos)
+    H = hamiltonian(model, H0, G, n, S)
+    ev, Vt = (eig or jacobi)(H if X is None else X @ H @ X)
     mu, f = fermi_mu(ev, model.beta, model.s.n_electrons)
     D = density(Vt, f)
-    q = charges(model, D)
+    if X is not None:
+        D = X @ D @ X
+    q = charges(model, D, S)
     return Electronic(H0=H0, G=G, H=H, evals=ev, Vt=Vt, mu=mu, f=f, D=D, q=q,
-                      n=np.array(n, dtype=np.float64))
+                      n=np.array(n, dtype=np.float64), S=S, X=X)
 
 
 # ---------------------------------------------------------------------------
@@ -234,7 +295,28 @@ def forces(model, pos, el):
                             s.taper_width, s.gamma_soft, _f64(el.D),
                             _f64(el.q), _f64(el.n), F) == 0
     _, Fr = model.erep(pos, want_force=True)
-    return F.reshape(model.nat, 3) + Fr
+    F = F.reshape(model.nat, 3) + Fr
+    if el.S is not None:
+        # S(R) enters twice: through H = H0 + (S V + V S)/2, which gives
+        # sum_ab dS_ab D_ab (V_a + V_b)/2, and through the normalisation of
+        # the generalised eigenvectors, which gives -Tr[E dS] with the
+        # energy-weighted density matrix E = 2 sum_i f_i e_i c_i c_i^T (the
+        # basis-set dependent Pulay term).  Both are -Tr[M dS/dR] for
+        # M = (V D + D V)/2 - E, the hopping-force contraction with the
+        # overlap's block and decay in place of the hopping's (and no
+        # Coulomb term).
+        v = model.orbital_potential(el.G, el.n)
+        C = el.eigvecs()
+        E = (C * (2.0 * el.f * el.evals)[None, :]) @ C.T
+        M = 0.5 * (v[:, None] * el.D + el.D * v[None, :]) - E
+        Fs = np.zeros(3 * model.nat)
+        zero = np.zeros(model.nat)
+        assert lib().orc_forces(model.nat, model.no, _f64(pos),
+                                _f64(s.overlap_block), s.overlap_decay,
+                                s.hop_cutoff, s.taper_width, s.gamma_soft,
+                                _f64(M), zero, zero, Fs) == 0
+        F = F + Fs.reshape(model.nat, 3)
+    return F
 
 
 # ---------------------------------------------------------------------------
@@ -247,10 +329,33 @@ def response(model, el, v):
     density-matrix response follows in closed form from the eigenpairs.
     """
     h = model.orbital_potential(el.G, v)
+    if el.S is not None:
+        return _response_nonorth(model, el, h)
     dd = np.zeros(model.N)
     lib().orc_response_diag(model.N, _f64(el.Vt), _f64(el.evals), model.beta,
                             el.mu, _f64(h), dd)
     return dd.reshape(model.nat, model.no).sum(axis=1)
+
+
+def _response_nonorth(model, el, h):
+    """Canonical response in a non-orthogonal basis: the perturbation of H
+    is H1 = (S diag(h) + diag(h) S)/2; in the generalised eigenbasis C
+    (C^T S C = I) its matrix is P = C^T H1 C and the response of the
+    occupation matrix is the divided difference of 2 f times P - mu' I,
+    with mu' chosen so that the electron count Tr[D1 S] = Tr[P1] stays
+    fixed (the closed form of the orthogonal case); q1 = Mulliken charges
+    of D1 = C P1 C^T."""
+    S = el.S
+    C = el.eigvecs()
+    P = C.T @ (0.5 * (S * h[None, :] + h[:, None] * S)) @ C
+    x = model.beta * (el.evals - el.mu)
+    Fd = np.empty((model.N, model.N))
+    lib().orc_fermi_divdiff_matrix(model.N, _f64(x), model.beta, Fd)
+    fd = np.diag(Fd)
+    mup = float(fd @ np.diag(P)) / float(fd.sum())
+    P1 = 2.0 * Fd * (P - mup * np.eye(model.N))
+    D1 = C @ P1 @ C.T
+    return charges(model, D1, S) + model.zcore
 
 
 def response_fd(model, pos, el, v, h=1e-4):

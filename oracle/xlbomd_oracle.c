@@ -333,6 +333,14 @@ double orc_fermi_divdiff(double xa, double xb, double beta)
  *   mu' = sum_i Delta_ii (V^T H1 V)_ii / sum_i Delta_ii,
  * with the eigenvectors v_i as the rows of Vt.
  * Writes dd[p] = D'[p,p] and returns mu'. */
+/* F[i*N + j] = orc_fermi_divdiff(x[i], x[j], beta) for all pairs */
+void orc_fermi_divdiff_matrix(int N, const double *x, double beta, double *F)
+{
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            F[(size_t)i * N + j] = orc_fermi_divdiff(x[i], x[j], beta);
+}
+
 double orc_response_diag(int N, const double *Vt, const double *ev,
                          double beta, double mu, const double *h, double *dd)
 {

@@ -51,6 +51,10 @@ class System:
     k0_gamma: float            # K0 = -gamma * I
     steps: int
     kernel_otf: int = 0        # on-the-fly rank-1 directions kept between rebuilds
+    # non-orthogonal basis: overlap block Bs (n_orb, n_orb) and its decay
+    # length, S[Ia,Jb] = Bs_ab exp(-r / overlap_decay) s(r); None = orthogonal
+    overlap_block: Optional[np.ndarray] = None
+    overlap_decay: float = 0.0
 
     @property
     def n(self) -> int:
@@ -237,6 +241,16 @@ def lattice_system(n_atoms: int, template: str = "c2", seed: int = 1,
     pos = sites + rng.uniform(-jitter, jitter, size=sites.shape)
     return _finish(f"{template}-lat{n_atoms}", cfg, rng, pos, n_atoms,
                    overrides)
+
+
+def with_overlap(s: System, scale: float = 0.3) -> System:
+    """The same system in a non-orthogonal basis: overlap block
+    -scale * B / max|B| for the hopping block B (bonding hoppings are
+    negative where overlaps are positive, as in extended-Hueckel-type
+    parametrisations) with the hopping's decay length."""
+    hb = np.asarray(s.hop_block, dtype=np.float64)
+    return s.replace(name=s.name + "-ov", overlap_block=-scale * hb / np.abs(hb).max(),
+                     overlap_decay=float(s.hop_decay))
 
 
 def serving_stream(n_requests: int = 256, rate_hz: float = 200.0,
