@@ -92,13 +92,22 @@ typedef struct {
     void *ctx;
 } xlbomd_allocator;
 
-/* System descriptor.  Model (orthogonal SCC tight binding):
+/* System descriptor.  Model (SCC tight binding, orthogonal unless an
+ * overlap block is given):
  *   H0[Ia,Ia] = onsite[a] + onsite_jitter[Ia]
  *   H0[Ia,Jb] = hop_block[a*n_orb+b] exp(-r/hop_decay) s(r), I != J, r < hop_cutoff
  *   s(r): 1 below hop_cutoff - taper_width, quintic C2 ramp to 0 at hop_cutoff
  *   Gamma[I,I] = hubbard_u[I], Gamma[I,J] = 1/sqrt(r^2 + gamma_soft^2)
  *   E_rep = sum_{I<J} rep_a exp(-r/rep_decay) s(r)
- *   q_I = sum_a D[Ia,Ia] - n_electrons/n_atoms */
+ *   H[n] = H0 + diag(Gamma n) on each atom's orbitals
+ *   q_I = sum_a D[Ia,Ia] - n_electrons/n_atoms
+ * In a non-orthogonal basis (overlap_block, Section VI's SCC-DFTB setting):
+ *   S[Ia,Ib] = delta_ab, S[Ia,Jb] = overlap_block[a*n_orb+b] exp(-r/overlap_decay) s(r)
+ *   H[n] = H0 + (S V + V S)/2, V = diag(Gamma n) on each atom's orbitals
+ *   D = 2 f at the generalised eigenproblem H C = S C E (through X = S^-1/2)
+ *   q_I = sum_a (D S)[Ia,Ia] - n_electrons/n_atoms (Mulliken)
+ *   forces include -Tr[(V D + D V)/2 dS/dR] and the Pulay term Tr[E dS/dR]
+ *   with the energy-weighted density matrix E */
 typedef struct {
     int32_t n_atoms, n_orb;       /* n_orb in 1..8; N = n_atoms*n_orb at most
                                      46336, so that a padded N x N matrix has
@@ -174,6 +183,14 @@ typedef struct {
                                      are kept after the rebuild's, the oldest
                                      leaving first.  kernel_rank + kernel_otf
                                      <= 16                                  */
+    const double *overlap_block;  /* n_orb*n_orb, symmetric: the overlap
+                                     block of a non-orthogonal basis (model
+                                     above), or NULL for an orthogonal one.
+                                     Needs XLBOMD_FP64 and host decisions
+                                     (step mode 0); positions where S is not
+                                     positive definite fail with
+                                     XLBOMD_E_NOCONV                        */
+    double overlap_decay;         /* overlap decay length, > 0 with a block */
 } xlbomd_desc;
 
 typedef struct {

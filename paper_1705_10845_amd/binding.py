@@ -81,6 +81,7 @@ class Desc(ctypes.Structure):
         ("allocator", ctypes.POINTER(Allocator)), ("foe_levels", ctypes.c_int32),
         ("foe_tol", ctypes.c_double), ("mu_tol", ctypes.c_double),
         ("kernel_otf", ctypes.c_int32),
+        ("overlap_block", _dp), ("overlap_decay", ctypes.c_double),
     ]
 
 
@@ -283,6 +284,11 @@ class XLBOMD:
         d.foe_levels = foe_levels
         d.foe_tol, d.mu_tol = float(foe_tol), float(mu_tol)
         d.kernel_otf = int(getattr(s, "kernel_otf", 0))
+        ob = getattr(s, "overlap_block", None)
+        if ob is not None:                  # non-orthogonal basis
+            keep["ov"] = _c(ob)
+            d.overlap_block = _ptr(keep["ov"])
+            d.overlap_decay = float(s.overlap_decay)
         if allocator == "torch":
             allocator = TorchAllocator()
         self.allocator = allocator

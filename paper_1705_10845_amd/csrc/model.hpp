@@ -15,6 +15,8 @@ struct ModelDev {
     const double *hop;            // no*no
     const double *U;              // nat
     double decay, rc, width, soft, rep_a, rep_decay;
+    const double *sblk;           // no*no overlap block (null: orthogonal basis)
+    double sdecay;                // overlap decay length
 };
 
 // smooth cutoff s(r) and ds/dr: 1 below rc - w, quintic C2 ramp, 0 at rc

@@ -38,6 +38,7 @@
 #include "model.hpp"
 #include "chol.hpp"
 #include "planned.hpp"
+#include "overlap.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -262,6 +263,12 @@ struct SysBase {
     double *V = nullptr, *W = nullptr, *Vprev = nullptr, *vtmp = nullptr;
     double *qp = nullptr, *hb = nullptr, *ub = nullptr, *part = nullptr, *vin = nullptr;
     double *hscal = nullptr;   // pinned host scalars
+    // non-orthogonal basis (overlap block given): the overlap block, and
+    // every atom's neighbour count set to -1 (dense rows) for the Lanczos
+    // matvecs on the dense H' = X H X
+    bool ov = false;
+    double *sblk = nullptr;
+    int *nbc_dense = nullptr;
     int head = 0;              // ring index of n(t) in hist
     int mcap = 0, rank_built = 0, rank_prev = 0, step_no = 0;
     // columns of V, W from the last rebuild, and on-the-fly directions
@@ -424,6 +431,12 @@ struct SysBase {
         A(V, (size_t)mcap * nat); A(W, (size_t)mcap * nat); A(Vprev, (size_t)mcap * nat);
         A(vtmp, nat); A(vin, (size_t)mcap * nat); A(qp, (size_t)mcap * nat); A(hb, (size_t)mcap * nat);
         A(fscr, 3 * nat); A(rdiag, nat);
+        ov = d.overlap_block != nullptr;
+        if (ov) {
+            A(sblk, no * no);
+            nbc_dense = dev<int>(nat);
+            XL_HIP(hipMemsetAsync(nbc_dense, 0xff, nat * sizeof(int), st));   // all -1
+        }
         A(ub, (size_t)mcap * Np);
         A(part, (size_t)mcap * ((Np + 63) / 64) * N + 3 * (size_t)N);
         void *hp = nullptr;
@@ -442,6 +455,7 @@ struct SysBase {
         else XL_HIP(hipMemsetAsync(jit, 0, N * sizeof(double), st));
         up(hop, d.hop_block, no * no);
         up(U, d.hubbard_u, nat);
+        if (ov) up(sblk, d.overlap_block, no * no);
         XL_HIP(hipMemsetAsync(ub, 0, (size_t)mcap * Np * sizeof(double), st));
         {   // fixed pseudo-random Lanczos start vector (xorshift64), unit norm
             std::vector<double> v0(N);
@@ -464,6 +478,8 @@ struct SysBase {
         md.pos = pos; md.onsite = onsite; md.jit = jit; md.hop = hop; md.U = U;
         md.decay = d.hop_decay; md.rc = d.hop_cutoff; md.width = d.taper_width;
         md.soft = d.gamma_soft; md.rep_a = d.rep_a; md.rep_decay = d.rep_decay;
+        md.sblk = sblk; md.sdecay = d.overlap_decay;
+        d.overlap_block = nullptr;   // host array: not kept
     }
 
     double *hist_row(int k) {
@@ -482,6 +498,10 @@ struct SysBase {
     virtual int levels_cap() const = 0;
     virtual void solve_planned() = 0;       // planned solve at n(t) = history row 0
     virtual void kernel_planned() = 0;      // sequential kernel, rank on the device
+    // non-orthogonal basis: S, X = S^-1/2 (when the positions changed), H
+    // and H' = X H X at the potentials vpot; the interval of H' into
+    // glo/ghi and its ends into scal[8..9]
+    virtual void overlap_prepare() { throw InvalidArg("overlap needs XLBOMD_FP64"); }
 
     // ---- electronic solve at charges n (device, nat) ----
     void gershgorin() {
@@ -506,7 +526,9 @@ struct SysBase {
     // most NB_MAX neighbours and at most a quarter of all atoms
     int *nbl = nullptr, *nbc = nullptr;
     int nb_max = 0;
-    bool sparse_seed() const { return nb_max > 0 && nb_max <= NB_MAX && 4 * nb_max <= nat; }
+    bool sparse_seed() const {
+        return !ov && nb_max > 0 && nb_max <= NB_MAX && 4 * nb_max <= nat;
+    }
     double *lz_v = nullptr, *lz_vp = nullptr, *lz_w = nullptr, *lz_v0 = nullptr, *lz_ab = nullptr;
     void spectral_tighten() {
         const double *a = hscal + 16, *b = hscal + 16 + LZ_M;
@@ -547,7 +569,8 @@ struct SysBase {
         hipLaunchKernelGGL(gamma_matvec_kernel, dim3(ceil_div((long)nat * 64, 256)), dim3(256),
                            0, st, md, 1, ncur, vpot);
         XL_LAUNCH_CHECK();
-        gershgorin();
+        if (ov) overlap_prepare();
+        else gershgorin();
         hipLaunchKernelGGL(neighbours_kernel, dim3(nat), dim3(64), 0, st, md, nbl, nbc);
         hipLaunchKernelGGL(max_count_kernel, dim3(1), dim3(1024), 0, st, nat, (const int *)nbc,
                            scal + 10);
@@ -885,7 +908,7 @@ struct SysBase {
     hipEvent_t done_ev = nullptr;
 
     bool planned_capable() const {
-        return d.krylov_mode == 0 && d.kernel_every == 1 && d.kernel_otf == 0;
+        return d.krylov_mode == 0 && d.kernel_every == 1 && d.kernel_otf == 0 && !ov;
     }
     void drop_graph() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -1335,6 +1358,14 @@ template <typename TF, typename TR> struct Sys : SysBase {
     TR *Ysr = nullptr, *Y2r = nullptr, *Y3r = nullptr, *Y4r = nullptr;
     TR *Zp = nullptr, *Ap = nullptr, *Tb = nullptr;   // response batch buffers
     double *m3 = nullptr;
+    // non-orthogonal basis (FP64 only): S, X = S^-1/2, Sh = S^1/2, H, H',
+    // D' (mu-corrected, orthogonalised basis), two work matrices, the
+    // Mulliken form of dD/dmu per orbital
+    double *Sm = nullptr, *Xm = nullptr, *Shm = nullptr, *Hm = nullptr, *Hpm = nullptr;
+    double *Dpm = nullptr, *Tm = nullptr, *Wm = nullptr, *gov = nullptr;
+    std::vector<double> ov_pos;    // positions X was computed at
+    long gov_for = -1;             // expansion gov belongs to
+    int ov_ns = 0;                 // Newton-Schulz steps of the last X
     double *e64[16] = {};                             // FP64 energy workspace
     int Lcap = 0, Lr = -1;                            // Lr: levels converted
 
@@ -1344,8 +1375,109 @@ template <typename TF, typename TR> struct Sys : SysBase {
     }
     int levels_cap() const override { return Lcap; }
 
+    void ov_alloc() {
+        if (Sm) return;
+        Sm = amat<double>(); Xm = amat<double>(); Shm = amat<double>(); Hm = amat<double>();
+        Hpm = amat<double>(); Dpm = amat<double>(); Tm = amat<double>(); Wm = amat<double>();
+        gov = this->template dev<double>(Np);
+    }
+    GemmArgs<double> b64() const {
+        GemmArgs<double> a;
+        a.n = Np;
+        a.ld = Np;
+        return a;
+    }
+    // X = S^-1/2 and Sh = S^1/2 by the coupled Newton-Schulz iteration
+    // Y_0 = S/c, Z_0 = I, T = (3I - Z Y)/2, Y <- Y T, Z <- T Z (Y -> (S/c)^1/2,
+    // Z -> (S/c)^-1/2; every iterate is a polynomial in S, so every product
+    // is symmetric), with c the Gershgorin bound of S, until |T - I| is
+    // below 1e-12 in every row (then one last step).
+    void inverse_sqrt() {
+        hipLaunchKernelGGL(dense_gershgorin_kernel, dim3(ceil_div((long)N * 64, 256)), dim3(256),
+                           0, st, N, Np, (const double *)Sm, glo, ghi);
+        hipLaunchKernelGGL(minmax_kernel, dim3(1), dim3(1024), 0, st, N, glo, ghi, scal + 8);
+        XL_LAUNCH_CHECK();
+        XL_HIP(hipMemcpyAsync(hscal, scal + 8, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        const double c = std::max(hscal[1], 1.0);
+        convert(Sm, Shm, 1.0 / c);                    // Y_0 (in Shm)
+        hipLaunchKernelGGL(identity_kernel, dim3(ceil_div((long)mat(), 256)), dim3(256), 0, st,
+                           (long)Np, Xm);             // Z_0 (in Xm)
+        XL_LAUNCH_CHECK();
+        for (int it = 0;; ++it) {
+            auto t = b64();                           // T = 3/2 I - Z Y / 2
+            t.A0 = Xm; t.B0 = Shm; t.alpha = -0.5; t.gamma = 1.5; t.C = Tm;
+            run_gemm(t, true);
+            hipLaunchKernelGGL(row_dev_identity_kernel, dim3(ceil_div((long)Np * 64, 256)),
+                               dim3(256), 0, st, Np, (const double *)Tm, part);
+            hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, st, Np, (const double *)part,
+                               scal + 12);
+            XL_LAUNCH_CHECK();
+            auto y = b64();                           // Y <- Y T
+            y.A0 = Shm; y.B0 = Tm; y.C = Wm;
+            run_gemm(y, true);
+            auto z = b64();                           // Z <- T Z
+            z.A0 = Tm; z.B0 = Xm; z.C = Dpm;
+            run_gemm(z, true);
+            std::swap(Shm, Wm);
+            std::swap(Xm, Dpm);
+            XL_HIP(hipMemcpyAsync(hscal + 12, scal + 12, sizeof(double), hipMemcpyDeviceToHost, st));
+            sync();
+            const double err = std::sqrt(hscal[12]);
+            if (!std::isfinite(err)) throw Diverged("non-finite overlap inverse square root");
+            if (err < 1e-12) { ov_ns = it + 1; break; }
+            if (it >= 60)
+                throw NoConv("overlap inverse square root did not converge (S not positive definite?)");
+        }
+        convert(Xm, Xm, 1.0 / std::sqrt(c));          // X = Z / sqrt(c)
+        convert(Shm, Shm, std::sqrt(c));              // Sh = sqrt(c) Y
+    }
+    void overlap_prepare() override {
+        if constexpr (!(SAME && std::is_same<TF, double>::value)) {
+            throw InvalidArg("the non-orthogonal basis needs XLBOMD_FP64");
+        } else {
+            ov_alloc();
+            hipLaunchKernelGGL(overlap_hamiltonian_kernel, dim3(ceil_div(Np, 256), Np), dim3(256), 0,
+                               st, md, (const double *)vpot, Sm, Hm);
+            XL_LAUNCH_CHECK();
+            std::vector<double> p(3 * (size_t)nat);
+            XL_HIP(hipMemcpyAsync(p.data(), pos, p.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+            sync();
+            if (p != ov_pos) {
+                inverse_sqrt();
+                ov_pos = p;
+            }
+            auto a = b64();                           // H X
+            a.A0 = Hm; a.B0 = Xm; a.C = Tm;
+            run_gemm(a, false);
+            a = b64();                                // H' = X (H X)
+            a.A0 = Xm; a.B0 = Tm; a.C = Hpm;
+            run_gemm(a, true);
+            hipLaunchKernelGGL(dense_gershgorin_kernel, dim3(ceil_div((long)N * 64, 256)),
+                               dim3(256), 0, st, N, Np, (const double *)Hpm, glo, ghi);
+            hipLaunchKernelGGL(minmax_kernel, dim3(1), dim3(1024), 0, st, N, glo, ghi, scal + 8);
+            XL_LAUNCH_CHECK();
+        }
+    }
+
     void lanczos() override {
         if (!Ys) alloc_matrices(std::max(Lcap, 1));
+        if (ov) {
+            // H' (dense) in the seed buffer; dense-row matvecs
+            hipLaunchKernelGGL(seed_dense_kernel, dim3(ceil_div(Np, 256), Np), dim3(256), 0, st, N,
+                               Np, (const double *)Hpm, 0.0, 1.0, (double *)Ys);
+            XL_LAUNCH_CHECK();
+            XL_HIP(hipMemcpyAsync(lz_v, lz_v0, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+            for (int j = 0; j < LZ_M; ++j) {
+                hipLaunchKernelGGL((sp_matvec_kernel<TF>), dim3(nat), dim3(64), 0, st, N, no, Np,
+                                   (const int *)nbl, (const int *)nbc_dense, (const TF *)Ys,
+                                   (const double *)lz_v, lz_w);
+                hipLaunchKernelGGL(lanczos_step_kernel, dim3(1), dim3(1024), 0, st, N, j, LZ_M,
+                                   lz_v, lz_vp, lz_w, lz_ab);
+            }
+            XL_LAUNCH_CHECK();
+            return;
+        }
         // H itself (scale 1, no shift) in the seed buffer; the expansion
         // rebuilds its seed there
         hipLaunchKernelGGL((build_seed_kernel<TF>), dim3(ceil_div(Np, 256), Np), dim3(256), 0, st,
@@ -1388,6 +1520,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
             Xb = this->template dev<TR>(mat() * nb);
             for (auto &q : Sd) q = this->template dev<TR>(mat() * nb);
         }
+        if (ov) Xb = this->template dev<TR>(mat() * nb);
         bcap = nb;
     }
     TR *Xb = nullptr;                 // fourth response buffer (split path)
@@ -1480,9 +1613,15 @@ template <typename TF, typename TR> struct Sys : SysBase {
         ++expansion_id;
         if constexpr (FUSE_COPY) alloc_resp_copies();
         sc = std::ldexp(beta, -(L + 1));
-        // Y = sc (H - mu0 I)
-        hipLaunchKernelGGL((build_seed_kernel<TF>), dim3(ceil_div(Np, 256), Np), dim3(256), 0, st,
-                           md, vpot, mu0, sc, Ys, mu_dev);
+        // Y = sc (H - mu0 I)  (H' = X H X in a non-orthogonal basis)
+        if (ov) {
+            if (mu_dev) throw InvalidArg("planned steps need an orthogonal basis");
+            hipLaunchKernelGGL(seed_dense_kernel, dim3(ceil_div(Np, 256), Np), dim3(256), 0, st, N,
+                               Np, (const double *)Hpm, mu0, sc, (double *)Ys);
+        } else {
+            hipLaunchKernelGGL((build_seed_kernel<TF>), dim3(ceil_div(Np, 256), Np), dim3(256), 0,
+                               st, md, vpot, mu0, sc, Ys, mu_dev);
+        }
         XL_LAUNCH_CHECK();
         const double ymax = std::ldexp(xmax, -(L + 1)), ym2 = ymax * ymax;
         t0max = ymax * (1.0 - ym2 / 3.0 + 2.0 * ym2 * ym2 / 15.0);
@@ -1766,10 +1905,38 @@ template <typename TF, typename TR> struct Sys : SysBase {
         a.X = Z[L]; a.beta = (TF)(-2.0 + 0.5 * bd * bd);
         a.X2 = ZL2; a.beta2 = (TF)(-2.0 * bd);
         a.gamma = (TF)(1.0 + 0.5 * bd); a.C = Dc;
+        if constexpr (SAME && std::is_same<TF, double>::value) {
+            if (ov) {
+                // D' in the orthogonalised basis, D = X D' X, Mulliken q
+                a.C = Dpm;
+                run_gemm(a, true);
+                auto b = b64();
+                b.A0 = Dpm; b.B0 = Xm; b.C = Tm;
+                run_gemm(b, false);
+                b = b64();
+                b.A0 = Xm; b.B0 = Tm; b.C = Dc;
+                run_gemm(b, true);
+                hipLaunchKernelGGL(mulliken_rows_kernel, dim3(ceil_div((long)N * 64, 256)),
+                                   dim3(256), 0, st, N, Np, (const double *)Dc,
+                                   (const double *)Sm, rdpop());
+                hipLaunchKernelGGL(charges_pop_kernel, dim3(1), dim3(1024), 0, st, nat, no,
+                                   (const double *)rdpop(), zc, (const double *)ncur, q, r,
+                                   scal + 16);
+                XL_LAUNCH_CHECK();
+                return;
+            }
+        }
         run_gemm(a, true);
         hipLaunchKernelGGL((charges_kernel<TF>), dim3(1), dim3(1024), 0, st, nat, no, Np, Dc, zc,
                            ncur, q, r, scal + 16);
         XL_LAUNCH_CHECK();
+    }
+    // Mulliken populations per orbital (the first Np entries of gov's
+    // neighbour: a buffer of its own)
+    double *pop = nullptr;
+    double *rdpop() {
+        if (!pop) pop = this->template dev<double>(Np);
+        return pop;
     }
 
     // ---- planned step: the solve and the kernel without host decisions ----
@@ -1955,6 +2122,26 @@ template <typename TF, typename TR> struct Sys : SysBase {
         hipLaunchKernelGGL((forces_kernel<TF>), dim3(ceil_div((long)nat * 64, 256)), dim3(256), 0,
                            st, md, Dc, q, ncur, vpot, F, epart);
         XL_LAUNCH_CHECK();
+        if constexpr (SAME && std::is_same<TF, double>::value) {
+            if (ov) {
+                // energy-weighted density matrix E = X (D' H') X, D' H'
+                // symmetrised (they commute up to the truncation error),
+                // then the overlap part of the forces
+                auto a = b64();
+                a.A0 = Dpm; a.B0 = Hpm; a.A1 = Hpm; a.B1 = Dpm; a.alpha = 0.5; a.C = Tm;
+                run_gemm(a, true);
+                a = b64();
+                a.A0 = Tm; a.B0 = Xm; a.C = Hm;
+                run_gemm(a, false);
+                a = b64();
+                a.A0 = Xm; a.B0 = Hm; a.C = Wm;
+                run_gemm(a, true);
+                hipLaunchKernelGGL(overlap_forces_kernel, dim3(ceil_div((long)nat * 64, 256)),
+                                   dim3(256), 0, st, md, (const double *)Dc, (const double *)Wm,
+                                   (const double *)vpot, F);
+                XL_LAUNCH_CHECK();
+            }
+        }
     }
 
     // response operands in TR (converted once per expansion when TF != TR)
@@ -1976,7 +2163,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
             }
             Lr = L;
         }
-        if (Y4_for != expansion_id) {   // Y^4 for the seed response, in TR (split when
+        if (!ov && Y4_for != expansion_id) {   // Y^4 for the seed response, in TR (split when
             if (!Y4r) Y4r = amat<TR>(); // the responses are)
             if (resp_split) {
                 SplitArgs a = sbase();
@@ -2119,6 +2306,12 @@ template <typename TF, typename TR> struct Sys : SysBase {
         hipLaunchKernelGGL(expand_orbital_kernel, dim3(ceil_div((long)N * nb, 256)), dim3(256), 0,
                            st, nat, no, nb, sc, hb, (long)Np, ub);
         XL_LAUNCH_CHECK();
+        if constexpr (SAME && std::is_same<TF, double>::value) {
+            if (ov) {
+                responses_ov(nb, v, qout, wout);
+                return;
+            }
+        }
         {   // G = Y D Y, H2 = Y2 D Y2, H13 = Y D Y3 + Y3 D Y, then Z'_0
             auto a = base<TR>();
             a.batch = nb; a.A0 = Ysr; a.B0 = Ysr; a.kscale = ub; a.sK = Np;
@@ -2158,6 +2351,80 @@ template <typename TF, typename TR> struct Sys : SysBase {
         XL_LAUNCH_CHECK();
         hipLaunchKernelGGL(resp_charges_kernel, dim3(nb), dim3(1024), 0, st, nat, no, nchunk, part,
                            sP, g, v, qout, wout);
+        XL_LAUNCH_CHECK();
+    }
+
+    // Responses in a non-orthogonal basis (FP64).  The perturbation of H'
+    // is dense: Y1 = sc X H1 X = (Sh U X + X U Sh)/2 with U = sc diag(Gamma v)
+    // per orbital (X S = Sh); the seed Z_0 = Y/2 - Y^3/6 + Y^5/15 is
+    // differentiated along the products that formed it,
+    //   (Y^2)' = Y1 Y + Y Y1,  (Y^3)' = Y1 Y^2 + Y (Y^2)',
+    //   Z'_0 = Y1/2 - (Y^3)'/6 + ((Y^3)' Y^2 + Y^3 (Y^2)')/15,
+    // then the levels as in the orthogonal basis, Z'_L in full, and the
+    // Mulliken charges of D1 = -2 X Z'_L X: sum over each atom's orbitals of
+    // diag(X Z'_L Sh); the canonical shift uses the same form of dD'/dmu.
+    void responses_ov(int nb, const double *v, double *qout, double *wout) {
+        const long sm = (long)mat();
+        if (gov_for != expansion_id) {        // dD'/dmu = (beta/2)(I - 4 Z_L^2)
+            auto a = b64();
+            a.A0 = (const double *)ZL2; a.B0 = Shm; a.alpha = -2.0 * beta;
+            a.X = Shm; a.beta = 0.5 * beta; a.C = Tm;
+            run_gemm(a, false);
+            const int nchunk = (N + 63) / 64;
+            hipLaunchKernelGGL((coldot_kernel<double>), dim3(ceil_div(N, 256), nchunk, 1), dim3(256),
+                               0, st, N, Np, (const double *)Xm, (const double *)Tm, 0L, part, 0L);
+            hipLaunchKernelGGL(chunk_sum_kernel, dim3(ceil_div(N, 256)), dim3(256), 0, st, N, nchunk,
+                               (const double *)part, gov);
+            XL_LAUNCH_CHECK();
+            gov_for = expansion_id;
+        }
+        double *Y1 = (double *)Tb, *Y2d = (double *)Ap, *Y3d = (double *)Zp;
+        const double *Yd = (const double *)Ys, *Y2m = (const double *)Y2, *Y3m = (const double *)Y3;
+        auto a = b64();                                  // Y1
+        a.batch = nb; a.A0 = Shm; a.B0 = Xm; a.A1 = Xm; a.B1 = Shm;
+        a.kscale = ub; a.sK = Np; a.kscale_both = true; a.alpha = 0.5; a.C = Y1; a.sC = sm;
+        run_gemm(a, true);
+        a = b64();                                       // (Y^2)'
+        a.batch = nb; a.A0 = Y1; a.sA0 = sm; a.B0 = Yd; a.A1 = Yd; a.B1 = Y1; a.sB1 = sm;
+        a.C = Y2d; a.sC = sm;
+        run_gemm(a, true);
+        a = b64();                                       // (Y^3)'
+        a.batch = nb; a.A0 = Y1; a.sA0 = sm; a.B0 = Y2m; a.A1 = Yd; a.B1 = Y2d; a.sB1 = sm;
+        a.C = Y3d; a.sC = sm;
+        run_gemm(a, true);
+        a = b64();                                       // Z'_0
+        a.batch = nb; a.A0 = Y3d; a.sA0 = sm; a.B0 = Y2m; a.A1 = Y3m; a.B1 = Y2d; a.sB1 = sm;
+        a.alpha = 1.0 / 15.0; a.X = Y3d; a.sX = sm; a.beta = -1.0 / 6.0;
+        a.X2 = Y1; a.sX2 = sm; a.beta2 = 0.5; a.C = (double *)Xb; a.sC = sm;
+        run_gemm(a, true);
+        std::swap(Zp, Xb);
+        for (int k = 0; k < L; ++k) {
+            auto p = base<TR>();           // A' = 4 (Z Z' + Z' Z)
+            p.batch = nb;
+            p.A0 = Zr[k]; p.B0 = Zp; p.sB0 = sm; p.A1 = Zp; p.sA1 = sm; p.B1 = Zr[k];
+            p.alpha = (TR)4.0; p.C = Ap; p.sC = sm;
+            run_gemm(p, true);
+            auto b = base<TR>();           // T = 2 Z' - A' Z_{k+1}
+            b.batch = nb;
+            b.A0 = Ap; b.sA0 = sm; b.B0 = Zr[k + 1]; b.alpha = (TR)-1.0;
+            b.X = Zp; b.sX = sm; b.beta = (TR)2.0; b.C = Tb; b.sC = sm;
+            run_gemm(b, false);
+            auto c = base<TR>();           // Z'_{k+1} = Y_k T
+            c.batch = nb;
+            c.A0 = Yr[k]; c.B0 = Tb; c.sB0 = sm; c.C = Zp; c.sC = sm;
+            run_gemm(c, true);
+        }
+        a = b64();                                       // Z'_L Sh
+        a.batch = nb; a.A0 = (const double *)Zp; a.sA0 = sm; a.B0 = Shm; a.C = (double *)Ap;
+        a.sC = sm;
+        run_gemm(a, false);
+        const int nchunk = (N + 63) / 64;
+        const long sP = (long)nchunk * N;
+        hipLaunchKernelGGL((coldot_kernel<double>), dim3(ceil_div(N, 256), nchunk, nb), dim3(256), 0,
+                           st, N, Np, (const double *)Xm, (const double *)Ap, sm, part, sP);
+        XL_LAUNCH_CHECK();
+        hipLaunchKernelGGL(resp_charges_kernel, dim3(nb), dim3(1024), 0, st, nat, no, nchunk, part,
+                           sP, (const double *)gov, v, qout, wout);
         XL_LAUNCH_CHECK();
     }
 
@@ -2430,6 +2697,16 @@ void validate(const xlbomd_desc *d) {
         throw InvalidArg("model lengths must be positive");
     for (int i = 0; i < d->n_atoms; ++i)
         if (!(d->mass[i] > 0.0)) throw InvalidArg("masses must be positive");
+    if (d->overlap_block) {
+        if (d->precision != XLBOMD_FP64)
+            throw InvalidArg("a non-orthogonal basis needs XLBOMD_FP64");
+        if (!(d->overlap_decay > 0.0)) throw InvalidArg("overlap_decay must be > 0");
+        for (int a = 0; a < d->n_orb; ++a)
+            for (int b = 0; b < d->n_orb; ++b)
+                if (!std::isfinite(d->overlap_block[a * d->n_orb + b]) ||
+                    d->overlap_block[a * d->n_orb + b] != d->overlap_block[b * d->n_orb + a])
+                    throw InvalidArg("overlap_block must be finite and symmetric");
+    }
 }
 
 }  // namespace
@@ -2553,7 +2830,8 @@ int xlbomd_set_step_mode(xlbomd_system *h, int32_t mode) {
         SysBase &s = *h->s;
         if (mode < 0 || mode > 2) throw InvalidArg("step mode must be 0, 1 or 2");
         if (mode != 0 && !s.planned_capable())
-            throw InvalidArg("planned steps need krylov_mode 0, kernel_every 1 and kernel_otf 0");
+            throw InvalidArg("planned steps need krylov_mode 0, kernel_every 1, kernel_otf 0 "
+                             "and an orthogonal basis");
         if (mode != s.step_mode) s.drop_graph();
         s.step_mode = mode;
     });

@@ -112,3 +112,16 @@ def test_missing_arrays_and_handles():
     assert L.xlbomd_kernel_update(None, 0) == -1
     F = np.zeros(3)
     assert L.xlbomd_forces(None, F.ctypes.data_as(B._dp), None) == -1
+
+
+def test_overlap_rules():
+    s = _c1()
+    ok_block = np.array([[0.3]])
+    e = _rejected(s.replace(overlap_block=ok_block, overlap_decay=1.0), precision=B.MIXED_BF16X3)
+    assert e.code == -1 and "XLBOMD_FP64" in str(e)
+    e = _rejected(s.replace(overlap_block=ok_block, overlap_decay=0.0))
+    assert e.code == -1 and "overlap_decay" in str(e)
+    s4 = _c1().replace(n_orb=2, n_electrons=64.0, onsite=np.zeros(2), hop_block=-np.eye(2))
+    e = _rejected(s4.replace(overlap_block=np.array([[0.1, 0.2], [0.0, 0.1]]),
+                             overlap_decay=1.0))
+    assert e.code == -1 and "symmetric" in str(e)
