@@ -214,6 +214,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving leg (p50/p99 step latency)")
     ap.add_argument("--serving-requests", type=int, default=64)
+    ap.add_argument("--no-nonorth", action="store_true",
+                    help="skip the FP64 leg of the workload in a non-orthogonal basis")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the planned-graph leg of the headline workload")
     ap.add_argument("--serving-only", action="store_true")
@@ -224,7 +226,7 @@ def main():
               "communication); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    from synth import make_system
+    from synth import make_system, with_overlap
     from paper_1705_10845_amd import FP32, FP64, MIXED, MIXED_BF16X3
     s = make_system("c2")
     if args.serving_only:
@@ -245,6 +247,10 @@ def main():
     fp64t = None if args.no_fp64 else time_path(s, FP64, args.fp64_steps, 1,
                                                  "fp64 (FP64 targets)")
     fp32 = None if args.no_fp32 else time_path(s, FP32, args.steps, 1, "fp32")
+    # the same workload in a non-orthogonal basis (overlap, Loewdin solve,
+    # Mulliken charges from D S, Pulay forces): FP64 at its own targets
+    nonorth = None if args.no_nonorth else time_path(with_overlap(s), FP64, args.fp64_steps, 1,
+                                                     "fp64, non-orthogonal basis")
 
     def roof(prof, steps):
         # the dominant product class of the step (the most kernel time)
@@ -307,6 +313,11 @@ def main():
         out["mixed_over_fp64_own_targets"] = mixed["steps_per_s"] / fp64t["steps_per_s"]
     if fp32 is not None:
         out["fp32"] = summary(fp32, args.steps)
+    if nonorth is not None:
+        out["fp64_nonorthogonal"] = summary(nonorth, args.fp64_steps)
+        out["fp64_nonorthogonal"]["workload"] = (
+            "the same system with overlap block -0.3 B / max|B| (hopping block B) and the "
+            "hopping's decay length; FP64, Newton-Schulz S^-1/2 per step, dense X H X seed")
     if not args.no_graph:
         out["mixed_planned_graph"] = time_graph(s, MIXED_BF16X3, args.steps, args.warmup)
     if not args.no_serving:

@@ -164,10 +164,11 @@ class Model:
         assert rc == 0
         return S
 
-    def loewdin(self, pos):
-        """(S, X = S^-1/2) from the eigen-decomposition of S (Jacobi)."""
+    def loewdin(self, pos, eig=None):
+        """(S, X = S^-1/2) from the eigen-decomposition of S (Jacobi, or
+        `eig` with the same return convention)."""
         S = self.overlap(pos)
-        ev, Vt = jacobi(S)
+        ev, Vt = (eig or jacobi)(S)
         if ev.min() <= 0.0:
             raise ValueError("overlap matrix is not positive definite")
         X = Vt.T @ np.diag(1.0 / np.sqrt(ev)) @ Vt
@@ -257,7 +258,7 @@ def electronic(model, pos, n, H0=None, G=None, eig=None, ov=None):
         G = model.gamma(pos)
     S = X = None
     if model.nonorth:
-        S, X = ov if ov is not None else model.loewdin(pos)
+        S, X = ov if ov is not None else model.loewdin(pos, eig)
     H = hamiltonian(model, H0, G, n, S)
     ev, Vt = (eig or jacobi)(H if X is None else X @ H @ X)
     mu, f = fermi_mu(ev, model.beta, model.s.n_electrons)

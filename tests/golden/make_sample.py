@@ -9,6 +9,10 @@ charge vector n (PCG64 seed 11, mean removed):
       (Section V.B), K_4 r from the literal Sherman-Morrison sequence of
       rank-1 updates (Eqs. 48-51; K0 = -0.01 I, sequential directions from
       K0 r), and the forces at fixed n (Eq. 40).
+  c2ov_n4096_full.txt  the same for the c2 system in a non-orthogonal
+      basis (synth.with_overlap: overlap block -0.3 B / max|B|, the
+      hopping's decay length; Section VI's SCC-DFTB setting): Loewdin
+      solve, Mulliken charges from D S, Pulay forces.
 
 Every value comes from the oracle (oracle/reference.py and its C loops: the
 Fermi-Dirac density at fixed electron number of Section IV.B, Eq. 36, the
@@ -19,6 +23,7 @@ stands in for the oracle's Jacobi sweeps, which are too slow at these sizes.
 Nothing here calls the HIP library.
 
     python tests/golden/make_sample.py c2    (about five minutes of CPU)
+    python tests/golden/make_sample.py c2ov  (about eight minutes)
     python tests/golden/make_sample.py c3    (about two minutes)
     python tests/golden/make_sample.py c5    (about ten minutes, ~15 GB)
 """
@@ -30,7 +35,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-from synth import make_system          # noqa: E402
+from synth import make_system, with_overlap   # noqa: E402
 from oracle import reference as R      # noqa: E402
 
 N_SEED, SAMPLE_SEED, N_SAMPLE = 11, 12, 128
@@ -89,8 +94,12 @@ def write_sample(name):
     print("wrote", path)
 
 
+def full_system(name):
+    return with_overlap(make_system("c2")) if name == "c2ov" else make_system(name)
+
+
 def write_full(name):
-    s = make_system(name)
+    s = full_system(name)
     m = R.Model(s)
     n = charge_vector(s.n_atoms)
     el = R.electronic(m, s.pos, n, eig=_eigh_rows)
@@ -113,6 +122,9 @@ def write_full(name):
         f.write(f"# with PCG64 seeds {DIR_SEEDS[0]}, {DIR_SEEDS[1]}, normalised; Section V.B),\n")
         f.write(f"# K_{KERNEL_RANK} r with r = q - n from the Sherman-Morrison sequence of\n")
         f.write(f"# Eqs. 48-51 (K0 = -{KERNEL_GAMMA} I, sequential directions), forces Fx Fy Fz\n")
+        if s.overlap_block is not None:
+            f.write("# non-orthogonal basis (overlap block -0.3 B / max|B|, the hopping's decay\n")
+            f.write("# length): Loewdin solve, Mulliken charges from D S, Pulay forces\n")
         f.write(SUBSTITUTION)
         f.write(f"mu {el.mu:.17e}\n")
         for k in ("omega", "e_band", "e_coul", "e_rep", "te_s"):
@@ -140,7 +152,7 @@ def read_full(name, n_orbitals):
 
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "c3"
-    if which == "c2":
-        write_full("c2")
+    if which in ("c2", "c2ov"):
+        write_full(which)
     else:
         write_sample(which)

@@ -1,6 +1,7 @@
 """Parity at the full size of the benchmarked workload (1024 atoms x 4
 orbitals, N = 4096), against the oracle's stored values
-(tests/golden/c2_n4096_full.txt, written by tests/golden/make_sample.py):
+(tests/golden/c2_n4096_full.txt, and c2ov_n4096_full.txt for the same
+system in a non-orthogonal basis; written by tests/golden/make_sample.py):
 charges, chemical potential, free energy and entropy, forces, canonical
 responses to two fixed unit directions (Section V.B) and K_4 r from the
 literal Sherman-Morrison sequence (Eqs. 48-51).
@@ -22,7 +23,7 @@ import os
 import numpy as np
 import pytest
 
-from synth import make_system
+
 
 pytestmark = pytest.mark.gpu
 
@@ -50,11 +51,12 @@ BOUNDS = {
 }
 
 
-@pytest.mark.parametrize("prec_name", ["FP64", "MIXED_BF16X3"])
-def test_c2_full_size_against_stored_oracle(P, prec_name):
+@pytest.mark.parametrize("name,prec_name", [("c2", "FP64"), ("c2", "MIXED_BF16X3"),
+                                            ("c2ov", "FP64")])
+def test_c2_full_size_against_stored_oracle(P, name, prec_name):
     gen = _gen()
-    scal, rows = gen.read_full("c2", 4096)
-    s = make_system("c2")
+    scal, rows = gen.read_full(name, 4096)
+    s = gen.full_system(name)
     assert rows.shape == (s.n_atoms, 7)
     n = gen.charge_vector(s.n_atoms)
     q_ref, resp_ref, kr_ref, F_ref = rows[:, 0], rows[:, 1:3].T, rows[:, 3], rows[:, 4:7]
@@ -74,7 +76,7 @@ def test_c2_full_size_against_stored_oracle(P, prec_name):
         resp=max(np.abs(dq[i] - resp_ref[i]).max() / np.abs(resp_ref[i]).max() for i in range(2)),
         kr=np.abs(kr - kr_ref).max() / np.abs(kr_ref).max(),
     )
-    print(f"N=4096 {prec_name} vs stored oracle:", {k: f"{v:.2e}" for k, v in err.items()},
+    print(f"N=4096 {name} {prec_name} vs stored oracle:", {k: f"{v:.2e}" for k, v in err.items()},
           f"TS {e['te_s']:.10f} (oracle {scal['te_s']:.10f})")
     for k, b in BOUNDS[prec_name].items():
         assert err[k] < b, (k, err[k], b)
