@@ -28,10 +28,11 @@ sys.path.insert(0, ROOT)
 
 # dense MFMA TFLOP/s, MI355X; a split bf16x3 product is three bf16 products,
 # so its algorithmic peak is a third of the bf16 rate
-PEAK = {"f32": 157.3, "f64": 78.6, "bf3": 2500.0 / 3}
+PEAK = {"f32": 157.3, "f64": 78.6, "bf3": 2500.0 / 3, "bf16": 2500.0}
 KERNEL = {"f64": "gemm_tn_kernel<double>", "f32": "gemm_tn_kernel<float>",
           "bf3": "split bf16x3 products: gemm_bw_kernel (256 x 128 tiles, pre-split "
-                 "operands) with its split-k fix-up"}
+                 "operands) with its split-k fix-up",
+          "bf16": "plain bf16 products: gemm_bw_kernel on the hi planes only"}
 
 
 def _sync():
@@ -214,6 +215,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving leg (p50/p99 step latency)")
     ap.add_argument("--serving-requests", type=int, default=64)
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the plain-bf16 response tier (XLBOMD_MIXED_BF16)")
     ap.add_argument("--no-nonorth", action="store_true",
                     help="skip the FP64 leg of the workload in a non-orthogonal basis")
     ap.add_argument("--no-graph", action="store_true",
@@ -227,7 +230,7 @@ def main():
         sys.exit(2)
 
     from synth import make_system, with_overlap
-    from paper_1705_10845_amd import FP32, FP64, MIXED, MIXED_BF16X3
+    from paper_1705_10845_amd import FP32, FP64, MIXED, MIXED_BF16, MIXED_BF16X3
     s = make_system("c2")
     if args.serving_only:
         t0 = time.perf_counter()
@@ -239,6 +242,9 @@ def main():
     mixed = time_path(s, MIXED_BF16X3, args.steps, args.warmup, "mixed (bf16x3 responses)")
     mixed32 = None if args.no_mixed_fp32 else time_path(s, MIXED, args.steps, 1,
                                                         "mixed (FP32 responses)")
+    # the same expansion with plain bf16 response products (the BF16 tier)
+    mixed16 = None if args.no_bf16 else time_path(s, MIXED_BF16, args.steps, 1,
+                                                  "mixed (plain bf16 responses)")
     # FP64 at the mixed path's accuracy targets (truncation 1e-9, mu rerun
     # threshold 1e-3), and at its own tighter defaults (2e-10, 1e-6)
     fp64 = None if args.no_fp64 else time_path(s, FP64, args.fp64_steps, 1,
@@ -303,6 +309,11 @@ def main():
     }
     if mixed32 is not None:
         out["mixed_fp32_responses"] = summary(mixed32, args.steps)
+    if mixed16 is not None:
+        out["mixed_bf16_responses"] = summary(mixed16, args.steps)
+        out["mixed_bf16_responses"]["precision"] = (
+            "XLBOMD_MIXED_BF16: the headline's expansion (same charges, forces and energy "
+            "at a given n), plain bf16 response products (the BF16 tier)")
     if fp64 is not None:
         # equal accuracy: both paths at truncation 1e-9 and mu threshold 1e-3
         out["fp64_plain"] = summary(fp64, args.fp64_steps)

@@ -62,7 +62,7 @@ typedef enum {
     XLBOMD_MIXED = 2,        /* density-matrix expansion in FP64 MFMA (it
                                 fixes charges, forces, energy); the
                                 kernel's response products in FP32 MFMA   */
-    XLBOMD_MIXED_BF16X3 = 3  /* split-precision bf16x3 products: each FP32
+    XLBOMD_MIXED_BF16X3 = 3, /* split-precision bf16x3 products: each FP32
                                 operand is split into bf16 hi + lo parts
                                 and hi*hi + hi*lo + lo*hi is accumulated
                                 in FP32 on the bf16 matrix cores (relative
@@ -75,6 +75,14 @@ typedef enum {
                                 level in a step: charges within ~1e-9 of
                                 the FP64 path; twice inside an SCF whose
                                 tolerance is below 1e-8)                   */
+    XLBOMD_MIXED_BF16 = 4    /* the expansion of XLBOMD_MIXED_BF16X3 (the
+                                same charges, forces and energy at a given
+                                n) with plain bf16 response products: the
+                                hi parts only, one bf16 matrix-core product
+                                each (relative error ~2^-8 per operand).
+                                The kernel is a preconditioner, so this
+                                changes the path of n, not the accuracy of
+                                the quantities computed from it          */
 } xlbomd_precision;
 
 /* Optional source of the device memory a system holds (PyTorch's caching
@@ -383,9 +391,9 @@ int xlbomd_scf(xlbomd_system *h, const double *n0, int32_t rank, double gamma, d
 
 /* Live timing of the dense MFMA products.  enable != 0 starts recording a
  * HIP event pair on the handle's stream around every product launched by
- * later calls; enable == 0 stops and, if out != NULL, writes 15 doubles:
- * out[0..4] for FP64 products, out[5..9] for FP32 products and out[10..14]
- * for split bf16x3 products, each
+ * later calls; enable == 0 stops and, if out != NULL, writes 20 doubles:
+ * out[0..4] for FP64 products, out[5..9] for FP32 products, out[10..14]
+ * for split bf16x3 products and out[15..19] for plain bf16 products, each
  *   {total kernel milliseconds, total algorithmic flops (2 n_k flops per
  *    output entry on the real n x n block; symmetric outputs count n(n+1)/2
  *    entries), number of launches, shortest launch ms, longest launch ms}. */
@@ -411,8 +419,10 @@ int xlbomd_selftest_gemm_time(int32_t n, int32_t precision, int32_t sym, int32_t
  * MIXED_BF16X3 response recursion): A and B (n x n row-major host arrays,
  * n a positive multiple of 128) are rounded to FP32 and stored as bf16
  * hi/lo planes; C = A B^T, i.e. C[i][j] = sum_k A[i][k] B[j][k], with the
- * result itself stored split and returned as hi + lo.  sym != 0 computes the
- * upper block triangle and mirrors it (valid when A B^T is symmetric).  With
+ * result itself stored split and returned as hi + lo.  Bit 0 of sym
+ * computes the upper block triangle and mirrors it (valid when A B^T is
+ * symmetric); bit 1 multiplies the hi planes only (the plain bf16 product
+ * of XLBOMD_MIXED_BF16).  With
  * reps > 0 the product is then launched reps more times and *ms_per_launch
  * receives the average time.  Synchronous. */
 int xlbomd_selftest_gemm_presplit(int32_t n, int32_t sym, int32_t reps, const double *A,

@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libxlbomd.so")
 
-FP64, FP32, MIXED, MIXED_BF16X3 = 0, 1, 2, 3
+FP64, FP32, MIXED, MIXED_BF16X3, MIXED_BF16 = 0, 1, 2, 3, 4
 _dp = ctypes.POINTER(ctypes.c_double)
 
 
@@ -217,14 +217,16 @@ def selftest_gemm_time(n, precision=FP64, sym=False, dual=False, reps=10):
     return float(out[0])
 
 
-def selftest_gemm_presplit(A, B, sym=False, reps=0):
-    """C = A B^T with the split product on pre-split operands (test hook).
-    Returns C, or (C, ms per launch) when reps > 0."""
+def selftest_gemm_presplit(A, B, sym=False, reps=0, hi_only=False):
+    """C = A B^T with the split product on pre-split operands (test hook;
+    hi_only: the plain bf16 product of the hi planes).  Returns C, or
+    (C, ms per launch) when reps > 0."""
     A = _c(A); B = _c(B)
     n = A.shape[0]
     C = np.zeros((n, n))
     ms = np.zeros(1)
-    _check(lib().xlbomd_selftest_gemm_presplit(n, 1 if sym else 0, reps, _ptr(A), _ptr(B),
+    flags = (1 if sym else 0) | (2 if hi_only else 0)
+    _check(lib().xlbomd_selftest_gemm_presplit(n, flags, reps, _ptr(A), _ptr(B),
                                                _ptr(C), _ptr(ms)))
     return (C, float(ms[0])) if reps > 0 else C
 
@@ -402,11 +404,13 @@ class XLBOMD:
 
     def profile_stop(self):
         """GEMM timing since profile_start: {'f64': {...}, 'f32': {...},
-        'bf3': {...}} (split bf16x3 products in 'bf3')."""
-        out = np.zeros(15)
+        'bf3': {...}, 'bf16': {...}} (split bf16x3 products in 'bf3', plain
+        bf16 products in 'bf16')."""
+        out = np.zeros(20)
         _check(lib().xlbomd_profile(self._h, 0, _ptr(out)))
         res = {}
-        for key, o in (("f64", out[:5]), ("f32", out[5:10]), ("bf3", out[10:])):
+        for key, o in (("f64", out[:5]), ("f32", out[5:10]), ("bf3", out[10:15]),
+                       ("bf16", out[15:])):
             res[key] = dict(ms=o[0], flops=o[1], launches=int(o[2]),
                             min_ms=o[3], max_ms=o[4])
         return res

@@ -14,6 +14,10 @@
 // go (also) to an FP64 matrix Cd.  The epilogue sum and its coefficients
 // are FP64.
 //
+// With `hi_only` the product is a plain bf16 one: only the hi planes of A
+// and B are loaded and multiplied (hi.hi, relative error ~2^-8 per
+// operand); the result is still written as a split matrix (its FP32 value).
+//
 // Against gemm_bf3_kernel (FP32 operands split while staging) the k-tiles
 // here are copied into LDS as 16-byte chunks with no conversion work, the
 // workgroup has 8 waves (four per SIMD at two workgroups per CU), and
@@ -38,6 +42,7 @@ struct SplitArgs {
     float *ws = nullptr;                          // split-k partial tiles (FP32)
     long ws_elems = 0;
     const int *skip = nullptr;                    // device flag: skip the launch while set
+    bool hi_only = false;                         // plain bf16 product (hi planes only)
 };
 
 // chunk permutation of LDS row r (values 0..3, rows in pairs): with it the
@@ -97,7 +102,7 @@ __device__ __forceinline__ void epilogue_split_block(const SplitArgs &p, long bz
 // (two waves per SIMD reach less than half of it).
 constexpr int BS_T = 512;
 
-template <bool SYM>
+template <bool SYM, bool HI>
 __global__ __launch_bounds__(BS_T, 2) void gemm_bs_kernel(SplitArgs p, int ntiles, int nfull,
                                                        int nsplit, int per_xcd) {
     if (p.skip && *p.skip) return;   // skipped launch (device flag)
@@ -148,15 +153,17 @@ __global__ __launch_bounds__(BS_T, 2) void gemm_bs_kernel(SplitArgs p, int ntile
     const int kt1 = (int)((long)nktot * (split + 1) / ns);
 
     // chunk v of thread tid: plane (idx >> 9), row ((idx >> 2) & 127),
-    // chunk (idx & 3) of the 128 x 32 k-tile, idx = tid + 512 v
-    u32x4 ra[2], rb[2];
+    // chunk (idx & 3) of the 128 x 32 k-tile, idx = tid + 512 v (HI: the
+    // hi plane only, v = 0)
+    constexpr int NV = HI ? 1 : 2;
+    u32x4 ra[NV], rb[NV];
     auto gload = [&](int kt) {
         const bool second = kt >= nk1;
         const uint16_t *Ap = second ? A1 : A0;
         const uint16_t *Bp = second ? B1 : B0;
         const int kb = (second ? kt - nk1 : kt) * B3K;
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
+        for (int v = 0; v < NV; ++v) {
             const int idx = tid + BS_T * v;
             const int pln = idx >> 9, row = (idx >> 2) & 127, ch = idx & 3;
             const long off = pln * pl + kb + 8 * ch;
@@ -166,7 +173,7 @@ __global__ __launch_bounds__(BS_T, 2) void gemm_bs_kernel(SplitArgs p, int ntile
     };
     auto sstore = [&](int buf) {
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
+        for (int v = 0; v < NV; ++v) {
             const int idx = tid + BS_T * v;
             const int pln = idx >> 9, row = (idx >> 2) & 127, ch = idx & 3;
             As[buf][pln][row][ch ^ swz(row)] = ra[v];
@@ -187,20 +194,22 @@ __global__ __launch_bounds__(BS_T, 2) void gemm_bs_kernel(SplitArgs p, int ntile
         for (int q = 0; q < 4; ++q) {
             const int r = wr * 64 + q * 16 + fc, c = fr ^ swz(r);
             ah[q] = __builtin_bit_cast(bf16x8, As[buf][0][r][c]);
-            al[q] = __builtin_bit_cast(bf16x8, As[buf][1][r][c]);
+            if (!HI) al[q] = __builtin_bit_cast(bf16x8, As[buf][1][r][c]);
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int r = wc * 32 + q * 16 + fc, c = fr ^ swz(r);
             bh[q] = __builtin_bit_cast(bf16x8, Bs[buf][0][r][c]);
-            bl[q] = __builtin_bit_cast(bf16x8, Bs[buf][1][r][c]);
+            if (!HI) bl[q] = __builtin_bit_cast(bf16x8, Bs[buf][1][r][c]);
         }
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
             for (int y = 0; y < 2; ++y) {
-                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], bh[y], acc[x][y], 0, 0, 0);
-                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bl[y], acc[x][y], 0, 0, 0);
+                if (!HI) {
+                    acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], bh[y], acc[x][y], 0, 0, 0);
+                    acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bl[y], acc[x][y], 0, 0, 0);
+                }
                 acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
             }
         if (kt + 1 < kt1) sstore(buf ^ 1);
@@ -310,13 +319,14 @@ struct BwFrag {
     bf16x8 ah[4], al[4], bh[4], bl[4];
 };
 
-template <bool SYM>
+template <bool SYM, bool HI>
 __global__ __launch_bounds__(BW_NTH, 1) void gemm_bw_kernel(SplitArgs p, int ntiles, int nfull,
                                                          int nsplit, int per_xcd) {
     if (p.skip && *p.skip) return;   // skipped launch (device flag)
     using acc_t = f32x4;
     constexpr int NTH = BW_NTH;
-    constexpr int NA = 2048 / NTH, NB = 1024 / NTH;   // 16-byte chunks per thread
+    constexpr int NPL = HI ? 1 : 2;                    // planes loaded (HI: hi only)
+    constexpr int NA = NPL * 1024 / NTH, NB = NPL * 512 / NTH;   // 16-byte chunks per thread
     __shared__ __attribute__((aligned(16))) u32x4 As[2][2][BW_M][4];
     __shared__ __attribute__((aligned(16))) u32x4 Bs[2][2][GT][4];
 
@@ -402,13 +412,13 @@ __global__ __launch_bounds__(BW_NTH, 1) void gemm_bw_kernel(SplitArgs p, int nti
         for (int q = 0; q < 4; ++q) {
             const int r = wr * 64 + q * 16 + fc, c = fr ^ swz(r);
             f.ah[q] = __builtin_bit_cast(bf16x8, As[buf][0][r][c]);
-            f.al[q] = __builtin_bit_cast(bf16x8, As[buf][1][r][c]);
+            if (!HI) f.al[q] = __builtin_bit_cast(bf16x8, As[buf][1][r][c]);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = wc * 64 + q * 16 + fc, c = fr ^ swz(r);
             f.bh[q] = __builtin_bit_cast(bf16x8, Bs[buf][0][r][c]);
-            f.bl[q] = __builtin_bit_cast(bf16x8, Bs[buf][1][r][c]);
+            if (!HI) f.bl[q] = __builtin_bit_cast(bf16x8, Bs[buf][1][r][c]);
         }
     };
     // one of the three split terms (lo.hi, hi.lo, hi.hi) over the 4 x 4
@@ -429,18 +439,22 @@ __global__ __launch_bounds__(BW_NTH, 1) void gemm_bw_kernel(SplitArgs p, int nti
     // instructions are spread between the MFMAs (one read or store per two
     // MFMAs): issued in a burst after the barrier they fill the LDS queue
     // and hold up the MFMAs behind them.
+    // HI: 8 fragment reads and 16 MFMAs per k-tile, one read per MFMA
+    constexpr int NMF = HI ? 16 : 48, NRD = HI ? 8 : 16, MPR = HI ? 1 : 2;
     auto step = [&](int kt, const BwFrag &cur, BwFrag &nxt) {
         const int buf = (kt - kt0) & 1;
         fread(buf ^ 1, nxt);
-        mfma(cur.al, cur.bh);
-        mfma(cur.ah, cur.bl);
+        if (!HI) {
+            mfma(cur.al, cur.bh);
+            mfma(cur.ah, cur.bl);
+        }
         sstore(buf);                        // every wave read t's fragments before the last barrier
         gload(min(kt + 3, kt1 - 1));
         mfma(cur.ah, cur.bh);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < NRD; ++i) {
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x008, MPR, 0); // MFMA
         }
 #pragma unroll
         for (int i = 0; i < NA + NB; ++i) {
@@ -448,7 +462,7 @@ __global__ __launch_bounds__(BW_NTH, 1) void gemm_bw_kernel(SplitArgs p, int nti
             __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // global read
             __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // MFMA
         }
-        __builtin_amdgcn_sched_group_barrier(0x008, 48 - 32 - 2 * (NA + NB), 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, NMF - NRD * MPR - 2 * (NA + NB), 0);
         __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
     };
@@ -533,12 +547,9 @@ inline void gemm_split(const SplitArgs &a, bool sym, hipStream_t st) {
         const int tail_units = (ntiles - s.nfull) * s.nsplit;
         const int per = (tail_units + NXCD - 1) / NXCD;
         dim3 grid(nfull_pad + per * NXCD, 1, a.batch);
-        if (sym)
-            hipLaunchKernelGGL((gemm_bw_kernel<true>), grid, dim3(BW_NTH), 0, st, a,
-                               ntiles, s.nfull, s.nsplit, per);
-        else
-            hipLaunchKernelGGL((gemm_bw_kernel<false>), grid, dim3(BW_NTH), 0, st, a,
-                               ntiles, s.nfull, s.nsplit, per);
+        auto kern = sym ? (a.hi_only ? gemm_bw_kernel<true, true> : gemm_bw_kernel<true, false>)
+                        : (a.hi_only ? gemm_bw_kernel<false, true> : gemm_bw_kernel<false, false>);
+        hipLaunchKernelGGL(kern, grid, dim3(BW_NTH), 0, st, a, ntiles, s.nfull, s.nsplit, per);
         XL_LAUNCH_CHECK();
         if (s.nfull < ntiles) {
             dim3 g2(ntiles - s.nfull, 32, a.batch);   // 16 blocks x 2 halves
@@ -562,12 +573,9 @@ inline void gemm_split(const SplitArgs &a, bool sym, hipStream_t st) {
     const int tail_units = (ntiles - s.nfull) * s.nsplit;
     const int per = (tail_units + NXCD - 1) / NXCD;
     dim3 grid(nfull_pad + per * NXCD, 1, a.batch);
-    if (sym)
-        hipLaunchKernelGGL((gemm_bs_kernel<true>), grid, dim3(BS_T), 0, st, a, ntiles, s.nfull,
-                           s.nsplit, per);
-    else
-        hipLaunchKernelGGL((gemm_bs_kernel<false>), grid, dim3(BS_T), 0, st, a, ntiles, s.nfull,
-                           s.nsplit, per);
+    auto kern = sym ? (a.hi_only ? gemm_bs_kernel<true, true> : gemm_bs_kernel<true, false>)
+                    : (a.hi_only ? gemm_bs_kernel<false, true> : gemm_bs_kernel<false, false>);
+    hipLaunchKernelGGL(kern, grid, dim3(BS_T), 0, st, a, ntiles, s.nfull, s.nsplit, per);
     XL_LAUNCH_CHECK();
     if (s.nfull < ntiles) {
         dim3 g2(ntiles - s.nfull, 8, a.batch);

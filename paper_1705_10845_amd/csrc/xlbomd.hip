@@ -1350,6 +1350,10 @@ void SysBase::swap_kernel_set() {
 template <typename TF, typename TR> struct Sys : SysBase {
     static constexpr bool SAME = std::is_same<TF, TR>::value;
     bool resp_split = false;       // response products as split bf16x3 (TR = float)
+    // the kernel's response products as plain bf16 products (hi planes of
+    // the split operands only; XLBOMD_MIXED_BF16)
+    bool resp_bf16 = false;
+    bool hi_now = false;           // set while responses_split runs
     std::vector<TF *> Z, Yk;       // Z_0..Z_L, Y_0..Y_{L-1}
     std::vector<TF *> Ak;          // A_k = I + 4 Z_k^2, k < L (kept for the entropy)
     TF *Ys = nullptr, *Y2 = nullptr, *Y3 = nullptr, *E = nullptr, *Wk = nullptr;
@@ -2185,9 +2189,10 @@ template <typename TF, typename TR> struct Sys : SysBase {
         a.ws = w.ws;
         a.ws_elems = w.ws_elems;
         if (cur_skip) a.skip = cur_skip;
+        a.hi_only = hi_now;
         prof_begin();
         gemm_split(a, sym, st);
-        prof_end(gemm_flops(sym, a.A1 ? 2 : 1) * a.batch, 2);
+        prof_end(gemm_flops(sym, a.A1 ? 2 : 1) * a.batch, a.hi_only ? 3 : 2);
     }
 
     // Responses with the recursion's operands in split bf16 storage: the
@@ -2195,6 +2200,11 @@ template <typename TF, typename TR> struct Sys : SysBase {
     // A' = 4 (Z Z' + Z' Z), T^T = 2 Z' - Z_{k+1} A' (T stored transposed),
     // Z'_{k+1} = Y_k T, all on pre-split operands; last level diag(Y T).
     void responses_split(int nb, const double *v, double *qout, double *wout) {
+        struct Hi {
+            bool &f;
+            Hi(bool &f_, bool on) : f(f_) { f = on; }
+            ~Hi() { f = false; }
+        } hi(hi_now, resp_bf16);
         const long sm = (long)mat();
         hipLaunchKernelGGL(gamma_matvec_kernel, dim3(ceil_div((long)nat * nb * 64, 256)),
                            dim3(256), 0, st, md, nb, v, hb);
@@ -2689,9 +2699,9 @@ void validate(const xlbomd_desc *d) {
         throw InvalidArg("foe_tol must be 0 or in [1e-14, 1e-3]");
     if (d->mu_tol != 0.0 && !(d->mu_tol >= 1e-12 && d->mu_tol <= 1e-1))
         throw InvalidArg("mu_tol must be 0 or in [1e-12, 1e-1]");
-    if (d->precision < XLBOMD_FP64 || d->precision > XLBOMD_MIXED_BF16X3)
-        throw InvalidArg("precision must be XLBOMD_FP64, XLBOMD_FP32, XLBOMD_MIXED or "
-                         "XLBOMD_MIXED_BF16X3");
+    if (d->precision < XLBOMD_FP64 || d->precision > XLBOMD_MIXED_BF16)
+        throw InvalidArg("precision must be XLBOMD_FP64, XLBOMD_FP32, XLBOMD_MIXED, "
+                         "XLBOMD_MIXED_BF16X3 or XLBOMD_MIXED_BF16");
     if (!(d->hop_decay > 0.0) || !(d->hop_cutoff > 0.0) || d->taper_width < 0.0 ||
         !(d->gamma_soft > 0.0) || (d->rep_a != 0.0 && !(d->rep_decay > 0.0)))
         throw InvalidArg("model lengths must be positive");
@@ -2723,7 +2733,9 @@ int xlbomd_init_system(const xlbomd_desc *desc, xlbomd_system **out) {
         else if (desc->precision == XLBOMD_FP32) h->s.reset(new Sys<float, float>());
         else {
             auto *m = new Sys<double, float>();
-            m->resp_split = desc->precision == XLBOMD_MIXED_BF16X3;
+            m->resp_split = desc->precision == XLBOMD_MIXED_BF16X3 ||
+                            desc->precision == XLBOMD_MIXED_BF16;
+            m->resp_bf16 = desc->precision == XLBOMD_MIXED_BF16;
             h->s.reset(m);
         }
         h->s->upload_model(desc);
@@ -3100,7 +3112,8 @@ int xlbomd_profile(xlbomd_system *h, int32_t enable, double *out) {
             s.prof.cls.clear();
             return;
         }
-        double acc[3][5] = {{0, 0, 0, 1e300, 0}, {0, 0, 0, 1e300, 0}, {0, 0, 0, 1e300, 0}};
+        double acc[4][5] = {{0, 0, 0, 1e300, 0}, {0, 0, 0, 1e300, 0}, {0, 0, 0, 1e300, 0},
+                            {0, 0, 0, 1e300, 0}};
         const size_t n = s.prof.used / 2;
         for (size_t i = 0; i < n; ++i) {
             float e = 0.0f;
@@ -3114,7 +3127,7 @@ int xlbomd_profile(xlbomd_system *h, int32_t enable, double *out) {
         }
         s.prof.on = false;
         if (out)
-            for (int p = 0; p < 3; ++p) {
+            for (int p = 0; p < 4; ++p) {
                 if (acc[p][2] == 0.0) acc[p][3] = 0.0;
                 for (int k = 0; k < 5; ++k) out[5 * p + k] = acc[p][k];
             }
@@ -3211,6 +3224,8 @@ int xlbomd_selftest_gemm_presplit(int32_t n, int32_t sym, int32_t reps, const do
                  *c = dalloc<uint16_t>(2 * nn);
         SplitArgs ga;
         ga.n = n; ga.ld = n; ga.pl = (long)nn; ga.A0 = a; ga.B0 = b; ga.C = c;
+        ga.hi_only = (sym & 2) != 0;
+        sym &= 1;
         ga.ws_elems = split_bs_ws_elems(n, sym != 0, 0, 1);
         float *ws = dalloc<float>(ga.ws_elems);
         ga.ws = ws;

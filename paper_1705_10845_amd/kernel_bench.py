@@ -6,7 +6,8 @@
 Times the library's product kernels at n x n through the C ABI hooks
 `xlbomd_selftest_gemm_time` / `xlbomd_selftest_gemm_presplit` for each
 precision (0 FP64, 1 FP32, 3 split bf16x3 on FP32 operands, 4 split bf16x3
-on pre-split operands) in three launch shapes (symmetric output, full output, two products
+on pre-split operands, 5 plain bf16 on the hi planes of pre-split operands)
+in three launch shapes (symmetric output, full output, two products
 concatenated along k) and prints algorithmic TFLOP/s against the dense MFMA
 peak.  With --copy-gib > 0 it first runs one device-to-device copy of that
 size: under `rocprofv3 --pmc FETCH_SIZE` / `WRITE_SIZE` this copy is the
@@ -15,8 +16,8 @@ calibration of the counters (known bytes read and written).
 import argparse
 import sys
 
-PEAK = {0: 78.6, 1: 157.3, 3: 2500.0 / 3, 4: 2500.0 / 3}
-NAME = {0: "f64", 1: "f32", 3: "bf16x3", 4: "bf16x3 pre-split"}
+PEAK = {0: 78.6, 1: 157.3, 3: 2500.0 / 3, 4: 2500.0 / 3, 5: 2500.0}
+NAME = {0: "f64", 1: "f32", 3: "bf16x3", 4: "bf16x3 pre-split", 5: "bf16 pre-split"}
 
 
 def main(argv=None):
@@ -40,14 +41,15 @@ def main(argv=None):
     n = args.n
     for prec in (int(p) for p in args.prec.split(",")):
         for sym, dual in ((True, False), (False, False), (True, True)):
-            if prec == 4:       # operands of the response recursion, pre-split
+            if prec in (4, 5):  # operands of the response recursion, pre-split
                 if dual:
                     continue
                 import numpy as np
                 rng = np.random.default_rng(1)
                 A = rng.standard_normal((n, n))
                 A = A + A.T
-                _, ms = B.selftest_gemm_presplit(A, A, sym=sym, reps=args.reps)
+                _, ms = B.selftest_gemm_presplit(A, A, sym=sym, reps=args.reps,
+                                                 hi_only=prec == 5)
             else:
                 ms = B.selftest_gemm_time(n, prec, sym, dual, reps=args.reps)
             ent = n * (n + 1) / 2 if sym else n * n

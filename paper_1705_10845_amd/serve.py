@@ -27,9 +27,9 @@ from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
-from .binding import MIXED, MIXED_BF16X3, FP32, FP64, XLBOMD
+from .binding import MIXED, MIXED_BF16X3, MIXED_BF16, FP32, FP64, XLBOMD
 
-_ESZ = {FP64: (8, 8), FP32: (4, 4), MIXED: (8, 4), MIXED_BF16X3: (8, 4)}
+_ESZ = {FP64: (8, 8), FP32: (4, 4), MIXED: (8, 4), MIXED_BF16X3: (8, 4), MIXED_BF16: (8, 4)}
 
 
 def footprint_bytes(system, precision=MIXED, levels=10, planned=True) -> int:
@@ -50,7 +50,7 @@ def footprint_bytes(system, precision=MIXED, levels=10, planned=True) -> int:
     ef, er = _ESZ[precision]
     m = max(1, system.rank)
     mats_f = 3 * levels + 8
-    if precision == MIXED_BF16X3:
+    if precision in (MIXED_BF16X3, MIXED_BF16):
         mats_r = 9 * m + 2 * levels + 13
         set_r = 2 * levels + 9
     else:

@@ -120,3 +120,31 @@ def test_gemm_presplit(B, n, sym):
     assert exact < 3e-5 * np.sqrt(n) * scale
     if sym:
         assert np.array_equal(C, C.T)
+
+
+@pytest.mark.parametrize("n", [128, 384, 1024, 2048])
+@pytest.mark.parametrize("sym", [False, True])
+def test_gemm_presplit_bf16(B, n, sym):
+    """Plain bf16 product (XLBOMD_MIXED_BF16's responses): C = A_hi B_hi^T
+    from the hi planes only, against the same product emulated on the CPU
+    (hi planes from the same rounding), and within bf16 accuracy of A B^T."""
+    rng = np.random.default_rng(5 * n + int(sym))
+    A = rng.standard_normal((n, n)); A = 0.5 * (A + A.T)
+    Bm = A @ A + 0.3 * A if sym else rng.standard_normal((n, n))
+    ah, _ = split_bf16x3(A)
+    bh, _ = split_bf16x3(Bm)
+    ref = ah @ bh.T
+    if sym:
+        # A_hi B_hi^T is symmetric only to bf16 accuracy: the kernel computes
+        # the upper block triangle and mirrors it
+        ref = np.triu(ref) + np.triu(ref, 1).T
+    scale = np.abs(A).max() * np.abs(Bm).max()
+    C = B.selftest_gemm_presplit(A, Bm, sym=sym, hi_only=True)
+    tol = 2e-6 * np.sqrt(n) * scale + 2.0 ** -15 * np.abs(ref).max()
+    err = np.abs(C - ref).max()
+    exact = np.abs(C - A @ Bm.T).max()
+    print(f"bf16 n={n} sym={sym}: vs emulation {err:.2e} (tol {tol:.1e}), vs exact {exact:.2e}")
+    assert err < tol
+    assert exact < 2e-2 * np.sqrt(n) * scale
+    if sym:
+        assert np.array_equal(C, C.T)

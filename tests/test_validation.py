@@ -82,7 +82,7 @@ def test_level_request_and_precision_ranges():
     assert e.code == -1 and "foe_levels" in str(e)
     e = _rejected(_c1(), foe_levels=-1)
     assert e.code == -1 and "foe_levels" in str(e)
-    e = _rejected(_c1(), precision=4)
+    e = _rejected(_c1(), precision=5)
     assert e.code == -1 and "precision" in str(e)
 
 
