@@ -319,6 +319,102 @@ struct BwFrag {
     bf16x8 ah[4], al[4], bh[4], bl[4];
 };
 
+// Epilogue of a whole 256 x 128 tile of a symmetric product with a split
+// output.  The elements on or above the diagonal go out from the
+// accumulator layout as in epilogue_split_at; their mirror images, which
+// written the same way would be 2-byte stores 2 ld bytes apart, are staged
+// in LDS (stg: 64 x 129 floats, the tile's k-tile buffers, free after the
+// k loop) one 64-row band at a time and written as rows of the transposed
+// band: four consecutive elements per lane, one 8-byte store per plane.
+// The mirror gets the same FP32 value, so the output is the same bit for
+// bit.  Called by every thread of the workgroup (it has barriers).
+// Epilogue of a whole 256 x 128 tile of a symmetric product with a split
+// output.  Every element on or above the diagonal is written from the
+// accumulator layout as in epilogue_split_at, and its FP32 value replaces
+// the accumulator.  The mirror images, which written the same way would be
+// 2-byte stores 2 ld bytes apart, then go through LDS one 128-row band at a
+// time (stg: 128 x 128 floats in the tile's k-tile buffers, free after the
+// k loop; element (r, c) at r * 128 + (c ^ (r & 31)) to spread the banks)
+// and are written as rows of the transposed band, four consecutive elements
+// per lane, one 8-byte store per plane.  The mirror gets the same FP32
+// value, so the output is the same bit for bit.  Called by every thread of
+// the workgroup (it has barriers).
+__device__ __forceinline__ void bw_sym_epilogue(const SplitArgs &p, long bz, int i0, int j0,
+                                                int wr, int wc, int fr, int fc, int tid,
+                                                f32x4 (&acc)[4][4], float *stg) {
+    const int ld = p.ld;
+    uint16_t *C = p.C + bz * p.sC;
+    const uint16_t *X = p.X ? p.X + bz * p.sX : nullptr;
+    const double *Xd = p.Xd ? p.Xd + bz * p.sX : nullptr;
+    const double *Xd2 = p.Xd2 ? p.Xd2 + bz * p.sX : nullptr;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = i0 + wr * 64 + x * 16 + 4 * fr + r;
+                const int col = j0 + wc * 64 + y * 16 + fc;
+                float v = 0.f;
+                if (row <= col) {
+                    const long o = (long)row * ld + col;
+                    double val = p.alpha * (double)acc[x][y][r];
+                    if (X) val += p.beta * (double)get_split(X, p.pl, o);
+                    if (Xd) val += p.beta * Xd[o];
+                    if (Xd2) val += p.beta2 * Xd2[o];
+                    if (row == col) val += p.gamma;
+                    v = (float)val;
+                    put_split(C, p.pl, o, v);
+                }
+                acc[x][y][r] = v;
+            }
+    const int wrf = __builtin_amdgcn_readfirstlane(wr);
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+        if ((wrf >> 1) == h) {             // the band's two wave rows stage it
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int rl = (wr & 1) * 64 + x * 16 + 4 * fr + r;
+                        const int cl = wc * 64 + y * 16 + fc;
+                        stg[rl * 128 + (cl ^ (rl & 31))] = acc[x][y][r];
+                    }
+        }
+        __syncthreads();
+        // output rows j0 + c, columns i0 + 128 h + r4 .. + 3; element k is
+        // the mirror of (i0 + 128 h + r4 + k, j0 + c), written when that
+        // lies strictly above the diagonal
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+            const int e = it * 512 + tid;
+            const int c = e >> 5, r4 = (e & 31) * 4;
+            const int orow = j0 + c, ocol = i0 + 128 * h + r4;
+            float v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int rl = r4 + k;
+                v[k] = stg[rl * 128 + (c ^ (rl & 31))];
+            }
+            const long o = (long)orow * ld + ocol;
+            if (ocol + 3 < orow) {
+                unsigned h0, l0, h1, l1;
+                split_pair(v[0], v[1], h0, l0);
+                split_pair(v[2], v[3], h1, l1);
+                *reinterpret_cast<u32x2 *>(C + o) = u32x2{h0, h1};
+                *reinterpret_cast<u32x2 *>(C + o + p.pl) = u32x2{l0, l1};
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (ocol + k < orow) put_split(C, p.pl, o + k, v[k]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <bool SYM, bool HI>
 __global__ __launch_bounds__(BW_NTH, 1) void gemm_bw_kernel(SplitArgs p, int ntiles, int nfull,
                                                          int nsplit, int per_xcd) {
@@ -489,6 +585,13 @@ __global__ __launch_bounds__(BW_NTH, 1) void gemm_bw_kernel(SplitArgs p, int nti
 #pragma unroll
             for (int y = 0; y < 4; ++y) wp[(x * 4 + y) * NTH] = acc[x][y];
         return;
+    }
+    if constexpr (SYM) {
+        if (p.C && !p.Cd) {
+            bw_sym_epilogue(p, bz, i0, j0, wr, wc, fr, fc, tid, acc,
+                            reinterpret_cast<float *>(&As[0][0][0][0]));
+            return;
+        }
     }
 #pragma unroll
     for (int x = 0; x < 4; ++x)
