@@ -64,8 +64,8 @@ ENERGY_EVERY = 10   # free-energy report cadence (every 10th step, in the timed 
 # source they were measured with.
 GEMM_SRC = [os.path.join(ROOT, "paper_1705_10845_amd", "csrc", f)
             for f in ("gemm.hpp", "gemm_split.hpp")]
-TRAFFIC = {"sha256": "668cfd643622746ab6b32dfd77afb4748ba854a3144c7efb8d8f6601c3efdb61",
-           "f64": 3.338e9, "bf3": 7.413e8}
+TRAFFIC = {"sha256": "28c8972046f21fb39b894b16d090c95acb0902a0dc45c60f37dd6f6cbb333317",
+           "f64": 3.344e9, "bf3": 7.067e8}
 
 
 def gemm_src_hash():
@@ -222,6 +222,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the planned-graph leg of the headline workload")
     ap.add_argument("--serving-only", action="store_true")
+    ap.add_argument("--only", choices=["mixed_bf16", "nonorth"],
+                    help="time one other leg alone (for kernel traces of it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: every system is stepped on one "
@@ -237,6 +239,15 @@ def main():
         summ = serving(args.serving_requests)
         summ["wall_total_s"] = time.perf_counter() - t0
         print(json.dumps({"serving": summ}), flush=True)
+        return
+
+    if args.only:
+        sysm, prec = ((s, MIXED_BF16) if args.only == "mixed_bf16"
+                      else (with_overlap(s), FP64))
+        r = time_path(sysm, prec, args.steps, args.warmup, args.only)
+        print(json.dumps({args.only: {"value": r["steps_per_s"], "ms_per_step": r["ms_per_step"],
+                                      "steps": args.steps, "warmup": args.warmup,
+                                      "foe_levels": r["report"]["foe_levels"]}}), flush=True)
         return
 
     mixed = time_path(s, MIXED_BF16X3, args.steps, args.warmup, "mixed (bf16x3 responses)")
