@@ -100,6 +100,8 @@ class Server:
         self.init_workers = int(init_workers)
         self.peak_used = 0
         self.peak_active = 0
+        # planned-step counters summed over the finished systems
+        self.plan_stats = {"planned": 0, "replays": 0, "captures": 0, "fallbacks": 0}
 
     def _init(self, system):
         g = XLBOMD(system, precision=self.precision, scf_tol=self.scf_tol)
@@ -212,6 +214,10 @@ class Server:
                             continue
                         n, q = r.g.charges()
                         r.st.final = dict(q=q, n=n)
+                        if self.step_mode:
+                            for k, v in r.g.step_stats().items():
+                                if k in self.plan_stats:
+                                    self.plan_stats[k] += int(v)
                     except Exception as e:
                         r.st.error = repr(e)
                     running.remove(r)
@@ -234,5 +240,6 @@ class Server:
             p50_queue_ms=float(np.percentile(qd, 50) * 1e3),
             p99_queue_ms=float(np.percentile(qd, 99) * 1e3),
             peak_hbm_bytes=self.peak_used, hbm_budget=self.budget,
-            peak_active=self.peak_active, step_mode=self.step_mode)
+            peak_active=self.peak_active, step_mode=self.step_mode,
+            plan_stats=dict(self.plan_stats) if self.step_mode else None)
         return stats, summary
