@@ -2,7 +2,9 @@
 the N = 4096 lattice for 1000 steps, the small-gap N = 8192 lattice for 500
 steps (plus its split-vs-FP32 comparison), and the randomly packed
 N = 16384 system for 160 steps, i.e. across three rebuilds of its rank-6
-kernel (every 50 steps, on-the-fly rank-1 updates in between).
+kernel (every 50 steps, on-the-fly rank-1 updates in between); and two
+further paths: the BF16 tier on the N = 4096 lattice (500 steps) and a
+160-atom lattice in a non-orthogonal basis (FP64, 600 steps).
 
 All three start far from mechanical equilibrium (jittered lattices, a
 random packing, zero velocities): potential energy turns into 150-300
@@ -121,3 +123,21 @@ def test_c5_three_kernel_rebuilds(P):
     # rank-1 updates in between
     assert min(out["ranks"]) >= 6 and max(out["ranks"]) <= 16
     assert out["rms_max"] < 5e-2
+
+
+def test_c2_bf16_tier_500_steps(P):
+    """The BF16 tier (plain bf16 responses) on the N = 4096 workload: the
+    same conservation criteria over 500 steps."""
+    out = _run(P, make_system("c2"), 500, P.MIXED_BF16, label="c2 bf16")
+    _no_drift(out)
+    assert out["rms_max"] < 1e-2
+
+
+def test_nonorthogonal_lattice_600_steps(P):
+    """A 160-atom s+3p lattice in a non-orthogonal basis (FP64): the same
+    conservation criteria over 600 steps."""
+    from synth import lattice_system, with_overlap
+    s = with_overlap(lattice_system(160, "c2", seed=12))
+    out = _run(P, s, 600, P.FP64, label="lat160 overlap")
+    _no_drift(out)
+    assert out["rms_max"] < 1e-2
