@@ -43,7 +43,9 @@ def footprint_bytes(system, precision=MIXED, levels=10, planned=True) -> int:
     copies of the expansion operands (Z, Y, Y..Y^4) when the two precisions
     differ, and on the split path the split Y, Y^2, Y^3, Z_L^2 and four
     level work matrices.  Planned steps hold a second set of the expansion
-    buffers (the rerun at the corrected chemical potential) and Z_L^3.
+    buffers (the rerun at the corrected chemical potential) and Z_L^3.  A
+    non-orthogonal basis adds eight FP64 matrices (S, S^-1/2, S^1/2, H, H',
+    D', two work matrices) and a fourth response batch buffer.
     """
     n = system.n_atoms * system.n_orb
     npad = -(-n // 128) * 128
@@ -59,6 +61,9 @@ def footprint_bytes(system, precision=MIXED, levels=10, planned=True) -> int:
     if planned:
         mats_f += 3 * levels + 8
         mats_r += set_r
+    if getattr(system, "overlap_block", None) is not None:
+        mats_f += 8
+        mats_r += m
     vecs = 64 * system.n_atoms * 8 + 16 * npad * 8
     return npad * npad * (mats_f * ef + mats_r * er) + vecs
 

@@ -157,3 +157,18 @@ def test_energy_conservation_nonorth(gpu):
           f"drift over the run {slope * len(et):.2e}")
     assert ek.max() - ek.min() > 50 * et.std()
     assert abs(slope) * len(et) < 2.0 * et.std() + 1e-8
+
+
+def test_nonorth_refuses_planned_steps_and_other_precisions(gpu):
+    """Planned steps and the reduced precisions are not built for a
+    non-orthogonal basis: both are refused with XLBOMD_E_INVALID."""
+    s = CASES["c1"]()
+    g = gpu.XLBOMD(s, precision=gpu.FP64, scf_tol=1e-9)
+    with pytest.raises(gpu.XlbomdError) as e:
+        g.set_step_mode(2)
+    assert e.value.code == -1 and "orthogonal" in str(e.value)
+    g.step(2, report=False)              # still stepping with host decisions
+    g.close()
+    with pytest.raises(gpu.XlbomdError) as e:
+        gpu.XLBOMD(s, precision=gpu.MIXED_BF16X3)
+    assert e.value.code == -1
