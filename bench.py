@@ -152,7 +152,7 @@ def cpu_baseline():
             "exponent": p, "extrapolated_s_per_step_N4096": t4096}
 
 
-def serving(n_requests=64, slots=16, budget_gib=96, step_mode=2):
+def serving(n_requests=64, slots=16, budget_gib=96, step_mode=0):
     """The serving workload: Poisson stream (200/s) of independent systems,
     16-512 atoms x 4 orbitals, Te U[0.02, 0.1], rank 2-6, 100 steps each,
     admitted by HBM footprint; the headline (MIXED_BF16X3) precision.

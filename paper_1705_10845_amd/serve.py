@@ -4,15 +4,24 @@ Requests (a System and an arrival time) are admitted while their estimated
 HBM footprint fits the budget and a slot is free.  An admitted system is set
 up (ground state by the kernel SCF) by a worker thread, then joins the
 running set: its whole state stays resident on the device (its library
-handle) and it takes planned steps, every decision on the device, each
-replayed from the system's captured HIP graph on its own stream.  One host
-thread drives all running systems: it polls their steps and enqueues each
-system's next step as soon as its last one is done, so the device overlaps
-the steps of every running system and a small system is never held back by
-a large one.  Requests that arrive while others run are admitted as slots
-and memory free up.  Per-step latency (completion of step s minus
-completion of step s-1, or of the initial state for s = 1) and the queueing
-delay (arrival to admission) are recorded.
+handle) and it steps on its own stream, each system's next step starting
+as soon as its last one is done, so the device overlaps the steps of every
+running system and a small system is never held back by a large one.  Two
+ways of stepping:
+
+  step_mode 0 (default): steps with host decisions, each taken by a worker
+      thread of its own system;
+  step_mode 2: planned steps (every decision on the device), each replayed
+      from the system's captured HIP graph, all enqueued and polled by the
+      one host thread that runs the loop.
+
+Step mode 0 serves the 16-512-atom stream faster: a planned step always
+launches its rerun expansion (returning at once when no rerun is needed),
+and these steps are bound by the GPU, not by the host.  Requests that
+arrive while others run are admitted as slots and memory free up.
+Per-step latency (completion of step s minus completion of step s-1, or of
+the initial state for s = 1) and the queueing delay (arrival to admission)
+are recorded.
 
 Only scheduling lives here; every step runs in the HIP library.
 """
@@ -94,7 +103,7 @@ class _Running:
 class Server:
     def __init__(self, hbm_budget: int, max_slots: int = 8, precision=MIXED,
                  steps: int = 100, scf_tol: Optional[float] = None,
-                 verbose: bool = False, step_mode: int = 2, init_workers: int = 4):
+                 verbose: bool = False, step_mode: int = 0, init_workers: int = 4):
         self.verbose = verbose
         self.budget = int(hbm_budget)
         self.max_slots = int(max_slots)
