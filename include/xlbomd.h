@@ -428,6 +428,18 @@ int xlbomd_selftest_gemm_time(int32_t n, int32_t precision, int32_t sym, int32_t
 int xlbomd_selftest_gemm_presplit(int32_t n, int32_t sym, int32_t reps, const double *A,
                                   const double *B, double *C, double *ms_per_launch);
 
+/* Kernel-level test hook for the batched FP64 log-determinant behind the
+ * electronic entropy of the free energy (the Fermi-Dirac entropy term of
+ * the Mermin functional, evaluated as log-determinants of the expansion's
+ * level matrices): slot b < nb of the batch holds A + b shift I, and
+ * out[b] receives its ln det.  A is an n x n row-major symmetric positive
+ * definite host array (only its lower triangle is read), n a positive
+ * multiple of 128, nb >= 1; every slot must stay positive definite
+ * (a non-positive pivot gives NaN).  The slots are factorised as one
+ * batch, as in the entropy evaluation.  Synchronous. */
+int xlbomd_selftest_logdet(int32_t n, int32_t nb, double shift, const double *A,
+                           double *out);
+
 /* The split product of xlbomd_selftest_gemm_presplit on device operands,
  * allocating nothing: for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid

@@ -155,6 +155,8 @@ def lib():
                                            ctypes.c_int32, _dp, _dp, _dp]
         L.xlbomd_selftest_gemm_time.argtypes = [ctypes.c_int32] * 5 + [_dp]
         L.xlbomd_selftest_gemm_presplit.argtypes = [ctypes.c_int32] * 3 + [_dp, _dp, _dp, _dp]
+        L.xlbomd_selftest_logdet.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                             _dp, _dp]
         L.xlbomd_gemm_presplit_noalloc.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp,
                                                    vp, vp]
         L.xlbomd_destroy.argtypes = [vp]
@@ -174,7 +176,7 @@ EXPORTED = ("xlbomd_init_system", "xlbomd_step", "xlbomd_step_batch",
             "xlbomd_load_state", "xlbomd_solve", "xlbomd_response",
             "xlbomd_kernel_apply", "xlbomd_scf", "xlbomd_profile", "xlbomd_selftest_gemm",
             "xlbomd_selftest_gemm_time", "xlbomd_selftest_gemm_presplit",
-            "xlbomd_gemm_presplit_noalloc",
+            "xlbomd_selftest_logdet", "xlbomd_gemm_presplit_noalloc",
             "xlbomd_destroy", "xlbomd_last_error",
             "xlbomd_version")
 
@@ -229,6 +231,15 @@ def selftest_gemm_presplit(A, B, sym=False, reps=0, hi_only=False):
     _check(lib().xlbomd_selftest_gemm_presplit(n, flags, reps, _ptr(A), _ptr(B),
                                                _ptr(C), _ptr(ms)))
     return (C, float(ms[0])) if reps > 0 else C
+
+
+def selftest_logdet(A, nb=1, shift=0.0):
+    """ln det(A + b shift I) for b < nb, factorised as one batch by the
+    library's blocked FP64 Cholesky (test hook)."""
+    A = _c(A)
+    out = np.zeros(nb)
+    _check(lib().xlbomd_selftest_logdet(A.shape[0], int(nb), float(shift), _ptr(A), _ptr(out)))
+    return out
 
 
 def gemm_presplit_noalloc(n, sym, A_ptr, B_ptr, C_ptr, stream=None):

@@ -37,7 +37,11 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 //     entries broadcast from their lanes);
 //  2. every row i below is updated the same way and solved against the
 //     factor: L_iq = (A_iq - L_i,[p,q) L_q,[p,q)^T) L_qq^-T.
-// Block 0 writes the factored diagonal block and adds 2 sum ln L_ii to *acc.
+// Every block factors the diagonal block itself from the original entries,
+// so none of them may be overwritten during the launch: the factored block
+// stays in LDS only (no later step reads it: inner panels further right
+// read only rows below it, the trailing update only rows below the outer
+// panel).  Block 0 adds 2 sum ln L_ii to *acc.
 constexpr int CHOL_PT = 64;
 __global__ __launch_bounds__(CHOL_PT) void chol_panel_kernel(int n, int ld, int p, int q,
                                                              double *A, long sA, double *acc) {
@@ -75,16 +79,10 @@ __global__ __launch_bounds__(CHOL_PT) void chol_panel_kernel(int n, int ld, int 
         for (int j = 0; j < CB; ++j) Ld[lane][j] = (j <= lane) ? row[j] : 0.0;
     }
     __syncthreads();
-    if (blockIdx.x == 0) {
-        if (lane < CB) {
-#pragma unroll
-            for (int j = 0; j < CB; ++j) A[(long)(q + lane) * ld + q + j] = Ld[lane][j];
-        }
-        if (lane == 0) {
-            double s = 0.0;
-            for (int k = 0; k < CB; ++k) s += log(Ld[k][k]);
-            acc[0] += 2.0 * s;
-        }
+    if (blockIdx.x == 0 && lane == 0) {
+        double s = 0.0;
+        for (int k = 0; k < CB; ++k) s += log(Ld[k][k]);
+        acc[0] += 2.0 * s;
     }
     const int i = q + CB + blockIdx.x * CHOL_PT + lane;
     if (i >= n) return;
@@ -127,6 +125,10 @@ __global__ __launch_bounds__(256) void chol_transpose_kernel(int m, int ld, int 
         if (i0 + tx < m) P[(long)(k0 + r) * m + i0 + tx] = t[tx][r];
 }
 
+__global__ void chol_zero_kernel(int nb, double *out) {
+    if ((int)threadIdx.x < nb) out[threadIdx.x] = 0.0;
+}
+
 // ln det of each of the nb n x n matrices A + b sA (destroyed; only the
 // lower triangles are read), n % NB == 0, into out[b] (device).  P is an
 // NB x n workspace per matrix (stride sP >= NB n), ws (ws_elems doubles)
@@ -134,8 +136,11 @@ __global__ __launch_bounds__(256) void chol_transpose_kernel(int m, int ld, int 
 inline void chol_logdet(int n, int ld, int nb, double *A, long sA, double *P, long sP, double *ws,
                         long ws_elems, double *out, hipStream_t st) {
     if (n % NB) throw InvalidArg("chol_logdet: n must be a multiple of 128");
-    if (nb < 1 || sP < (long)NB * n) throw InvalidArg("chol_logdet: bad batch");
-    XL_HIP(hipMemsetAsync(out, 0, nb * sizeof(double), st));
+    if (nb < 1 || nb > 1024 || sP < (long)NB * n) throw InvalidArg("chol_logdet: bad batch");
+    // the accumulators are cleared by a kernel, not a memset node, so the
+    // sequence stays valid inside a captured graph
+    hipLaunchKernelGGL(chol_zero_kernel, dim3(1), dim3(1024), 0, st, nb, out);
+    XL_LAUNCH_CHECK();
     for (int p = 0; p < n; p += NB) {
         const int pe = p + NB;
         for (int q = p; q < pe; q += CB) {

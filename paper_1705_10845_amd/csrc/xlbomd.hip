@@ -2599,6 +2599,13 @@ template <typename TF, typename TR> struct Sys : SysBase {
         const double s1 = 0.5 * trX - zx;             // <1/2 I - Z_L, X_eff>
         const double s2 = trX - 4.0 * z2x;            // <X_eff, I - 4 Z_L^2>
         const double S0 = 2.0 * (-lnF + s1);
+        if (debug()) {
+            std::fprintf(stderr, "[xlbomd] entropy L %d t0max %.6f J %d lnF %.10f trX %.10f "
+                         "zx %.10f z2x %.10f S0 %.10f dmu %.3e lds:", L, t0max, J, lnF, trX, zx,
+                         z2x, S0, dmu);
+            for (double v : lds) std::fprintf(stderr, " %.10f", v);
+            std::fprintf(stderr, "\n");
+        }
         return S0 / beta + dmu * 0.5 * s2;
     }
 };
@@ -3254,6 +3261,29 @@ int xlbomd_selftest_gemm_presplit(int32_t n, int32_t sym, int32_t reps, const do
             (void)hipEventDestroy(e1);
             *ms_per_launch = ms / reps;
         }
+    });
+}
+
+int xlbomd_selftest_logdet(int32_t n, int32_t nb, double shift, const double *A,
+                           double *out) {
+    if (n <= 0 || n % 128 || nb < 1 || nb > 1024 || !A || !out)
+        return fail(XLBOMD_E_INVALID, "bad self-test args");
+    if (!std::isfinite(shift)) return fail(XLBOMD_E_INVALID, "self-test shift must be finite");
+    return guarded([&] {
+        const size_t nn = (size_t)n * n;
+        double *dA = dalloc<double>(nn), *batch = dalloc<double>(nn * nb);
+        double *P = dalloc<double>((size_t)NB * n * nb), *dout = dalloc<double>(nb);
+        DevFree fr;
+        fr.ptrs = {dA, batch, P, dout};
+        XL_HIP(hipMemcpy(dA, A, nn * 8, hipMemcpyHostToDevice));
+        for (int b = 0; b < nb; ++b) {
+            hipLaunchKernelGGL(add_diag_copy_kernel, dim3(ceil_div((long)nn, 256)), dim3(256), 0,
+                               0, n, n, (const double *)dA, b * shift, batch + (size_t)b * nn);
+            XL_LAUNCH_CHECK();
+        }
+        chol_logdet(n, n, nb, batch, (long)nn, P, (long)NB * n, nullptr, 0, dout, 0);
+        XL_HIP(hipDeviceSynchronize());
+        XL_HIP(hipMemcpy(out, dout, nb * sizeof(double), hipMemcpyDeviceToHost));
     });
 }
 
