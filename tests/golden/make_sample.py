@@ -1,8 +1,10 @@
 """Writes the stored oracle values of the large workloads, at a fixed, seeded
 charge vector n (PCG64 seed 11, mean removed):
 
-  <name>_n<N>_sample.txt  (c3, c5): the chemical potential and the net
-      charges of a seeded sample of 128 atoms.
+  <name>_n<N>_sample.txt  (c3, c5): the chemical potential, the free
+      energy and its parts, and for a seeded sample of 128 atoms the net
+      charge, the canonical response dq/dlambda along the unit direction v1
+      (Section V.B) and the force at fixed n (Eq. 40).
   c2_n4096_full.txt  (c2, 1024 atoms x 4 orbitals): mu, the free energy and
       its parts, and per atom the net charge q, the canonical responses
       dq/dlambda of q[n + lambda v] to two fixed unit directions v1, v2
@@ -24,8 +26,8 @@ Nothing here calls the HIP library.
 
     python tests/golden/make_sample.py c2    (about five minutes of CPU)
     python tests/golden/make_sample.py c2ov  (about eight minutes)
-    python tests/golden/make_sample.py c3    (about two minutes)
-    python tests/golden/make_sample.py c5    (about ten minutes, ~15 GB)
+    python tests/golden/make_sample.py c3    (about five minutes)
+    python tests/golden/make_sample.py c5    (about half an hour, ~25 GB)
 """
 import os
 import sys
@@ -76,22 +78,51 @@ def full_path(name, n_orbitals):
 
 def write_sample(name):
     s = make_system(name)
+    m = R.Model(s)
     n = charge_vector(s.n_atoms)
-    ref = R.electronic(R.Model(s), s.pos, n, eig=_eigh_rows)
+    ref = R.electronic(m, s.pos, n, eig=_eigh_rows)
+    print("solved", flush=True)
+    en = R.free_energy(m, s.pos, ref)
+    F = R.forces(m, s.pos, ref)
+    dq = R.response(m, ref, unit_direction(s.n_atoms, DIR_SEEDS[0]))
+    print("response", flush=True)
     atoms = sample_atoms(s.n_atoms)
     path = sample_path(name, s.n)
     with open(path, "w") as f:
-        f.write(f"# oracle charges of the {name} workload ({s.n_atoms} atoms x {s.n_orb} "
+        f.write(f"# oracle values of the {name} workload ({s.n_atoms} atoms x {s.n_orb} "
                 f"orbitals, Te = {s.te})\n")
         f.write(f"# at n = 0.02 N(0,1) (PCG64 seed {N_SEED}, mean removed); "
                 f"atoms sampled with seed {SAMPLE_SEED}\n")
-        f.write("# D = 2 f(H[n]) at fixed electron number (Section IV.B, Eq. 36), net\n")
-        f.write("# Mulliken charges (Section VI)\n")
+        f.write("# D = 2 f(H[n]) at fixed electron number (Section IV.B, Eq. 36); mu;\n")
+        f.write("# Omega = Tr[H0 D] + (2q - n)^T Gamma n / 2 + E_rep - Te S and its parts\n")
+        f.write("# (Eqs. 35, 37, 38); per sampled atom: net Mulliken charge q (Section VI),\n")
+        f.write(f"# the canonical response dq/dlambda along the unit direction v1 (N(0,1)\n")
+        f.write(f"# with PCG64 seed {DIR_SEEDS[0]}, normalised; Section V.B), forces Fx Fy Fz\n")
         f.write(SUBSTITUTION)
         f.write(f"mu {ref.mu:.17e}\n")
+        for k in ("omega", "e_band", "e_coul", "e_rep", "te_s"):
+            f.write(f"{k} {en[k]:.17e}\n")
+        f.write("# atom q dq_v1 Fx Fy Fz\n")
         for a in atoms:
-            f.write(f"{a} {ref.q[a]:.17e}\n")
+            vals = [ref.q[a], dq[a], F[a, 0], F[a, 1], F[a, 2]]
+            f.write(f"{a} " + " ".join(f"{v:.17e}" for v in vals) + "\n")
     print("wrote", path)
+
+
+def read_sample(name, n_orbitals):
+    """(scalars dict, sampled atom indices, per-atom array (n, 5)) of a
+    sample file."""
+    scal, atoms, rows = {}, [], []
+    for line in open(sample_path(name, n_orbitals)):
+        if line.startswith("#"):
+            continue
+        parts = line.split()
+        if len(parts) == 2:
+            scal[parts[0]] = float(parts[1])
+        else:
+            atoms.append(int(parts[0]))
+            rows.append([float(x) for x in parts[1:]])
+    return scal, np.array(atoms), np.array(rows)
 
 
 def full_system(name):

@@ -306,57 +306,53 @@ def _golden(name, n_orbitals):
                                                   os.path.join(here, "make_sample.py"))
     gen = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(gen)
-    mu, atoms, q = None, [], []
-    for line in open(gen.sample_path(name, n_orbitals)):
-        if line.startswith("#"):
-            continue
-        a, v = line.split()
-        if a == "mu":
-            mu = float(v)
-        else:
-            atoms.append(int(a))
-            q.append(float(v))
-    return gen, mu, np.array(atoms), np.array(q)
+    scal, atoms, rows = gen.read_sample(name, n_orbitals)
+    return gen, scal, atoms, rows
+
+
+def _large_sample_check(P, name, n_orbitals, scf_tol):
+    """Charges and chemical potential of the solve at the stored n, then the
+    forces, free energy and one canonical response of the MD state at that
+    n, against the oracle's stored sample.  Bounds as at N = 4096: charges
+    1e-8 (8x the 1e-9 truncation target, rounded up), mu 1e-9, forces 1e-5,
+    relative free energy 1e-8, the response 1e-3 relative (split products)."""
+    gen, scal, atoms, rows = _golden(name, n_orbitals)
+    s = make_system(name)
+    n = gen.charge_vector(s.n_atoms)
+    g = P.XLBOMD(s, precision=P.MIXED_BF16X3, scf_tol=scf_tol)
+    q, rep = g.solve(n)
+    g.set_state(n_hist=np.tile(n, (s.kmax + 1, 1)))
+    F, e = g.forces()
+    v = gen.unit_direction(s.n_atoms, gen.DIR_SEEDS[0])
+    dq = g.response(v[None, :])[0]
+    g.close()
+    err = dict(q=np.abs(q[atoms] - rows[:, 0]).max(), mu=abs(rep["mu"] - scal["mu"]),
+               F=np.abs(F[atoms] - rows[:, 2:5]).max(),
+               omega=abs(e["omega"] - scal["omega"]) / abs(scal["omega"]),
+               resp=np.abs(dq[atoms] - rows[:, 1]).max() / np.abs(rows[:, 1]).max())
+    print(f"N={n_orbitals} MIXED_BF16X3, {rep['foe_levels']} levels vs stored oracle sample:",
+          {k: f"{x:.2e}" for k, x in err.items()})
+    bounds = dict(q=1e-8, mu=1e-9, F=1e-5, omega=1e-8, resp=1e-3)
+    for k, b in bounds.items():
+        assert err[k] < b, (k, err[k], b)
 
 
 def test_small_gap_workload_at_n8192(P):
     """The small-gap workload (2048 atoms x 4 orbitals, N = 8192, T_e = 0.02,
     7 levels) at a fixed n in the headline precision, against the oracle's
-    charges on a seeded sample of 128 atoms and its chemical potential, both
-    stored by a script that runs the oracle alone.  The bound is the one of
-    the N = 4096 case: 8 times the 1e-9 truncation target per atom, rounded
-    up to 1e-8."""
-    gen, mu_ref, atoms, q_ref = _golden("c3", 8192)
-    s = make_system("c3")
-    n = gen.charge_vector(s.n_atoms)
-    g = P.XLBOMD(s, precision=P.MIXED_BF16X3, scf_tol=1e-5)
-    q, rep = g.solve(n)
-    g.close()
-    err = np.abs(q[atoms] - q_ref).max()
-    print(f"N=8192 MIXED_BF16X3, {rep['foe_levels']} levels: sampled charges vs oracle "
-          f"{err:.2e}, mu {rep['mu']:.12f} vs {mu_ref:.12f}")
-    assert err < 1e-8
-    assert abs(rep["mu"] - mu_ref) < 1e-9
-
+    values on a seeded sample of 128 atoms (charges, forces, one response),
+    its chemical potential and free energy, all stored by a script that runs
+    the oracle alone."""
+    _large_sample_check(P, "c3", 8192, 1e-5)
 
 
 def test_random_packing_workload_at_n16384(P):
     """The largest workload (4096 randomly packed atoms x 4 orbitals,
     N = 16384, irregular neighbour counts) at a fixed n in the headline
-    precision, against the oracle's stored sample of 128 atoms and its
-    chemical potential; the bound is the one of the N = 4096 case.  A loose
-    initial SCF keeps the test short: the solve at n does not depend on it."""
-    gen, mu_ref, atoms, q_ref = _golden("c5", 16384)
-    s = make_system("c5")
-    n = gen.charge_vector(s.n_atoms)
-    g = P.XLBOMD(s, precision=P.MIXED_BF16X3, scf_tol=1e-3)
-    q, rep = g.solve(n)
-    g.close()
-    err = np.abs(q[atoms] - q_ref).max()
-    print(f"N=16384 MIXED_BF16X3, {rep['foe_levels']} levels: sampled charges vs oracle "
-          f"{err:.2e}, mu {rep['mu']:.12f} vs {mu_ref:.12f}")
-    assert err < 1e-8
-    assert abs(rep["mu"] - mu_ref) < 1e-9
+    precision, against the oracle's stored sample of 128 atoms, its
+    chemical potential and free energy.  A loose initial SCF keeps the test
+    short: the solve at n does not depend on it."""
+    _large_sample_check(P, "c5", 16384, 1e-3)
 
 
 def test_energy_conservation_split_path_c1(P):

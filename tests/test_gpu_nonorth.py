@@ -197,3 +197,38 @@ def test_nonorth_checkpoint_resumes_bit_for_bit(gpu):
     print(f"resumed vs original: max state diff {d:.1e}, charges {np.abs(qa - qb).max():.1e}")
     assert d == 0.0 and np.array_equal(qa, qb)
     assert ra["e_total"] == rb["e_total"]
+
+
+def test_nonorth_dimer_closed_form_on_the_gpu(gpu):
+    """The two-atom closed form of the oracle's pins, through the GPU path:
+    eigenvalues (e +- t)/(1 +- s), mu halfway, Mulliken charges 0, band
+    energy and the force along the bond with its Pulay part."""
+    import math
+    r, te = 1.7, 0.2
+    pos = np.array([[0.0, 0.0, 0.0], [r, 0.0, 0.0]])
+    s = make_system("c1").replace(
+        n_atoms=2, pos=pos, vel=np.zeros((2, 3)), mass=np.ones(2),
+        onsite=np.array([-0.2]), onsite_jitter=np.zeros(2),
+        hop_block=np.array([[-1.0]]), hop_decay=1.0, hop_cutoff=4.0,
+        taper_width=0.5, hubbard_u=np.array([1.0, 1.0]), n_electrons=2.0,
+        te=te, rep_a=0.0, rank=1, overlap_block=np.array([[0.3]]), overlap_decay=0.8)
+    e, t, so = -0.2, -math.exp(-r), 0.3 * math.exp(-r / 0.8)
+    ep, em = (e + t) / (1 + so), (e - t) / (1 - so)
+    mu = 0.5 * (ep + em)
+    fp = 1.0 / (1.0 + math.exp((ep - mu) / te))
+    fm = 1.0 / (1.0 + math.exp((em - mu) / te))
+    dt, ds = -t, -so / 0.8
+    dep = (dt * (1 + so) - (e + t) * ds) / (1 + so) ** 2
+    dem = (-dt * (1 - so) + (e - t) * ds) / (1 - so) ** 2
+    f_bond = -2.0 * (fp * dep + fm * dem)
+    g = gpu.XLBOMD(s, precision=gpu.FP64, scf_tol=1e-12)
+    g.set_state(n_hist=np.zeros((s.kmax + 1, 2)))
+    F, en = g.forces()
+    n, q = g.charges()
+    g.close()
+    print(f"dimer: q {q}, mu {en['mu']:.12f} ({mu:.12f}), F_x {F[:, 0]} ({-f_bond:.12f}), "
+          f"e_band {en['e_band']:.12f} ({2 * (fp * ep + fm * em):.12f})")
+    assert np.abs(q).max() < 1e-10
+    assert abs(en["mu"] - mu) < 1e-9
+    assert abs(en["e_band"] - 2 * (fp * ep + fm * em)) < 1e-10
+    assert abs(F[0, 0] + f_bond) < 1e-10 and abs(F[1, 0] - f_bond) < 1e-10
