@@ -258,13 +258,21 @@ __global__ __launch_bounds__(BS_T) void gemm_bs_fixup_kernel(SplitArgs p, int nt
 
 // ---------------------------------------------------------------------------
 // Wide variant: 256 x 128 workgroup tile, one workgroup of 8 waves per CU
-// (two per SIMD; 96 KB of LDS), used when n % 256 == 0.  Waves in 4 rows x
-// 2 columns of 64 x 64 (4 x 4 accumulator blocks, 48 MFMAs per 32-wide
-// k-tile).  The k loop is software-pipelined three deep: while a wave runs
-// the MFMAs of k-tile t from registers, it reads the fragments of t + 1
-// from LDS into a second register set, stores t + 2 (fetched from global
-// memory one iteration earlier) into the LDS buffer t has vacated and
-// issues the global loads of t + 3, with one barrier per k-tile.  Tiles of a
+// (two per SIMD), used when n % 256 == 0.  Waves in 4 rows x 2 columns of
+// 64 x 64 (4 x 4 accumulator blocks, 48 MFMAs per 32-wide k-tile).  The
+// operand tiles go from global memory straight into LDS
+// (global_load_lds_dwordx4: lane l of a wave writes the 16 bytes it fetched
+// at M0 + 16 l, so each load instruction of a wave fills one contiguous 1 KB
+// run of LDS): no staging registers and no LDS store instructions.  The
+// swizzle of a row's four 16-byte chunks is applied on the fetch side (LDS
+// slot s of row r receives chunk s ^ swz(r)).  Three k-tile buffers of
+// 48 KB: during step t the waves run the MFMAs of k-tile t from registers,
+// read the fragments of t + 1 from LDS into a second register set and issue
+// the loads of t + 3 into the buffer t vacated; a step ends when this wave's
+// loads of t + 2 have landed (each wave waits for its own, then the barrier
+// makes all of them visible), so a load has two steps to arrive.  The
+// barrier is a bare s_barrier with explicit waits: the workgroup fence of
+// __syncthreads would also wait for the loads of t + 3.  Tiles of a
 // symmetric product: in 256-row block bi, the 128-column blocks bj >= 2 bi.
 // ---------------------------------------------------------------------------
 constexpr int BW_NTH = 512;
@@ -319,15 +327,6 @@ struct BwFrag {
     bf16x8 ah[4], al[4], bh[4], bl[4];
 };
 
-// Epilogue of a whole 256 x 128 tile of a symmetric product with a split
-// output.  The elements on or above the diagonal go out from the
-// accumulator layout as in epilogue_split_at; their mirror images, which
-// written the same way would be 2-byte stores 2 ld bytes apart, are staged
-// in LDS (stg: 64 x 129 floats, the tile's k-tile buffers, free after the
-// k loop) one 64-row band at a time and written as rows of the transposed
-// band: four consecutive elements per lane, one 8-byte store per plane.
-// The mirror gets the same FP32 value, so the output is the same bit for
-// bit.  Called by every thread of the workgroup (it has barriers).
 // Epilogue of a whole 256 x 128 tile of a symmetric product with a split
 // output.  Every element on or above the diagonal is written from the
 // accumulator layout as in epilogue_split_at, and its FP32 value replaces
@@ -415,16 +414,35 @@ __device__ __forceinline__ void bw_sym_epilogue(const SplitArgs &p, long bz, int
     }
 }
 
+struct BwTile {
+    u32x4 a[2][BW_M][4];   // A planes (hi, lo): 256 rows x 32 k
+    u32x4 b[2][GT][4];     // B planes: 128 rows x 32 k
+};
+constexpr int BW_NBUF = 3;
+
+// s_waitcnt vmcnt(VM) lgkmcnt(0) (expcnt not waited on)
+template <int VM> __device__ __forceinline__ void wait_vm_lgkm0() {
+    static_assert(VM >= 0 && VM < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((VM & 15) | ((VM >> 4) << 14) | (7 << 4));
+}
+// barrier without a memory fence; the empty asm statements keep the
+// compiler from moving LDS accesses across it
+__device__ __forceinline__ void bare_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 template <bool SYM, bool HI>
 __global__ __launch_bounds__(BW_NTH, 1) void gemm_bw_kernel(SplitArgs p, int ntiles, int nfull,
-                                                         int nsplit, int per_xcd) {
+                                                          int nsplit, int per_xcd) {
     if (p.skip && *p.skip) return;   // skipped launch (device flag)
     using acc_t = f32x4;
     constexpr int NTH = BW_NTH;
     constexpr int NPL = HI ? 1 : 2;                    // planes loaded (HI: hi only)
-    constexpr int NA = NPL * 1024 / NTH, NB = NPL * 512 / NTH;   // 16-byte chunks per thread
-    __shared__ __attribute__((aligned(16))) u32x4 As[2][2][BW_M][4];
-    __shared__ __attribute__((aligned(16))) u32x4 Bs[2][2][GT][4];
+    constexpr int NA = NPL * 1024 / NTH, NB = NPL * 512 / NTH;   // loads per thread per k-tile
+    constexpr int ND = NA + NB;
+    __shared__ __attribute__((aligned(1024))) BwTile Lt[BW_NBUF];
 
     const int b = blockIdx.x;
     const int ntail = ntiles - nfull;
@@ -452,7 +470,8 @@ __global__ __launch_bounds__(BW_NTH, 1) void gemm_bw_kernel(SplitArgs p, int nti
     const int ld = p.ld;
     const long pl = p.pl;
     const int i0 = bi * BW_M, j0 = bj * GT;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wid >> 1, wc = wid & 1;
     const int fr = lane >> 4, fc = lane & 15;
 
@@ -467,59 +486,50 @@ __global__ __launch_bounds__(BW_NTH, 1) void gemm_bw_kernel(SplitArgs p, int nti
     const int kt0 = (int)((long)nktot * split / ns);
     const int kt1 = (int)((long)nktot * (split + 1) / ns);
 
-    // A: 2 planes x 256 rows x 4 chunks; B: 2 x 128 x 4 (chunk idx = tid + NTH v)
-    u32x4 ra[NA], rb[NB];
-    auto gload = [&](int kt) {
+    // k-tile kt into buffer buf: load v of wave wid fills the 1 KB run
+    // (8 v + wid) of the A planes (v < NA) or of the B planes
+    auto dload = [&](int kt, int buf) {
         const bool second = kt >= nk1;
         const uint16_t *Ap = second ? A1 : A0;
         const uint16_t *Bp = second ? B1 : B0;
         const int kb = (second ? kt - nk1 : kt) * B3K;
+        char *la = reinterpret_cast<char *>(&Lt[buf].a[0][0][0]);
+        char *lb = reinterpret_cast<char *>(&Lt[buf].b[0][0][0]);
 #pragma unroll
         for (int v = 0; v < NA; ++v) {
             const int idx = tid + NTH * v;
-            const int pln = idx >> 10, row = (idx >> 2) & (BW_M - 1), ch = idx & 3;
-            ra[v] = *reinterpret_cast<const u32x4 *>(Ap + pln * pl + kb + 8 * ch +
-                                                     (long)(i0 + row) * ld);
+            const int pln = idx >> 10, row = (idx >> 2) & (BW_M - 1);
+            const int ch = (idx & 3) ^ swz(row);
+            __builtin_amdgcn_global_load_lds(
+                (const void __attribute__((address_space(1))) *)(Ap + pln * pl + kb + 8 * ch +
+                                                                (long)(i0 + row) * ld),
+                (void __attribute__((address_space(3))) *)(la + (8 * v + wid) * 1024), 16, 0, 0);
         }
 #pragma unroll
         for (int v = 0; v < NB; ++v) {
             const int idx = tid + NTH * v;
-            const int pln = idx >> 9, row = (idx >> 2) & (GT - 1), ch = idx & 3;
-            rb[v] = *reinterpret_cast<const u32x4 *>(Bp + pln * pl + kb + 8 * ch +
-                                                     (long)(j0 + row) * ld);
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int v = 0; v < NA; ++v) {
-            const int idx = tid + NTH * v;
-            const int pln = idx >> 10, row = (idx >> 2) & (BW_M - 1), ch = idx & 3;
-            As[buf][pln][row][ch ^ swz(row)] = ra[v];
-        }
-#pragma unroll
-        for (int v = 0; v < NB; ++v) {
-            const int idx = tid + NTH * v;
-            const int pln = idx >> 9, row = (idx >> 2) & (GT - 1), ch = idx & 3;
-            Bs[buf][pln][row][ch ^ swz(row)] = rb[v];
+            const int pln = idx >> 9, row = (idx >> 2) & (GT - 1);
+            const int ch = (idx & 3) ^ swz(row);
+            __builtin_amdgcn_global_load_lds(
+                (const void __attribute__((address_space(1))) *)(Bp + pln * pl + kb + 8 * ch +
+                                                                (long)(j0 + row) * ld),
+                (void __attribute__((address_space(3))) *)(lb + (8 * v + wid) * 1024), 16, 0, 0);
         }
     };
     auto fread = [&](int buf, BwFrag &f) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = wr * 64 + q * 16 + fc, c = fr ^ swz(r);
-            f.ah[q] = __builtin_bit_cast(bf16x8, As[buf][0][r][c]);
-            if (!HI) f.al[q] = __builtin_bit_cast(bf16x8, As[buf][1][r][c]);
+            f.ah[q] = __builtin_bit_cast(bf16x8, Lt[buf].a[0][r][c]);
+            if (!HI) f.al[q] = __builtin_bit_cast(bf16x8, Lt[buf].a[1][r][c]);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = wc * 64 + q * 16 + fc, c = fr ^ swz(r);
-            f.bh[q] = __builtin_bit_cast(bf16x8, Bs[buf][0][r][c]);
-            if (!HI) f.bl[q] = __builtin_bit_cast(bf16x8, Bs[buf][1][r][c]);
+            f.bh[q] = __builtin_bit_cast(bf16x8, Lt[buf].b[0][r][c]);
+            if (!HI) f.bl[q] = __builtin_bit_cast(bf16x8, Lt[buf].b[1][r][c]);
         }
     };
-    // one of the three split terms (lo.hi, hi.lo, hi.hi) over the 4 x 4
-    // blocks: the three products into one accumulator are 16 instructions
-    // apart
     auto mfma = [&](const bf16x8 (&a)[4], const bf16x8 (&bb)[4]) {
 #pragma unroll
         for (int x = 0; x < 4; ++x)
@@ -527,25 +537,18 @@ __global__ __launch_bounds__(BW_NTH, 1) void gemm_bw_kernel(SplitArgs p, int nti
             for (int y = 0; y < 4; ++y)
                 acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], bb[y], acc[x][y], 0, 0, 0);
     };
-    // k-tile t lives in LDS buffer (t - kt0) & 1.  One step: fragments of t
-    // in `cur`; t + 1 stored and visible; t + 2 in flight in ra / rb.  The
-    // step is branch-free so that one scheduling region holds it: near the
-    // end of the range the fragment read and LDS store handle stale data that
-    // is never used, and the global load repeats the last k-tile.  The LDS
-    // instructions are spread between the MFMAs (one read or store per two
-    // MFMAs): issued in a burst after the barrier they fill the LDS queue
-    // and hold up the MFMAs behind them.
-    // HI: 8 fragment reads and 16 MFMAs per k-tile, one read per MFMA
+    // One step, branch-free: near the end of the range
+    // the loads repeat the last k-tile into the vacated buffer and the
+    // fragment read takes stale data that is never used.
     constexpr int NMF = HI ? 16 : 48, NRD = HI ? 8 : 16, MPR = HI ? 1 : 2;
     auto step = [&](int kt, const BwFrag &cur, BwFrag &nxt) {
-        const int buf = (kt - kt0) & 1;
-        fread(buf ^ 1, nxt);
+        const int r = kt - kt0;
+        fread((r + 1) % BW_NBUF, nxt);
         if (!HI) {
             mfma(cur.al, cur.bh);
             mfma(cur.ah, cur.bl);
         }
-        sstore(buf);                        // every wave read t's fragments before the last barrier
-        gload(min(kt + 3, kt1 - 1));
+        dload(min(kt + 3, kt1 - 1), r % BW_NBUF);   // every wave read t's fragments before the last barrier
         mfma(cur.ah, cur.bh);
 #pragma unroll
         for (int i = 0; i < NRD; ++i) {
@@ -553,32 +556,33 @@ __global__ __launch_bounds__(BW_NTH, 1) void gemm_bw_kernel(SplitArgs p, int nti
             __builtin_amdgcn_sched_group_barrier(0x008, MPR, 0); // MFMA
         }
 #pragma unroll
-        for (int i = 0; i < NA + NB; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // LDS write
-            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // global read
+        for (int i = 0; i < ND; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // direct load
             __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // MFMA
         }
-        __builtin_amdgcn_sched_group_barrier(0x008, NMF - NRD * MPR - 2 * (NA + NB), 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, NMF - NRD * MPR - 2 * ND, 0);
         __builtin_amdgcn_sched_barrier(0);
-        __syncthreads();
+        wait_vm_lgkm0<ND>();        // this wave's loads of t + 2 landed, t + 1 read
+        bare_barrier();
     };
 
     BwFrag f0, f1;
-    gload(kt0);
-    sstore(0);
-    if (kt0 + 1 < kt1) gload(kt0 + 1);
-    __syncthreads();
+    dload(kt0, 0);
+    dload(min(kt0 + 1, kt1 - 1), 1);
+    dload(min(kt0 + 2, kt1 - 1), 2);
+    wait_vm_lgkm0<2 * ND>();        // k-tile kt0
+    bare_barrier();
     fread(0, f0);
-    if (kt0 + 1 < kt1) sstore(1);
-    if (kt0 + 2 < kt1) gload(kt0 + 2);
-    __syncthreads();
+    wait_vm_lgkm0<ND>();            // k-tile kt0 + 1; f0 read
+    bare_barrier();
     for (int kt = kt0; kt < kt1; kt += 2) {
         step(kt, f0, f1);
         if (kt + 1 < kt1) step(kt + 1, f1, f0);
     }
+    wait_vm_lgkm0<0>();             // no load may land in the staging area below
+    bare_barrier();
 
     if (part) {
-        // block g = 4 x + y of thread tid at [(g * NTH + tid) * 4]
         acc_t *wp = reinterpret_cast<acc_t *>(p.ws + ((long)bz * ntail * nsplit + w) * BW_TILE) + tid;
 #pragma unroll
         for (int x = 0; x < 4; ++x)
@@ -589,7 +593,7 @@ __global__ __launch_bounds__(BW_NTH, 1) void gemm_bw_kernel(SplitArgs p, int nti
     if constexpr (SYM) {
         if (p.C && !p.Cd) {
             bw_sym_epilogue(p, bz, i0, j0, wr, wc, fr, fc, tid, acc,
-                            reinterpret_cast<float *>(&As[0][0][0][0]));
+                            reinterpret_cast<float *>(&Lt[0].a[0][0][0]));
             return;
         }
     }
