@@ -402,18 +402,98 @@ __global__ __launch_bounds__(1024) void max_count_kernel(int nat, const int *cnt
     }
 }
 
-// C = alpha Y B + beta X + beta2 X2 over the whole padded ld x ld array
-// (rows of padding zero), for the seed Y with its neighbour-block sparsity
-// and dense B; optional FP32 (Cf) and split (Cs, planes pl apart) copies of
-// C.  One workgroup per (atom, 256 columns), each thread accumulating the NO
-// rows of one column in FP64.  The Y blocks are the same for the whole
-// workgroup and are read with scalar loads; the optional column scale of Y
-// is applied to the NO loaded values of B instead.  Vector registers then
-// hold only B values and accumulators, and the neighbour loop, unrolled
-// four times, keeps 4 NO loads of B per wave in flight.
+// Atoms per workgroup of the sparse-dense seed product: 16 rows of Y.
+template <int NO> struct SpmmGroup {
+    static constexpr int G = NO >= 16 ? 1 : 16 / NO;
+};
+inline int spmm_group(int no) { return no >= 16 ? 1 : 16 / no; }
+
+// Per group g of G consecutive atoms: the union of their neighbour lists in
+// ascending atom order, gnb[g * gstride + e] for e < gcnt[g], and for each
+// entry the G-bit mask gmask[...] of the group's atoms that have it as a
+// neighbour (bit i: atom g G + i).  The union is collected in a bitmask over
+// all atoms in dynamic LDS (ceil(nat / 32) words), compacted in order, and
+// each list entry then finds its place by binary search.  256 threads per
+// group; G <= 16, gstride >= G NB_MAX.
+__global__ __launch_bounds__(256) void group_union_kernel(int nat, int G, const int *nb,
+                                                          const int *cnt, int *gnb,
+                                                          unsigned *gmask, int *gcnt, int gstride) {
+    extern __shared__ unsigned bits[];
+    __shared__ int un[16 * NB_MAX];
+    __shared__ unsigned msk[16 * NB_MAX];
+    __shared__ int part[256];
+    __shared__ int total;
+    const int g = blockIdx.x, t = threadIdx.x;
+    const int W = (nat + 31) >> 5;
+    const int I0 = g * G, ng = min(G, nat - I0);
+    for (int w = t; w < W; w += 256) bits[w] = 0u;
+    for (int e = t; e < 16 * NB_MAX; e += 256) msk[e] = 0u;
+    __syncthreads();
+    auto count = [&](int I) {
+        const int c = cnt[I];
+        return (c < 0 || c > NB_MAX) ? NB_MAX : c;
+    };
+    for (int i = 0; i < ng; ++i) {
+        const int c = count(I0 + i);
+        for (int e = t; e < c; e += 256) {
+            const int J = nb[(I0 + i) * NB_MAX + e];
+            atomicOr(&bits[J >> 5], 1u << (J & 31));
+        }
+    }
+    __syncthreads();
+    const int per = (W + 255) / 256, w0 = min(W, t * per), w1 = min(W, w0 + per);
+    int own = 0;
+    for (int w = w0; w < w1; ++w) own += __popc(bits[w]);
+    part[t] = own;
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int k = 0; k < 256; ++k) {
+            const int v = part[k];
+            part[k] = run;
+            run += v;
+        }
+        total = run;
+    }
+    __syncthreads();
+    int o = part[t];
+    for (int w = w0; w < w1; ++w) {
+        unsigned m = bits[w];
+        while (m) {
+            const int k = __ffs(m) - 1;
+            m &= m - 1;
+            un[o++] = w * 32 + k;
+        }
+    }
+    __syncthreads();
+    const int tot = total;
+    for (int i = 0; i < ng; ++i) {
+        const int c = count(I0 + i);
+        for (int e = t; e < c; e += 256) {
+            const int J = nb[(I0 + i) * NB_MAX + e];
+            int lo = 0, hi = tot - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (un[mid] < J) lo = mid + 1;
+                else hi = mid;
+            }
+            atomicOr(&msk[lo], 1u << i);
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < tot; e += 256) {
+        gnb[(long)g * gstride + e] = un[e];
+        gmask[(long)g * gstride + e] = msk[e];
+    }
+    if (t == 0) gcnt[g] = tot;
+}
+
 template <typename T> struct SpmmArgs {
     int nat, ld;
-    const int *nb, *cnt;
+    // neighbour-list unions of the atom groups (group_union_kernel)
+    const int *gnb = nullptr, *gcnt = nullptr;
+    const unsigned *gmask = nullptr;
+    int gstride = 0;
     const T *Y, *B, *X = nullptr, *X2 = nullptr;
     T *C = nullptr;
     float *Cf = nullptr;
@@ -426,53 +506,125 @@ template <typename T> struct SpmmArgs {
     long su = 0, sC = 0, sCs = 0;
     const int *skip = nullptr;          // device flag: skip the launch while set
 };
-template <typename T, int NO, bool SCALE>
-__device__ __forceinline__ void spmm_rows(const T *__restrict__ Yr, const T *__restrict__ B,
-                                          const int *__restrict__ nl, const double *__restrict__ u,
-                                          int c, int ld, int col, double *acc) {
+// C = alpha Y B + beta X + beta2 X2 over the whole padded ld x ld array
+// (rows of padding zero), for the seed Y with its neighbour-block sparsity
+// and dense B; optional FP32 (Cf) and split (Cs, planes pl apart) copies of
+// C.  One workgroup per (group of G atoms, 256 columns), each thread
+// accumulating the G NO rows of one column in FP64.  The workgroup walks
+// the union of the group's neighbour lists once, so each row block of B is
+// fetched once per group instead of once per atom (the lists of nearby
+// atoms overlap: on a jittered cubic lattice four consecutive atoms with 24
+// neighbours each have 48 distinct ones).  The group's blocks of Y for 32
+// union entries at a time are gathered into LDS by the whole workgroup and
+// read back as broadcasts; the B rows of four entries are loaded before
+// any of them is used; the membership mask skips the blocks of Y that are
+// zero.  For every atom the terms are added in ascending neighbour order.
+// The optional column scale of Y is applied to the loaded values of B.
+constexpr int SPMM_CH = 32;    // union entries per LDS chunk
+template <typename T, int NO, bool SCALE, int E>
+__device__ __forceinline__ void spmm_group_step(const double (*ys)[SpmmGroup<NO>::G * NO][NO],
+                                                const T *__restrict__ B,
+                                                const int *__restrict__ nl,
+                                                const unsigned *__restrict__ ml,
+                                                const double *__restrict__ u, int ld, int col,
+                                                bool live, double (&acc)[SpmmGroup<NO>::G][NO]) {
+    constexpr int G = SpmmGroup<NO>::G;
+    int J[E];
+    unsigned m[E];
+    double bv[E][NO];
 #pragma unroll
-    for (int a = 0; a < NO; ++a) acc[a] = 0.0;
-#pragma unroll 4
-    for (int e = 0; e < c; ++e) {
-        const int J = nl[e];
-        const T *brow = B + (long)J * NO * ld + col;
-        double bv[NO];
+    for (int q = 0; q < E; ++q) {
+        J[q] = nl[q];
+        m[q] = ml[q];
+    }
+    // all E NO loads of B issued before any use
 #pragma unroll
-        for (int b = 0; b < NO; ++b) bv[b] = (double)brow[(long)b * ld];
-        if (SCALE) {
+    for (int q = 0; q < E; ++q)
 #pragma unroll
-            for (int b = 0; b < NO; ++b) bv[b] *= u[J * NO + b];
+        for (int b = 0; b < NO; ++b)
+            bv[q][b] = live ? (double)B[((long)J[q] * NO + b) * ld + col] : 0.0;
+    if (SCALE) {
+#pragma unroll
+        for (int q = 0; q < E; ++q)
+#pragma unroll
+            for (int b = 0; b < NO; ++b) bv[q][b] *= u[J[q] * NO + b];
+    }
+#pragma unroll
+    for (int q = 0; q < E; ++q)
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            if (!(m[q] & (1u << i))) continue;
+#pragma unroll
+            for (int a = 0; a < NO; ++a)
+#pragma unroll
+                for (int b = 0; b < NO; ++b) acc[i][a] += ys[q][i * NO + a][b] * bv[q][b];
         }
+}
+template <typename T, int NO, bool SCALE>
+__device__ __forceinline__ void spmm_group_rows(double (*ys)[SpmmGroup<NO>::G * NO][NO],
+                                                const T *__restrict__ Yg, int nrow,
+                                                const T *__restrict__ B,
+                                                const int *__restrict__ nl,
+                                                const unsigned *__restrict__ ml,
+                                                const double *__restrict__ u, int c, int ld,
+                                                int col, double (&acc)[SpmmGroup<NO>::G][NO]) {
+    constexpr int G = SpmmGroup<NO>::G, R = G * NO;
 #pragma unroll
-        for (int a = 0; a < NO; ++a)
+    for (int i = 0; i < G; ++i)
 #pragma unroll
-            for (int b = 0; b < NO; ++b) acc[a] += (double)Yr[(long)a * ld + J * NO + b] * bv[b];
+        for (int a = 0; a < NO; ++a) acc[i][a] = 0.0;
+    const bool live = col < ld;
+    for (int e0 = 0; e0 < c; e0 += SPMM_CH) {
+        const int ce = min(SPMM_CH, c - e0);
+        for (int t = threadIdx.x; t < ce * R * NO; t += blockDim.x) {
+            const int q = t / (R * NO), r = (t / NO) % R, b = t % NO;
+            ys[q][r][b] = r < nrow ? (double)Yg[(long)r * ld + nl[e0 + q] * NO + b] : 0.0;
+        }
+        __syncthreads();
+        int e = 0;
+        for (; e + 4 <= ce; e += 4)
+            spmm_group_step<T, NO, SCALE, 4>(ys + e, B, nl + e0 + e, ml + e0 + e, u, ld, col,
+                                             live, acc);
+        for (; e < ce; ++e)
+            spmm_group_step<T, NO, SCALE, 1>(ys + e, B, nl + e0 + e, ml + e0 + e, u, ld, col,
+                                             live, acc);
+        __syncthreads();
     }
 }
 template <typename T, int NO>
 __global__ __launch_bounds__(256) void spmm_seed_kernel(SpmmArgs<T> p) {
+    constexpr int G = SpmmGroup<NO>::G;
     if (p.skip && *p.skip) return;   // skipped launch (device flag)
-    const int I = blockIdx.y;
+    const int g = blockIdx.y;
     const long bz = blockIdx.z;
     const int ld = p.ld;
+    // every thread stays for the barriers; columns past ld neither load nor store
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= ld) return;
-    const int c = p.cnt[I];
+    const int I0 = g * G;
+    const int nrow = min(G, p.nat - I0) * NO;
+    const int c = p.gcnt[g];
+    const int *nl = p.gnb + (long)g * p.gstride;
+    const unsigned *ml = p.gmask + (long)g * p.gstride;
     const double *u = p.u ? p.u + bz * p.su : nullptr;
-    const T *Yr = p.Y + (long)I * NO * ld;     // the atom's NO rows of Y
-    const int *nl = p.nb + I * NB_MAX;
-    double acc[NO];
-    if (u) spmm_rows<T, NO, true>(Yr, p.B, nl, u, c, ld, col, acc);
-    else spmm_rows<T, NO, false>(Yr, p.B, nl, u, c, ld, col, acc);
+    const T *Yg = p.Y + (long)I0 * NO * ld;      // the group's G NO rows of Y
+    __shared__ double ys[SPMM_CH][G * NO][NO];   // Y blocks of one chunk of the union
+    double acc[G][NO];
+    if (u) spmm_group_rows<T, NO, true>(ys, Yg, nrow, p.B, nl, ml, u, c, ld, col, acc);
+    else spmm_group_rows<T, NO, false>(ys, Yg, nrow, p.B, nl, ml, u, c, ld, col, acc);
+    if (col >= ld) return;
 #pragma unroll
-    for (int a = 0; a < NO; ++a) {
-        const long o = (long)(I * NO + a) * ld + col;
-        double v = p.alpha * acc[a];
-        if (p.X) v += p.beta * (double)p.X[o];
-        if (p.X2) v += p.beta2 * (double)p.X2[o];
-        if (p.C) p.C[bz * p.sC + o] = (T)v;
-        if (p.Cf) p.Cf[o] = (float)v;
-        if (p.Cs) put_split(p.Cs + bz * p.sCs, p.pl, o, (float)v);
+    for (int i = 0; i < G; ++i) {
+        if (I0 + i >= p.nat) break;
+#pragma unroll
+        for (int a = 0; a < NO; ++a) {
+            const long o = (long)((I0 + i) * NO + a) * ld + col;
+            double v = p.alpha * acc[i][a];
+            if (p.X) v += p.beta * (double)p.X[o];
+            if (p.X2) v += p.beta2 * (double)p.X2[o];
+            if (p.C) p.C[bz * p.sC + o] = (T)v;
+            if (p.Cf) p.Cf[o] = (float)v;
+            if (p.Cs) put_split(p.Cs + bz * p.sCs, p.pl, o, (float)v);
+        }
     }
 }
 

@@ -427,6 +427,12 @@ struct SysBase {
         A(scal, 64); A(cvec, 8);
         A(lz_v, N); A(lz_vp, N); A(lz_w, N); A(lz_v0, N); A(lz_ab, 2 * LZ_M);
         A(nbl, (size_t)nat * NB_MAX); A(nbc, nat);
+        sp_g = spmm_group(no);
+        sp_ng = ceil_div(nat, sp_g);
+        sp_gs = sp_g * NB_MAX;
+        if ((long)ceil_div(nat, 32) * 4 > 48 * 1024)
+            throw InvalidArg("more atoms than the neighbour-list union kernel supports (393216)");
+        A(gnb, (size_t)sp_ng * sp_gs); A(gmask, (size_t)sp_ng * sp_gs); A(gcnt, sp_ng);
         mcap = std::max(1, std::min(d.kernel_rank + d.kernel_otf, 16));
         A(V, (size_t)mcap * nat); A(W, (size_t)mcap * nat); A(Vprev, (size_t)mcap * nat);
         A(vtmp, nat); A(vin, (size_t)mcap * nat); A(qp, (size_t)mcap * nat); A(hb, (size_t)mcap * nat);
@@ -526,6 +532,20 @@ struct SysBase {
     // most NB_MAX neighbours and at most a quarter of all atoms
     int *nbl = nullptr, *nbc = nullptr;
     int nb_max = 0;
+    // unions of the neighbour lists of groups of sp_g consecutive atoms
+    // (sp_ng groups, sp_gs entries each) for the sparse-dense seed products
+    int *gnb = nullptr, *gcnt = nullptr;
+    unsigned *gmask = nullptr;
+    int sp_g = 1, sp_ng = 0, sp_gs = 0;
+    void neighbour_lists() {
+        hipLaunchKernelGGL(neighbours_kernel, dim3(nat), dim3(64), 0, st, md, nbl, nbc);
+        hipLaunchKernelGGL(group_union_kernel, dim3(sp_ng), dim3(256),
+                           ceil_div(nat, 32) * sizeof(unsigned), st, nat, sp_g,
+                           (const int *)nbl, (const int *)nbc, gnb, gmask, gcnt, sp_gs);
+        hipLaunchKernelGGL(max_count_kernel, dim3(1), dim3(1024), 0, st, nat, (const int *)nbc,
+                           scal + 10);
+        XL_LAUNCH_CHECK();
+    }
     bool sparse_seed() const {
         return !ov && nb_max > 0 && nb_max <= NB_MAX && 4 * nb_max <= nat;
     }
@@ -571,10 +591,7 @@ struct SysBase {
         XL_LAUNCH_CHECK();
         if (ov) overlap_prepare();
         else gershgorin();
-        hipLaunchKernelGGL(neighbours_kernel, dim3(nat), dim3(64), 0, st, md, nbl, nbc);
-        hipLaunchKernelGGL(max_count_kernel, dim3(1), dim3(1024), 0, st, nat, (const int *)nbc,
-                           scal + 10);
-        XL_LAUNCH_CHECK();
+        neighbour_lists();
         lanczos();
         XL_HIP(hipMemcpyAsync(hscal, scal + 8, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
         XL_HIP(hipMemcpyAsync(hscal + 16, lz_ab, 2 * LZ_M * sizeof(double),
@@ -1865,10 +1882,11 @@ template <typename TF, typename TR> struct Sys : SysBase {
     TR *ZL2s = nullptr;               // split copy of Z_L^2 (split path)
     TF *Y4f = nullptr;                // FP64 Y^4 of the sparse seed (when TF != TR)
     void spmm(SpmmArgs<TF> a, int nb = 1) {
-        a.nat = nat; a.ld = Np; a.nb = nbl; a.cnt = nbc;
+        a.nat = nat; a.ld = Np;
+        a.gnb = gnb; a.gcnt = gcnt; a.gmask = gmask; a.gstride = sp_gs;
         if (cur_skip) a.skip = cur_skip;
         if (nb > 1 && Np > N) throw InvalidArg("spmm: batched products need an unpadded matrix");
-        const dim3 g(ceil_div(Np, 256), nat, nb);
+        const dim3 g(ceil_div(Np, 256), sp_ng, nb);
         switch (no) {
 #define XL_SPMM(K) case K: hipLaunchKernelGGL((spmm_seed_kernel<TF, K>), g, dim3(256), 0, st, a); break;
             XL_SPMM(1) XL_SPMM(2) XL_SPMM(3) XL_SPMM(4) XL_SPMM(5) XL_SPMM(6) XL_SPMM(7) XL_SPMM(8)
@@ -2062,10 +2080,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
                            0, st, md, 1, ncur, vpot);
         XL_LAUNCH_CHECK();
         gershgorin();
-        hipLaunchKernelGGL(neighbours_kernel, dim3(nat), dim3(64), 0, st, md, nbl, nbc);
-        hipLaunchKernelGGL(max_count_kernel, dim3(1), dim3(1024), 0, st, nat, (const int *)nbc,
-                           scal + 10);
-        XL_LAUNCH_CHECK();
+        neighbour_lists();
         lanczos();
         hipLaunchKernelGGL(plan_interval_kernel, dim3(1), dim3(64), 0, st, (const double *)(scal + 8),
                            (const double *)lz_ab, LZ_M, nat, beta, plan.xmax, plan.sparse ? 1 : 0,
