@@ -6,7 +6,7 @@ matrix, no integrator coefficients): the oracle and the HIP library each
 build those themselves from the raw parameters returned here.
 """
 from .systems import (CONFIGS, System, make_system, lattice_system,
-                      serving_stream, with_overlap)
+                      packed_system, serving_stream, with_overlap)
 
 __all__ = ["CONFIGS", "System", "make_system", "lattice_system",
-           "serving_stream", "with_overlap"]
+           "packed_system", "serving_stream", "with_overlap"]

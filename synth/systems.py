@@ -243,6 +243,18 @@ def lattice_system(n_atoms: int, template: str = "c2", seed: int = 1,
                    overrides)
 
 
+def packed_system(n_atoms: int, template: str = "c5", seed: int = 1,
+                  **overrides) -> System:
+    """n_atoms randomly packed atoms at `template`'s density and minimum
+    distance, with its model: the large workload's geometry (irregular
+    neighbour counts, atoms in no spatial order) at any size."""
+    cfg = dict(CONFIGS[template])
+    rng = np.random.Generator(np.random.PCG64(seed))
+    side = (n_atoms / cfg["density"]) ** (1.0 / 3.0)
+    pos = _random_packing(rng, n_atoms, side, cfg["rmin"])
+    return _finish(f"{template}-packed{n_atoms}", cfg, rng, pos, n_atoms, overrides)
+
+
 def with_overlap(s: System, scale: float = 0.3) -> System:
     """The same system in a non-orthogonal basis: overlap block
     -scale * B / max|B| for the hopping block B (bonding hoppings are

@@ -7,7 +7,7 @@ stated in the test; the achieved values are printed.
 import numpy as np
 import pytest
 
-from synth import make_system, lattice_system
+from synth import make_system, lattice_system, packed_system
 from oracle import reference as R
 
 pytestmark = pytest.mark.gpu
@@ -399,3 +399,41 @@ def test_single_atom(gpu, tmpl, prec_name):
     assert np.abs(state["vel"] - vel).max() < 1e-12
     assert np.abs(state["n_hist"]).max() < qtol and np.abs(state["kr"]).max() < qtol
     g.close()
+
+
+def _eigh_rows(H):
+    w, V = np.linalg.eigh(H)
+    return w, np.ascontiguousarray(V.T)
+
+
+@pytest.mark.parametrize("no", [4, 3])
+def test_sparse_seed_random_packing_partial_group(gpu, no):
+    """The sparse-dense seed products walk the neighbour-list union of each
+    group of 16 / no consecutive atoms.  203 randomly packed atoms (the
+    large workload's geometry: irregular neighbour counts, atoms in no
+    spatial order, so the unions are irregular) leave a last group of
+    three atoms, and N = 812 (609) is padded to 896 (640).  FP64 and
+    MIXED_BF16X3 charges and one FP64 response against the oracle (numpy's
+    eigh in place of its Jacobi sweeps at this size)."""
+    s = packed_system(203, seed=11)
+    if no != 4:
+        s = _leading_orbitals(s, no)
+    assert 4 * _max_neighbours(s) <= s.n_atoms      # the sparse seed is taken
+    assert s.n_atoms % (16 // no) != 0              # a partial last group
+    m = R.Model(s)
+    n = _rand_n(s.n_atoms, 4)
+    el = R.electronic(m, s.pos, n, eig=_eigh_rows)
+    V = np.random.default_rng(9).standard_normal((1, s.n_atoms))
+    V /= np.linalg.norm(V)
+    ref = R.response(m, el, V[0])
+    for prec, tol_q, tol_r in ((gpu.FP64, 1e-8, 1e-6), (gpu.MIXED_BF16X3, 1e-8, 1e-3)):
+        g = gpu.XLBOMD(s, precision=prec, scf_tol=1e-9)
+        q, rep = g.solve(n)
+        dv = g.response(V)[0]
+        g.close()
+        dq = np.abs(q - el.q).max()
+        err = np.abs(dv - ref).max() / np.abs(ref).max()
+        print(f"packed 203 x {no}, precision {prec}: max|dq| {dq:.2e}, response rel err "
+              f"{err:.2e}, L={rep['foe_levels']}")
+        assert dq < tol_q
+        assert err < tol_r
