@@ -74,6 +74,8 @@ def _run(P, s, steps, precision, every=10, chunk=10, label="", scf_tol=1e-9):
                drift_all=float(abs(np.polyfit(t, et, 1)[0]) * t[-1]),
                rms_max=float(max(rms)), rms_mean=float(np.mean(rms)),
                rms_half=float(np.mean(rms[h:])), ranks=sorted(set(ranks)), q=q, F=F)
+    print(f"[{label}] E_tot every {every} steps, minus the first: "
+          + " ".join(f"{x - et[0]:+.4f}" for x in et), flush=True)
     print(f"[{label}] {steps} steps in {wall:.1f}s: E_tot range {out['e_range']:.2e} against "
           f"{out['e_exchange']:.1f} of kinetic energy exchanged; second half: trend "
           f"{out['drift_half']:.2e}, detrended std {out['fluct_half']:.2e}; whole run trend "
@@ -116,8 +118,11 @@ def test_c3_500_steps_and_split_vs_fp32(P):
 
 
 def test_c5_three_kernel_rebuilds(P):
+    """160 steps of the largest workload: three kernel rebuilds with
+    on-the-fly updates between them.  The energy is taken every 5 steps so
+    that the second-half trend is fitted to 16 samples."""
     s = make_system("c5")
-    out = _run(P, s, 160, P.MIXED_BF16X3, label="c5", scf_tol=1e-8)
+    out = _run(P, s, 160, P.MIXED_BF16X3, every=5, chunk=5, label="c5", scf_tol=1e-8)
     _no_drift(out)
     # rank 6 rebuilt at step 1 and every 50 steps, plus up to 10 on-the-fly
     # rank-1 updates in between
