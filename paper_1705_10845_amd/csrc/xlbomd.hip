@@ -2553,12 +2553,27 @@ template <typename TF, typename TR> struct Sys : SysBase {
         // below 1e-14 in the trace; q by Paterson-Stockmeyer: baby steps
         // W^0..W^s, then Horner in W^s over blocks of s coefficients
         const double *ZL = as64(Z[L], 2, 1.0);
-        double *Z2 = w64(3), *W = w64(4);
-        {
+        const double *Z2 = nullptr;
+        double *W = w64(4);
+        if constexpr (std::is_same<TF, double>::value) {
+            // the expansion's own FP64 Z_L^2, and W = T0^2 = 4 Z_0^2 = A_0 - I
+            // (A_0 over the padded array has a unit diagonal in the padding)
+            Z2 = ZL2;
+            if (L > 0) {
+                hipLaunchKernelGGL(add_diag_copy_kernel, dim3(ceil_div((long)mat(), 256)),
+                                   dim3(256), 0, st, Np, Np, (const double *)Ak[0], -1.0, W);
+                XL_LAUNCH_CHECK();
+            }
+        }
+        if (!Z2) {
+            double *z2 = w64(3);
             GemmArgs<double> b = a;
-            b.A0 = ZL; b.B0 = ZL; b.C = Z2;
+            b.A0 = ZL; b.B0 = ZL; b.C = z2;
             gemm(b, true, st);
-            b = a;
+            Z2 = z2;
+        }
+        if (!(std::is_same<TF, double>::value && L > 0)) {
+            GemmArgs<double> b = a;
             b.A0 = T0; b.B0 = T0; b.C = W;
             gemm(b, true, st);
         }
