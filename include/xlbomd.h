@@ -230,8 +230,12 @@ int xlbomd_init_system(const xlbomd_desc *desc, xlbomd_system **out);
  * last != NULL the report of the final step is written (its energy fields
  * are valid when has_energy is 1; xlbomd_forces evaluates them on demand).
  * Returns XLBOMD_E_DIVERGED if a non-finite value or a residual above 1e3
- * appears.  The handle then holds the state of the failed step; to go on,
- * restore a checkpoint taken with xlbomd_get_state via xlbomd_set_state. */
+ * appears.  A runaway residual is caught right after the step's solve,
+ * before its forces are computed: positions and velocities are left at the
+ * half step (moved by the previous forces only).  To go on, restore a
+ * checkpoint taken with xlbomd_get_state via xlbomd_set_state, or converge
+ * the electrons at the current positions (xlbomd_scf) and set the charge
+ * history to the result with xlbomd_set_state. */
 int xlbomd_step(xlbomd_system *h, int32_t n_steps, xlbomd_report *last);
 
 /* Advance n_steps steps of `count` independent systems concurrently.  When

@@ -869,6 +869,10 @@ struct SysBase {
         head = dst;
         solve(hist_row(0), predict_mu(), mu_known > 0);
         el_stale = false;
+        // a runaway residual stops the step before its forces move the
+        // nuclei: positions and velocities stay at the half step, where the
+        // previous forces took them
+        if (rms > 1e3) throw Diverged("residual above 1e3");
         push_mu();
         forces_parts(force);
         ++step_no;
@@ -885,7 +889,6 @@ struct SysBase {
         hipLaunchKernelGGL(kick_drift_kernel, dim3(nthr3), dim3(256), 0, st, nat, 0.5 * dt, 0.0,
                            force, mass, vel, (double *)nullptr);
         XL_LAUNCH_CHECK();
-        if (rms > 1e3) throw Diverged("residual above 1e3");
         have_energy = want_energy;
         if (want_energy) energy(&last);
         if (rep) {
@@ -1057,7 +1060,9 @@ struct SysBase {
     // the state it started from and take the step with host decisions
     void planned_complete(bool want_energy, xlbomd_report *rep) {
         sync();
-        if (hpi[PI_FLAGS] != 0) {
+        // a runaway (or non-finite) residual is retaken the same way: the
+        // host-decision step reports it before its forces move the nuclei
+        if (hpi[PI_FLAGS] != 0 || !(hps[PS_RMS] <= 1e3)) {
             if (debug())
                 std::fprintf(stderr, "[xlbomd] planned step %d left its plan (flags %d): "
                              "host decisions\n", step_no + 1, hpi[PI_FLAGS]);

@@ -7,7 +7,8 @@ chemical potential, electron-count error, expansion levels, Newton-Schulz
 iterations, chemical-potential reruns, kernel rank, the library's own time
 for the step and the host wall time per step of the chunk.  Energy fields
 are null for steps on which no energy was evaluated (the handle's
-`energy_every` cadence).
+`energy_every` cadence).  `recover` restarts the electrons after a step
+that reported a divergence.
 
     python -m paper_1705_10845_amd.trajectory --system c2 --steps 100 \\
         --every 10 --energy-every 10 --log c2.jsonl
@@ -16,6 +17,8 @@ import argparse
 import json
 import sys
 import time
+
+import numpy as np
 
 _ENERGY = ("omega", "e_band", "e_coul", "e_rep", "te_s", "e_kin", "e_total")
 _ALWAYS = ("step", "rms_res", "mu", "d_nelec", "foe_levels", "ns_iters", "mu_reruns",
@@ -31,28 +34,64 @@ def record(rep, wall_ms_per_step):
     return out
 
 
-def run(md, steps, every=1, log=None):
+# status codes of the C ABI that a recovery answers
+_DIVERGED, _NOCONV = -4, -3
+
+
+def recover(md, tol=1e-8, max_iter=200, rank=1):
+    """After a step reported a divergence: re-converge the electrons at the
+    current positions by the kernel SCF from n = 0, and refill the charge
+    history with the result (the initial boundary condition of the
+    extended Lagrangian).  Returns the converged n; raises if the SCF does
+    not converge."""
+    n, hist, ok = md.scf(rank=rank, tol=tol, max_iter=max_iter)
+    if not ok:
+        raise RuntimeError(f"recovery SCF did not converge (RMS {hist[-1]:.2e} after "
+                           f"{len(hist)} evaluations)")
+    n = np.asarray(n, dtype=np.float64)
+    md.set_state(n_hist=np.tile(n, (md.kmax + 1, 1)))
+    return n
+
+
+def run(md, steps, every=1, log=None, recover_on_divergence=False):
     """Take `steps` MD steps of the handle `md`, `every` at a time, and
     write each chunk's report as one JSON line to `log` (a path, a
-    writable text file, or None).  Returns the list of records."""
+    writable text file, or None).  With recover_on_divergence, a chunk that
+    reports a divergence (or a failed chemical-potential solve) is followed
+    by `recover` and a line {"event": "recovered", ...}, and the run goes
+    on; the steps of that chunk are not repeated.  Returns the list of
+    records."""
+    from .binding import XlbomdError
     if steps < 0 or every < 1:
         raise ValueError("steps must be >= 0 and every >= 1")
     own = isinstance(log, str)
     fh = open(log, "w") if own else log
     recs = []
+
+    def emit(r):
+        recs.append(r)
+        if fh is not None:
+            fh.write(json.dumps(r) + "\n")
+            fh.flush()
+
     try:
         done = 0
         while done < steps:
             k = min(every, steps - done)
             t0 = time.perf_counter()
-            rep = md.step(k)
+            try:
+                rep = md.step(k)
+            except XlbomdError as e:
+                if not recover_on_divergence or e.code not in (_DIVERGED, _NOCONV):
+                    raise
+                done += k
+                n = recover(md)
+                emit({"event": "recovered", "after_steps": done, "error": str(e),
+                      "n_rms": float(np.sqrt(np.mean(n * n)))})
+                continue
             wall = (time.perf_counter() - t0) * 1e3 / k
             done += k
-            r = record(rep, wall)
-            recs.append(r)
-            if fh is not None:
-                fh.write(json.dumps(r) + "\n")
-                fh.flush()
+            emit(record(rep, wall))
     finally:
         if own:
             fh.close()

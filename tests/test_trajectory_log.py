@@ -44,3 +44,41 @@ def test_rejects_bad_arguments():
         trajectory.run(_FakeHandle(1), steps=5, every=0)
     with pytest.raises(ValueError):
         trajectory.run(_FakeHandle(1), steps=-1)
+
+
+class _FailingHandle(_FakeHandle):
+    """Reports a divergence on the chunk that reaches step `fail_at`; the
+    recovery's SCF and history refill are recorded."""
+
+    kmax = 5
+
+    def __init__(self, fail_at):
+        super().__init__(energy_every=1)
+        self.fail_at = fail_at
+        self.calls = []
+
+    def step(self, k):
+        if self.n < self.fail_at <= self.n + k:
+            from paper_1705_10845_amd.binding import XlbomdError
+            self.n += k
+            self.fail_at = -1
+            raise XlbomdError(-4, "residual above 1e3")
+        return super().step(k)
+
+    def scf(self, rank=1, tol=1e-8, max_iter=200):
+        self.calls.append("scf")
+        return [0.1, -0.1], [1.0, 1e-9], True
+
+    def set_state(self, n_hist=None):
+        self.calls.append(("n_hist", len(n_hist)))
+
+
+def test_recovery_after_a_reported_divergence():
+    h = _FailingHandle(fail_at=5)
+    recs = trajectory.run(h, steps=8, every=2, recover_on_divergence=True)
+    assert [r.get("event") for r in recs] == [None, None, "recovered", None]
+    assert recs[2]["after_steps"] == 6 and "residual" in recs[2]["error"]
+    assert h.calls == ["scf", ("n_hist", 6)]
+    from paper_1705_10845_amd.binding import XlbomdError
+    with pytest.raises(XlbomdError):
+        trajectory.run(_FailingHandle(fail_at=1), steps=2, every=1)
