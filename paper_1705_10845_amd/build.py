@@ -20,7 +20,7 @@ def build() -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
     cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"),
-                                   "-o", tmp, SRC]
+                                   "-o", tmp, SRC, "-lrocprofiler-sdk-roctx"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

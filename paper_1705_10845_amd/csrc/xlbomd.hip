@@ -41,6 +41,8 @@
 #include "overlap.hpp"
 
 #include <algorithm>
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -63,6 +65,17 @@ bool debug() {
     static const bool on = std::getenv("XLBOMD_DEBUG") != nullptr;
     return on;
 }
+
+// A named ROCTX range over a phase of the host orchestration (visible with
+// rocprofv3 --marker-trace; a no-op call when no tool is attached).  The
+// range covers the host's enqueueing and its synchronisations, not device
+// time that runs on after the phase returns.
+struct Phase {
+    explicit Phase(const char *name) { roctxRangePush(name); }
+    ~Phase() { roctxRangePop(); }
+    Phase(const Phase &) = delete;
+    Phase &operator=(const Phase &) = delete;
+};
 
 // Table I: kappa, alpha and c_0..c_K of the dissipative term of Eq. 23.
 struct DampRow {
@@ -584,6 +597,7 @@ struct SysBase {
     // One-shot electronic solve at n (device pointer, nat).  mu0 < -1e300
     // requests a fresh guess.
     void solve(const double *n_dev, double mu_guess, bool have_guess) {
+        Phase ph("xlbomd:solve");
         if (n_dev != ncur)
             XL_HIP(hipMemcpyAsync(ncur, n_dev, nat * sizeof(double), hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(gamma_matvec_kernel, dim3(ceil_div((long)nat * 64, 256)), dim3(256),
@@ -657,6 +671,7 @@ struct SysBase {
     // although m > 0 leaves kernel_pending set: the next step rebuilds.
     int build_kernel(int m, int mode, bool use_prev, bool floor = true,
                      const double *res = nullptr) {
+        Phase ph("xlbomd:kernel");
         if (!res) res = r;
         m = std::min(m, mcap);
         if (d.kernel_rank <= 0) m = 0;
@@ -774,6 +789,7 @@ struct SysBase {
 
     // ---- energy report at the current state ----
     void energy(xlbomd_report *rep) {
+        Phase ph("xlbomd:energy");
         forces_parts(fscr);
         hipLaunchKernelGGL(sum_rows_kernel, dim3(1), dim3(1024), 0, st, nat, 3, epart, scal + 40);
         XL_LAUNCH_CHECK();
@@ -854,6 +870,7 @@ struct SysBase {
     bool full_mode() const { return d.krylov_mode == 2; }
 
     void md_step(bool want_energy, xlbomd_report *rep) {
+        Phase ph("xlbomd:step");
         leave_planned();
         const double dt = d.dt;
         const int nthr3 = ceil_div(3 * nat, 256);
@@ -983,6 +1000,7 @@ struct SysBase {
     }
     // one planned step, enqueued (no host synchronisation)
     void md_step_planned() {
+        Phase ph("xlbomd:planned_step");
         const double dt = d.dt;
         const int nthr3 = ceil_div(3 * nat, 256);
         const int K = d.kmax + 1;
@@ -1157,6 +1175,7 @@ struct SysBase {
 
     // ---- initial state (Eqs. 20, 52) ----
     void init() {
+        Phase ph("xlbomd:init");
         XL_HIP(hipMemsetAsync(ncur, 0, nat * sizeof(double), st));
         if (d.k0_gamma <= 0.0) {
             solve(ncur, 0.0, false);
@@ -1209,6 +1228,7 @@ struct SysBase {
     // MD history and K r are left as they are.  Returns true if RMS(r) <= tol.
     bool scf_run(int rank, double gamma, double tol, int max_iter, double *rms_hist,
                  int *n_eval) {
+        Phase ph("xlbomd:scf");
         const double g_saved = d.k0_gamma;
         if (gamma > 0.0) d.k0_gamma = gamma;
         bool have = false, ok = false;
@@ -1631,6 +1651,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
     // diagonal of dD/dmu to g_out.
     void foe_core(int Lq, double xmax, double mu0, const double *mu_dev, const int *skip,
                   bool sparse, double *st_out, double *g_out) {
+        Phase ph("xlbomd:expansion");
         L = Lq;
         cur_skip = skip;
         seed_sparse = sparse;
@@ -2143,6 +2164,7 @@ template <typename TF, typename TR> struct Sys : SysBase {
     }
 
     void forces_parts(double *F) override {
+        Phase ph("xlbomd:forces");
         hipLaunchKernelGGL((forces_kernel<TF>), dim3(ceil_div((long)nat * 64, 256)), dim3(256), 0,
                            st, md, Dc, q, ncur, vpot, F, epart);
         XL_LAUNCH_CHECK();
